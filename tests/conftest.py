@@ -1,0 +1,20 @@
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: oracle test taking more than ~10 s")
+
+
+@pytest.fixture(scope="session")
+def paper():
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as f:
+        return json.load(f)

@@ -1,0 +1,180 @@
+/*
+ * vh.h -- C ABI of the MI355X (gfx950) Vanka-smoothed shifted-Laplacian Helmholtz solver.
+ *
+ * Method: Yovel, He, Treister, "Vanka-smoothed Shifted Laplacian multigrid
+ * preconditioners for the Helmholtz equations" (2025).  The library solves the
+ * finite-difference acoustic Helmholtz equation of Sec. 1 eq. (acousitcHelm),
+ *     -Lap u - omega^2 kappa^2 (1 - i gamma/omega) u = q,
+ * discretised by the 2nd-order 5-point (2D) / 7-point (3D) stencil of Sec. 2.1 on a
+ * nodal grid, with an absorbing layer and a first-order absorbing closure, by
+ * right-preconditioned flexible GMRES(m) (Sec. 2.3).  The preconditioner is one
+ * V(nu1,nu2) cycle (Sec. 2.2) on the shifted operator H_s = H + i alpha omega^2 M
+ * (eq. (shift)) with Galerkin coarse operators (Sec. 3.1), the additive Vanka
+ * smoother of eq. (smoother) with boundary patches and weights (Sec. 3.2, 3.3), and
+ * a direct solve on the coarsest grid.
+ *
+ * Conventions shared by every call
+ *   - Grid: n[d] nodes per dimension (n[d] - 1 cells), all nodes unknown; spacing h.
+ *     Node (x, y[, z]) has linear index x + n[0]*(y + n[1]*z) (x fastest).
+ *   - Complex numbers are interleaved (re, im) pairs: "c128" = two doubles,
+ *     "c64" = two floats.
+ *   - Every array argument is a DEVICE pointer (memory of the GPU that is current
+ *     when vh_setup runs) unless the argument says "host".  The library never takes
+ *     ownership of caller memory; it copies what it keeps.
+ *   - Work is enqueued on the stream given in vh_options.stream (NULL = the null
+ *     stream).  vh_setup and vh_solve return after their work has completed on that
+ *     stream.
+ *   - Every call returns a vh_status; no C++ exception crosses the ABI.  On error,
+ *     vh_last_error() returns a thread-local message.
+ *   - A handle is used by one host thread at a time; distinct handles may be used
+ *     concurrently from different threads.
+ */
+#ifndef VH_H
+#define VH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int vh_status;
+#define VH_OK 0
+#define VH_EINVAL (-1)      /* invalid argument (dims, levels, kappa <= 0, non-finite input) */
+#define VH_ENOMEM (-2)      /* device allocation failed or footprint above the budget      */
+#define VH_ENOCONV (-3)     /* maxit reached before tol; the last iterate is returned      */
+#define VH_EBREAKDOWN (-4)  /* NaN/Inf in the Krylov recurrences                           */
+#define VH_EDEVICE (-5)     /* a HIP runtime call failed                                    */
+#define VH_EUNSUPPORTED (-6)/* combination of options with no kernel (see vh_setup)         */
+
+/* Precision of the preconditioner (V-cycle).  FGMRES, the unshifted operator,
+ * the true residual and the coarsest factorisation are always FP64. */
+#define VH_PREC_FP64 0      /* whole V-cycle in complex128                               */
+#define VH_PREC_C64 1       /* V-cycle vectors, coefficients, patch inverses in complex64 */
+
+/* Intergrid schemes, Sec. 3.1. */
+#define VH_IG_LEVDEP 0      /* eq. (level1Intergrid)/(levelDepIntergrid): cubic R,P from the finest level, then linear R / cubic P */
+#define VH_IG_MIXED 1       /* linear R / cubic P on every level                      */
+#define VH_IG_LINEAR 2      /* (bi/tri)linear R and P on every level (3D default)      */
+
+/* Vanka patches, Sec. 3.2 list of patches. */
+#define VH_PATCH_FULL 0     /* 3x3 (2D) / 3x3x3 (3D) box around every node, truncated at the boundary */
+#define VH_PATCH_POINT 1    /* 1x1 patch = damped point Jacobi (Sec. 4.1)              */
+
+/* Boundary treatment of the finest operator. */
+#define VH_BC_ABC 0         /* absorbing layer + first-order absorbing closure (default) */
+#define VH_BC_DIRICHLET 1   /* no layer, missing neighbours are zero (test mode)         */
+
+/* Smoother storage. */
+#define VH_SMOOTHER_PATCH 0     /* per-patch inverses, [Np*Np][node]; block multiply + weighted overlap-add */
+#define VH_SMOOTHER_ASSEMBLED 1 /* the same operator summed into a 5^d-point stencil at setup */
+
+typedef struct vh_options {
+    int precision;          /* VH_PREC_*; default VH_PREC_FP64                         */
+    int restart;            /* FGMRES restart length m; default 20                     */
+    int maxit;              /* total preconditioner applications; default 1000         */
+    int nu1, nu2;           /* pre/post smoothing steps; default 1, 1                  */
+    int intergrid;          /* VH_IG_*; default VH_IG_LEVDEP (2D), VH_IG_LINEAR (3D) when -1 */
+    int bc;                 /* VH_BC_*; default VH_BC_ABC                              */
+    int sponge_width;       /* absorbing-layer width in cells; default 20              */
+    double sponge_amp;      /* layer attenuation at the face, in units of omega; default 1 */
+    int smoother;           /* VH_SMOOTHER_*; default VH_SMOOTHER_PATCH                */
+    int ndamping;           /* number of valid entries in damping[]; 0 = defaults      */
+    double damping[16];     /* w_l for level l = 0 (finest) ...; the last one repeats   */
+    void *stream;           /* hipStream_t; NULL = null stream                         */
+} vh_options;
+
+typedef struct vh_solve_stats {
+    int iterations;         /* preconditioner applications (summed over restarts)      */
+    int restarts;
+    int converged;          /* 1 when the true relative residual <= tol                */
+    double relres;          /* true ||q - H u|| / ||q||, FP64                          */
+    double relres_est;      /* Arnoldi estimate at exit                                */
+    double solve_ms;        /* wall time of the solve on the stream (HIP events)       */
+} vh_solve_stats;
+
+typedef struct vh_level_info {
+    int n[3];               /* nodes per dimension (n[2] = 1 in 2D)                    */
+    int stencil_points;     /* K: coefficients per node of the level operator          */
+    int smoother_entries;   /* Np*Np (patch form) or 5^d (assembled) per node          */
+    int offsets[125][3];    /* stencil offsets, K used entries                          */
+    size_t bytes;           /* device bytes owned by this level                        */
+} vh_level_info;
+
+typedef struct vh_handle vh_handle;
+
+/* Fills *opt with the defaults listed above. */
+void vh_options_default(vh_options *opt);
+
+const char *vh_status_string(vh_status s);
+const char *vh_last_error(void);
+
+/* vh_setup -- build the whole preconditioner on the device (Sec. 2.3, 3.1, 3.2, 3.3).
+ *   out     : host pointer receiving the new handle.
+ *   dim     : 2 or 3.
+ *   n       : host array of dim node counts, each >= 3; (n[d]-1) must be divisible by
+ *             2^(levels-1) and every level must keep >= 3 nodes per dimension.
+ *   h       : grid spacing (> 0).   omega : angular frequency (>= 0).
+ *   kappa   : device, float64[N], slowness > 0 (N = prod n).
+ *   gamma   : device, float64[N], physical attenuation >= 0, or NULL for zero.
+ *   shift   : alpha of eq. (shift) (>= 0).
+ *   levels  : number of multigrid levels (>= 1; 1 = direct solve only).
+ *   patch   : VH_PATCH_*.
+ *   opt     : host, or NULL for defaults.
+ * Builds: finest H (FP64) and H_s; Galerkin H_s^l = R H_s^{l-1} P; every patch inverse
+ * of every non-coarsest level (batched FP64 Gauss-Jordan, stored at the preconditioner
+ * precision with the weights w_l / cnt folded in); the FP64 inverse of the coarsest
+ * H_s^L.  Returns VH_EINVAL for bad arguments (checked before any allocation),
+ * VH_EUNSUPPORTED for an intergrid/dimension pair without kernels, VH_ENOMEM if an
+ * allocation fails (nothing is leaked). */
+vh_status vh_setup(vh_handle **out, int dim, const int *n, double h, double omega,
+                   const double *kappa, const double *gamma, double shift, int levels,
+                   int patch, const vh_options *opt);
+
+/* vh_solve -- FGMRES(m) (Sec. 2.3) preconditioned by one V-cycle, from u = 0.
+ *   q     : device, c128[nsrc][N], right-hand sides (source-major).
+ *   nsrc  : number of right-hand sides (>= 1), solved one after another.
+ *   tol   : relative residual target (> 0), checked on the true FP64 residual.
+ *   u     : device, c128[nsrc][N], output (may not alias q).
+ *   stats : host array of nsrc entries, or NULL.
+ * Returns VH_ENOCONV if some source did not reach tol within maxit (u holds the last
+ * iterate), VH_EBREAKDOWN on NaN/Inf. */
+vh_status vh_solve(vh_handle *hd, const void *q, int nsrc, double tol, void *u,
+                   vh_solve_stats *stats);
+
+/* vh_destroy -- frees every device allocation of the handle.  NULL is allowed. */
+vh_status vh_destroy(vh_handle *hd);
+
+/* ---- inspection hooks (used by the parity tests) ----------------------------- */
+
+int vh_num_levels(const vh_handle *hd);
+vh_status vh_get_level_info(const vh_handle *hd, int level, vh_level_info *info);
+
+/* y = A x on level `level` (0 = finest): which = 0 -> unshifted H (finest only, FP64),
+ * which = 1 -> H_s^level at the preconditioner precision.  x, y: device c128[N_level]. */
+vh_status vh_apply_operator(vh_handle *hd, int level, int which, const void *x, void *y);
+
+/* z = M^{-1} v: one V-cycle from zero, v and z device c128[N]. */
+vh_status vh_apply_vcycle(vh_handle *hd, const void *v, void *z);
+
+/* u <- u + B_l (q - A_l u) on level l (one damped smoothing step, eq. (smoother));
+ * q, u device c128[N_l]. */
+vh_status vh_apply_smoother(vh_handle *hd, int level, const void *q, void *u);
+
+/* Copies level data to HOST buffers (each may be NULL):
+ *   coef : c128[K][N]  operator coefficients (H_s^level)
+ *   smoother : c128[E][N] smoother entries (E = smoother_entries), weights folded in
+ *   coarse_inv : c128[N][N] inverse of the coarsest operator (coarsest level only). */
+vh_status vh_export_level(const vh_handle *hd, int level, void *coef, void *smoother,
+                          void *coarse_inv);
+
+/* Device bytes vh_setup would allocate (excluding the caller's arrays), plus the
+ * per-source FGMRES workspace of vh_solve.  Pure function of its arguments. */
+size_t vh_footprint_bytes(int dim, const int *n, int levels, int patch,
+                          const vh_options *opt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VH_H */

@@ -1,0 +1,227 @@
+"""ctypes binding of libvh.so (include/vh.h).  Argument marshalling only.
+
+Function names mirror the C ABI.  Device arrays are passed as torch tensors on the
+GPU (complex128 / float64, contiguous); the binding checks dtype, device and size
+and hands the raw pointers to the library.  There is no fallback: if the library
+is missing or the GPU is absent the calls raise.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvh.so")
+
+VH_OK = 0
+VH_EINVAL = -1
+VH_ENOMEM = -2
+VH_ENOCONV = -3
+VH_EBREAKDOWN = -4
+VH_EDEVICE = -5
+VH_EUNSUPPORTED = -6
+
+VH_PREC_FP64 = 0
+VH_PREC_C64 = 1
+VH_IG_LEVDEP = 0
+VH_IG_MIXED = 1
+VH_IG_LINEAR = 2
+VH_PATCH_FULL = 0
+VH_PATCH_POINT = 1
+VH_BC_ABC = 0
+VH_BC_DIRICHLET = 1
+VH_SMOOTHER_PATCH = 0
+VH_SMOOTHER_ASSEMBLED = 1
+
+
+class vh_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+        ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("intergrid", ctypes.c_int),
+        ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
+        ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
+        ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p),
+    ]
+
+
+class vh_solve_stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+        ("relres", ctypes.c_double), ("relres_est", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vh_level_info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3), ("stencil_points", ctypes.c_int),
+        ("smoother_entries", ctypes.c_int), ("offsets", (ctypes.c_int * 3) * 125),
+        ("bytes", ctypes.c_size_t),
+    ]
+
+
+class VhError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"vh status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_SIGNATURES = {
+    "vh_options_default": (None, [ctypes.POINTER(vh_options)]),
+    "vh_status_string": (ctypes.c_char_p, [_I]),
+    "vh_last_error": (ctypes.c_char_p, []),
+    "vh_setup": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_I), _D, _D, _P, _P, _D, _I, _I,
+                      ctypes.POINTER(vh_options)]),
+    "vh_solve": (_I, [_P, _P, _I, _D, _P, ctypes.POINTER(vh_solve_stats)]),
+    "vh_destroy": (_I, [_P]),
+    "vh_num_levels": (_I, [_P]),
+    "vh_get_level_info": (_I, [_P, _I, ctypes.POINTER(vh_level_info)]),
+    "vh_apply_operator": (_I, [_P, _I, _I, _P, _P]),
+    "vh_apply_vcycle": (_I, [_P, _P, _P]),
+    "vh_apply_smoother": (_I, [_P, _I, _P, _P]),
+    "vh_export_level": (_I, [_P, _I, _P, _P, _P]),
+    "vh_footprint_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _I,
+                                             ctypes.POINTER(vh_options)]),
+}
+
+
+def lib():
+    """Loads libvh.so (built in-tree by paper_2511_16808_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2511_16808_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != VH_OK:
+        raise VhError(status, lib().vh_last_error().decode())
+    return status
+
+
+def _ptr(t, dtype_name, numel=None):
+    """Raw device pointer of a contiguous GPU tensor of the given dtype (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    want = {"complex128": torch.complex128, "float64": torch.float64}[dtype_name]
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if t.dtype != want:
+        raise ValueError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def vh_options_default():
+    o = vh_options()
+    lib().vh_options_default(ctypes.byref(o))
+    return o
+
+
+def vh_status_string(s):
+    return lib().vh_status_string(s).decode()
+
+
+def vh_last_error():
+    return lib().vh_last_error().decode()
+
+
+def vh_setup(dim, n, h, omega, kappa, gamma, shift, levels, patch, opt=None):
+    """kappa, gamma: float64 GPU tensors of prod(n) nodes (gamma may be None)."""
+    N = 1
+    for k in n[:dim]:
+        N *= int(k)
+    arr = (_I * 3)(*(list(n) + [1] * (3 - len(n))))
+    hd = _P()
+    st = lib().vh_setup(ctypes.byref(hd), dim, arr, float(h), float(omega),
+                        _ptr(kappa, "float64", N), _ptr(gamma, "float64", N), float(shift),
+                        levels, patch, ctypes.byref(opt) if opt is not None else None)
+    check(st)
+    return hd
+
+
+def vh_solve(hd, q, nsrc, tol, u, raise_on_noconv=False):
+    """q, u: complex128 GPU tensors of nsrc*N.  Returns (status, [stats dicts])."""
+    stats = (vh_solve_stats * nsrc)()
+    st = lib().vh_solve(hd, _ptr(q, "complex128"), nsrc, float(tol), _ptr(u, "complex128"), stats)
+    if st != VH_OK and (st != VH_ENOCONV or raise_on_noconv):
+        check(st)
+    return st, [s.as_dict() for s in stats]
+
+
+def vh_destroy(hd):
+    check(lib().vh_destroy(hd))
+
+
+def vh_num_levels(hd):
+    return lib().vh_num_levels(hd)
+
+
+def vh_get_level_info(hd, level):
+    info = vh_level_info()
+    check(lib().vh_get_level_info(hd, level, ctypes.byref(info)))
+    K = info.stencil_points
+    return {
+        "n": tuple(info.n), "stencil_points": K, "smoother_entries": info.smoother_entries,
+        "offsets": [tuple(info.offsets[k]) for k in range(K)], "bytes": info.bytes,
+    }
+
+
+def vh_apply_operator(hd, level, which, x, y):
+    check(lib().vh_apply_operator(hd, level, which, _ptr(x, "complex128"), _ptr(y, "complex128")))
+
+
+def vh_apply_vcycle(hd, v, z):
+    check(lib().vh_apply_vcycle(hd, _ptr(v, "complex128"), _ptr(z, "complex128")))
+
+
+def vh_apply_smoother(hd, level, q, u):
+    check(lib().vh_apply_smoother(hd, level, _ptr(q, "complex128"), _ptr(u, "complex128")))
+
+
+def vh_export_level(hd, level, coef=None, smoother=None, coarse_inv=None):
+    """Host numpy complex128 output arrays (C-contiguous) or None."""
+    def hp(a):
+        if a is None:
+            return None
+        assert a.dtype.name == "complex128" and a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    check(lib().vh_export_level(hd, level, hp(coef), hp(smoother), hp(coarse_inv)))
+
+
+def vh_footprint_bytes(dim, n, levels, patch, opt=None):
+    arr = (_I * 3)(*(list(n) + [1] * (3 - len(n))))
+    return lib().vh_footprint_bytes(dim, arr, levels, patch,
+                                    ctypes.byref(opt) if opt is not None else None)
+
+
+def make_options(**kw):
+    """vh_options with defaults, overridden by keyword arguments; `damping` may be a list,
+    `stream` a torch.cuda.Stream or raw handle."""
+    o = vh_options_default()
+    for k, v in kw.items():
+        if k == "damping":
+            o.ndamping = len(v)
+            for i, w in enumerate(v):
+                o.damping[i] = float(w)
+        elif k == "stream":
+            o.stream = v if isinstance(v, int) or v is None else v.cuda_stream
+        else:
+            setattr(o, k, v)
+    return o

@@ -1,0 +1,172 @@
+// vh_common.h -- device types, compile-time stencil shapes and kernel launchers.
+//
+// Internal header of the gfx950 library; the public ABI is include/vh.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace vh {
+
+// ---------------------------------------------------------------- complex scalars
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> cmk(T r, T i) {
+  cpx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
+  return cmk(a.re + b.re, a.im + b.im);
+}
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) {
+  return cmk(a.re - b.re, a.im - b.im);
+}
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) {
+  return cmk(s * a.re, s * a.im);
+}
+// acc + a*b with fused multiply-adds
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a)*b
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> cfma_conj(cpx<T> a, cpx<T> b, cpx<T> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+template <class TO, class TI>
+__host__ __device__ __forceinline__ cpx<TO> ccast(cpx<TI> a) {
+  return cmk<TO>(static_cast<TO>(a.re), static_cast<TO>(a.im));
+}
+template <class T>
+__host__ __device__ __forceinline__ cpx<T> cinv(cpx<T> a) {
+  // 1/a with a scaling step so that |a|^2 does not overflow or underflow
+  T s = fmax(fabs(a.re), fabs(a.im));
+  T ar = a.re / s, ai = a.im / s;
+  T d = ar * ar + ai * ai;
+  return cmk<T>(ar / (d * s), -ai / (d * s));
+}
+
+// ---------------------------------------------------------------- grids
+struct Grid {
+  int nx, ny, nz;  // nodes per dimension (nz = 1 in 2D)
+  int dim;
+  long long N;  // nx*ny*nz
+};
+
+__host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int nz) {
+  Grid g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = (dim == 3) ? nz : 1;
+  g.dim = dim;
+  g.N = (long long)g.nx * g.ny * g.nz;
+  return g;
+}
+
+// ---------------------------------------------------------------- stencil shapes
+// CROSS: centre + the 2*DIM axis neighbours, ordered centre, -x, +x, -y, +y, -z, +z.
+// BOX<r>: the (2r+1)^DIM box, x fastest.
+enum Shape : int { CROSS = 0, BOX1 = 1, BOX2 = 2 };
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <int DIM, int SHAPE>
+__host__ __device__ constexpr int shape_K() {
+  return SHAPE == CROSS ? 2 * DIM + 1 : ipow(2 * SHAPE + 1, DIM);
+}
+
+template <int DIM, int SHAPE>
+__host__ __device__ constexpr int shape_radius() {
+  return SHAPE == CROSS ? 1 : SHAPE;
+}
+
+// component c (0 = x, 1 = y, 2 = z) of the offset of entry k
+template <int DIM, int SHAPE>
+__host__ __device__ constexpr int shape_off(int k, int c) {
+  if (SHAPE == CROSS) {
+    if (k == 0) return 0;
+    return ((k - 1) / 2 == c) ? (((k - 1) % 2 == 0) ? -1 : 1) : 0;
+  }
+  if (c >= DIM) return 0;
+  return (k / ipow(2 * SHAPE + 1, c)) % (2 * SHAPE + 1) - SHAPE;
+}
+
+// entry index of offset (dx, dy, dz), or -1 if the shape does not contain it
+template <int DIM, int SHAPE>
+__host__ __device__ constexpr int shape_index(int dx, int dy, int dz) {
+  if (DIM == 2 && dz != 0) return -1;
+  if (SHAPE == CROSS) {
+    int nz = (dx != 0) + (dy != 0) + (dz != 0);
+    if (nz == 0) return 0;
+    if (nz > 1) return -1;
+    if (dx == -1) return 1;
+    if (dx == 1) return 2;
+    if (dy == -1) return 3;
+    if (dy == 1) return 4;
+    if (dz == -1) return 5;
+    if (dz == 1) return 6;
+    return -1;
+  }
+  const int r = SHAPE, W = 2 * SHAPE + 1;
+  if (dx < -r || dx > r || dy < -r || dy > r || dz < -r || dz > r) return -1;
+  return (dx + r) + W * (dy + r) + (DIM == 3 ? W * W * (dz + r) : 0);
+}
+
+// Vanka patches: FULL = the 3^DIM box (BOX1 ordering), POINT = the node itself.
+enum Patch : int { PATCH_FULL = 0, PATCH_POINT = 1 };
+
+template <int DIM, int PATCH>
+__host__ __device__ constexpr int patch_Np() {
+  return PATCH == PATCH_FULL ? ipow(3, DIM) : 1;
+}
+template <int DIM, int PATCH>
+__host__ __device__ constexpr int patch_off(int k, int c) {
+  return PATCH == PATCH_FULL ? shape_off<DIM, BOX1>(k, c) : 0;
+}
+
+// Intergrid families (1D weights, Sec. 3.1): restriction r(t), prolongation p(t) = 2 r(t).
+enum Family : int { FAM_LINEAR = 0, FAM_CUBIC = 1 };
+
+__host__ __device__ constexpr int fam_radius(int fam) { return fam == FAM_LINEAR ? 1 : 2; }
+// restriction weight at fine offset t from 2I (|t| <= radius)
+__host__ __device__ constexpr double fam_r(int fam, int t) {
+  return fam == FAM_LINEAR
+             ? ((t == 0) ? 0.5 : ((t == 1 || t == -1) ? 0.25 : 0.0))
+             : ((t == 0) ? 6.0 / 16 : ((t == 1 || t == -1) ? 4.0 / 16 : ((t == 2 || t == -2) ? 1.0 / 16 : 0.0)));
+}
+// 1D prolongation weight of coarse node J at fine node 2J + t
+__host__ __device__ constexpr double fam_p(int fam, int t) { return 2.0 * fam_r(fam, t); }
+
+// ---------------------------------------------------------------- launch helpers
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD owns one
+// contiguous range of the domain (its L2 then sees neighbouring rows).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b & 7u, j = b >> 3, q = nb >> 3, r = nb & 7u;
+  return x * q + (x < r ? x : r) + j;
+}
+
+}  // namespace vh

@@ -1,0 +1,1082 @@
+// vh_kernels.hip -- gfx950 kernels of the Vanka-smoothed shifted-Laplacian solver.
+//
+// Every kernel is one sweep over a structured nodal grid, one thread per node
+// (or per coarse node / per patch row), linear node index x + nx*(y + ny*z).
+// Blocks are remapped so that each XCD owns a contiguous slab of the domain.
+// No atomics anywhere: overlap-adds are gathers, reductions run in a fixed order,
+// so every result is bitwise reproducible.
+#include "vh_launch.h"
+
+namespace vh {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void decode(unsigned i, const Grid& g, int& x, int& y, int& z) {
+  x = (int)(i % (unsigned)g.nx);
+  const unsigned t = i / (unsigned)g.nx;
+  y = (int)(t % (unsigned)g.ny);
+  z = (int)(t / (unsigned)g.ny);
+}
+__device__ __forceinline__ bool inside(const Grid& g, int x, int y, int z) {
+  return (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
+}
+__device__ __forceinline__ long long lin(const Grid& g, int x, int y, int z) {
+  return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+__device__ __forceinline__ unsigned node_id() {
+  return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+static inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define VH_LAUNCH_CHECK()                                 \
+  do {                                                    \
+    hipError_t e__ = hipGetLastError();                   \
+    if (e__ != hipSuccess) return e__;                    \
+  } while (0)
+
+// ------------------------------------------------------------------ fill / convert
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(cpx<T>* __restrict__ p, size_t n, T re, T im) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = i; k < n; k += stride) p[k] = cmk<T>(re, im);
+}
+
+template <class TO, class TI>
+__global__ __launch_bounds__(256) void k_convert(const cpx<TI>* __restrict__ a, cpx<TO>* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = i; k < n; k += stride) b[k] = ccast<TO>(a[k]);
+}
+
+hipError_t fill(void* p, size_t n, int prec, double re, double im, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  if (prec == PREC_F64)
+    k_fill<double><<<nb, 256, 0, s>>>((cpx<double>*)p, n, re, im);
+  else
+    k_fill<float><<<nb, 256, 0, s>>>((cpx<float>*)p, n, (float)re, (float)im);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t convert(const void* a, int pa, void* b, int pb, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  if (pa == PREC_F64 && pb == PREC_F32)
+    k_convert<float, double><<<nb, 256, 0, s>>>((const cpx<double>*)a, (cpx<float>*)b, n);
+  else if (pa == PREC_F32 && pb == PREC_F64)
+    k_convert<double, float><<<nb, 256, 0, s>>>((const cpx<float>*)a, (cpx<double>*)b, n);
+  else if (pa == PREC_F64)
+    k_convert<double, double><<<nb, 256, 0, s>>>((const cpx<double>*)a, (cpx<double>*)b, n);
+  else
+    k_convert<float, float><<<nb, 256, 0, s>>>((const cpx<float>*)a, (cpx<float>*)b, n);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ finest operator
+// 2nd-order stencil (Sec. 2.1) of eq. (acousitcHelm) with
+//   beta = omega^2 kappa^2 - i omega kappa^2 gamma,  gamma = gamma0 + absorbing layer,
+//   layer: amp*omega*sum_d ((W - s_d)/W)^2 for s_d < W (s_d = cells to the nearer face),
+//   boundary (ABC): ghost node eliminated with du/dn = -i omega kappa u, i.e. the
+//   inward neighbour weight doubles and the diagonal gains 2 i omega kappa / h per
+//   boundary direction; the row is then scaled by 1/2 per boundary direction
+//   (complex-symmetric H).  H_s = H + i alpha omega^2 * scale (eq. (shift), same sign
+//   as the attenuation; M = identity of the unscaled rows).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fine_operator(Grid g, const double* __restrict__ kappa,
+                                                       const double* __restrict__ gamma0, double h,
+                                                       double omega, double alpha, int bc, int sw,
+                                                       double samp, cpx<double>* __restrict__ H,
+                                                       cpx<double>* __restrict__ Hs) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int c[3];
+  decode(i, g, c[0], c[1], c[2]);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const double k = kappa[i];
+  double gam = gamma0 ? gamma0[i] : 0.0;
+  const bool abc = (bc == BC_ABC);
+  if (abc && sw > 0) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int s = min(c[d], n[d] - 1 - c[d]);
+      if (s < sw) {
+        const double f = (double)(sw - s) / (double)sw;
+        gam += samp * omega * f * f;
+      }
+    }
+  }
+  const double ih2 = 1.0 / (h * h);
+  double scale = 1.0;
+  double dre = 2.0 * DIM * ih2 - omega * omega * k * k;
+  double dim_ = omega * k * k * gam;  // -beta adds +i omega kappa^2 gamma
+  cpx<double> off[2 * DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
+    double wm = (lo ? 0.0 : -ih2), wp = (hi ? 0.0 : -ih2);
+    if (abc && (lo || hi)) {
+      if (lo) wp = -2.0 * ih2;
+      if (hi) wm = -2.0 * ih2;
+      dim_ += 2.0 * omega * k / h;
+      scale *= 0.5;
+    }
+    off[2 * d] = cmk(wm, 0.0);
+    off[2 * d + 1] = cmk(wp, 0.0);
+  }
+  const size_t N = (size_t)g.N;
+  H[i] = cmk(scale * dre, scale * dim_);
+  Hs[i] = cmk(scale * dre, scale * (dim_ + alpha * omega * omega));
+#pragma unroll
+  for (int e = 0; e < 2 * DIM; ++e) {
+    H[(size_t)(e + 1) * N + i] = scale * off[e];
+    Hs[(size_t)(e + 1) * N + i] = scale * off[e];
+  }
+}
+
+hipError_t fine_operator(int dim, Grid g, const double* kappa, const double* gamma, double h,
+                         double omega, double alpha, int bc, int sw, double samp, cpx<double>* H,
+                         cpx<double>* Hs, hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+  if (dim == 2)
+    k_fine_operator<2><<<nb, 256, 0, s>>>(g, kappa, gamma, h, omega, alpha, bc, sw, samp, H, Hs);
+  else
+    k_fine_operator<3><<<nb, 256, 0, s>>>(g, kappa, gamma, h, omega, alpha, bc, sw, samp, H, Hs);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// kappa must be finite and > 0, gamma finite and >= 0; flag[0] = 1 otherwise
+__global__ __launch_bounds__(256) void k_check_media(long long N, const double* __restrict__ kappa,
+                                                     const double* __restrict__ gamma,
+                                                     int* __restrict__ flag) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double k = kappa[i];
+  const double g = gamma ? gamma[i] : 0.0;
+  const bool ok = (k > 0.0) && (k < 1e300) && (g >= 0.0) && (g < 1e300);
+  if (!ok) flag[0] = 1;
+}
+
+hipError_t check_media(long long N, const double* kappa, const double* gamma, int* flag,
+                       hipStream_t s) {
+  k_check_media<<<nblocks(N, 256), 256, 0, s>>>(N, kappa, gamma, flag);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ stencil sweep
+// y = A x (APPLY), y = b - A x (RESID), y += A x (ADD); A stored [K][N] in TC,
+// accumulation in TC.  Coefficients that point outside the grid are zero by
+// construction, so those neighbours are skipped.
+template <int DIM, int SHAPE, int MODE, class TC, class TX, class TY>
+__global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restrict__ A,
+                                                 const cpx<TX>* __restrict__ x,
+                                                 const cpx<TY>* __restrict__ b,
+                                                 cpx<TY>* __restrict__ y) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int cx, cy, cz;
+  decode(i, g, cx, cy, cz);
+  constexpr int K = shape_K<DIM, SHAPE>();
+  const size_t N = (size_t)g.N;
+  cpx<TC> acc = cmk<TC>(0, 0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+              dz = shape_off<DIM, SHAPE>(k, 2);
+    if (inside(g, cx + dx, cy + dy, cz + dz)) {
+      const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+      acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[j]), acc);
+    }
+  }
+  if (MODE == OP_APPLY) {
+    y[i] = ccast<TY>(acc);
+  } else if (MODE == OP_RESID) {
+    y[i] = ccast<TY>(ccast<TC>(b[i]) - acc);
+  } else {
+    y[i] = ccast<TY>(ccast<TC>(y[i]) + acc);
+  }
+}
+
+template <int DIM, int SHAPE, class TC, class TX, class TY>
+static hipError_t stencil_t(Grid g, int mode, const void* A, const void* x, const void* b, void* y,
+                            hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+  auto Ap = (const cpx<TC>*)A;
+  auto xp = (const cpx<TX>*)x;
+  auto bp = (const cpx<TY>*)b;
+  auto yp = (cpx<TY>*)y;
+  if (mode == OP_APPLY)
+    k_stencil<DIM, SHAPE, OP_APPLY, TC, TX, TY><<<nb, 256, 0, s>>>(g, Ap, xp, bp, yp);
+  else if (mode == OP_RESID)
+    k_stencil<DIM, SHAPE, OP_RESID, TC, TX, TY><<<nb, 256, 0, s>>>(g, Ap, xp, bp, yp);
+  else
+    k_stencil<DIM, SHAPE, OP_ADD, TC, TX, TY><<<nb, 256, 0, s>>>(g, Ap, xp, bp, yp);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <int DIM, int SHAPE>
+static hipError_t stencil_p(Grid g, int mode, int pc, const void* A, int px, const void* x, int py,
+                            const void* b, void* y, hipStream_t s) {
+  if (pc == PREC_F64 && px == PREC_F64 && py == PREC_F64)
+    return stencil_t<DIM, SHAPE, double, double, double>(g, mode, A, x, b, y, s);
+  if (pc == PREC_F32 && px == PREC_F32 && py == PREC_F32)
+    return stencil_t<DIM, SHAPE, float, float, float>(g, mode, A, x, b, y, s);
+  if (pc == PREC_F64 && px == PREC_F32 && py == PREC_F64)
+    return stencil_t<DIM, SHAPE, double, float, double>(g, mode, A, x, b, y, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, int px,
+                   const void* x, int py, const void* b, void* y, hipStream_t s) {
+  if (dim == 2) {
+    if (shape == CROSS) return stencil_p<2, CROSS>(g, mode, pc, A, px, x, py, b, y, s);
+    if (shape == BOX1) return stencil_p<2, BOX1>(g, mode, pc, A, px, x, py, b, y, s);
+    if (shape == BOX2) return stencil_p<2, BOX2>(g, mode, pc, A, px, x, py, b, y, s);
+  } else {
+    if (shape == CROSS) return stencil_p<3, CROSS>(g, mode, pc, A, px, x, py, b, y, s);
+    if (shape == BOX1) return stencil_p<3, BOX1>(g, mode, pc, A, px, x, py, b, y, s);
+    if (shape == BOX2) return stencil_p<3, BOX2>(g, mode, pc, A, px, x, py, b, y, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ additive Vanka apply
+// Sec. 3.2, eq. (smoother): u <- u + w sum_c V_c^T W_c A_c^{-1} V_c r.  Written as a
+// gather at the destination node i: node i is member a of the patch anchored at
+// c = i - off_a, whose local solve contributes row a of A_c^{-1} times r on the
+// members c + off_m.  G[(a*Np + m)][i] = (w / cnt_i) (A_{i-off_a}^{-1})[a][m]
+// (zero where the patch or the member does not exist), so
+//     u_i += sum_{a,m} G[(a*Np+m)][i] * r[i - off_a + off_m].
+// Every patch inverse entry is read exactly once per sweep; no atomics.
+// 2D: the 5x5 neighbourhood of r is loaded once into registers.
+template <int DIM, int PATCH, bool ZERO, class T>
+__global__ __launch_bounds__(256) void k_vanka_patch(Grid g, const cpx<T>* __restrict__ G,
+                                                     const cpx<T>* __restrict__ r,
+                                                     cpx<T>* __restrict__ u) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int cx, cy, cz;
+  decode(i, g, cx, cy, cz);
+  constexpr int Np = patch_Np<DIM, PATCH>();
+  const size_t N = (size_t)g.N;
+  cpx<T> acc = cmk<T>(0, 0);
+  if (DIM == 2) {
+    cpx<T> rn[25];
+#pragma unroll
+    for (int e = 0; e < 25; ++e) {
+      const int dx = e % 5 - 2, dy = e / 5 - 2;
+      rn[e] = inside(g, cx + dx, cy + dy, cz) ? r[(long long)i + dx + (long long)g.nx * dy]
+                                              : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < Np; ++a) {
+#pragma unroll
+      for (int m = 0; m < Np; ++m) {
+        const int dx = patch_off<DIM, PATCH>(m, 0) - patch_off<DIM, PATCH>(a, 0);
+        const int dy = patch_off<DIM, PATCH>(m, 1) - patch_off<DIM, PATCH>(a, 1);
+        acc = cfma(G[(size_t)(a * Np + m) * N + i], rn[(dx + 2) + 5 * (dy + 2)], acc);
+      }
+    }
+  } else {
+#pragma unroll 3
+    for (int a = 0; a < Np; ++a) {
+      const int ax = patch_off<DIM, PATCH>(a, 0), ay = patch_off<DIM, PATCH>(a, 1),
+                az = patch_off<DIM, PATCH>(a, 2);
+#pragma unroll
+      for (int m = 0; m < Np; ++m) {
+        const int dx = patch_off<DIM, PATCH>(m, 0) - ax, dy = patch_off<DIM, PATCH>(m, 1) - ay,
+                  dz = patch_off<DIM, PATCH>(m, 2) - az;
+        if (inside(g, cx + dx, cy + dy, cz + dz)) {
+          const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+          acc = cfma(G[(size_t)(a * Np + m) * N + i], r[j], acc);
+        }
+      }
+    }
+  }
+  u[i] = ZERO ? acc : (u[i] + acc);
+}
+
+template <int DIM, int PATCH, class T>
+static hipError_t vanka_patch_t(Grid g, const void* G, const void* r, void* u, bool zero,
+                                hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+  if (zero)
+    k_vanka_patch<DIM, PATCH, true, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                          (cpx<T>*)u);
+  else
+    k_vanka_patch<DIM, PATCH, false, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                           (cpx<T>*)u);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t vanka_patch(int dim, int patch, Grid g, int prec, const void* G, const void* r, void* u,
+                       bool zero, hipStream_t s) {
+#define VH_VP(D, P)                                                              \
+  if (dim == D && patch == P)                                                    \
+    return prec == PREC_F64 ? vanka_patch_t<D, P, double>(g, G, r, u, zero, s) \
+                            : vanka_patch_t<D, P, float>(g, G, r, u, zero, s);
+  VH_VP(2, PATCH_FULL)
+  VH_VP(3, PATCH_FULL)
+  VH_VP(2, PATCH_POINT)
+  VH_VP(3, PATCH_POINT)
+#undef VH_VP
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ Vanka setup
+// Sec. 3.2/3.3: for every patch c (anchored at every node, truncated at the
+// boundary), A_c = V_c H_s V_c^T is inverted in FP64 by Gauss-Jordan elimination
+// with partial pivoting.  One lane per patch row (Np lanes per patch, 64/Np patches
+// per wave); out-of-domain members are identity rows (padding).  Pivoting is
+// implicit: rows stay in their lanes, the pivot row of each step is broadcast with
+// lane shuffles.  After step s, A^{-1}[step(L)][piv[s]] = a_L[s] for lane L.
+// Row i of A_c^{-1} is written, scaled by w / cnt(c + off_i), to
+// G[(i*Np + m)][c + off_i].
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
+
+template <int DIM, int PATCH>
+__device__ __forceinline__ int patch_count(const Grid& g, int x, int y, int z) {
+  if (PATCH == PATCH_POINT) return 1;
+  int c = (3 - (x == 0) - (x == g.nx - 1)) * (3 - (y == 0) - (y == g.ny - 1));
+  if (DIM == 3) c *= (3 - (z == 0) - (z == g.nz - 1));
+  return c;
+}
+
+template <int DIM, int SHAPE, int PATCH, class T>
+__global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
+                                                     double w, cpx<T>* __restrict__ G) {
+  constexpr int Np = patch_Np<DIM, PATCH>();
+  constexpr int PPW = 64 / Np;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const unsigned slot = lane / Np;
+  const int k = (int)(lane % Np);
+  const long long c = (long long)wave * PPW + slot;
+  const bool active = slot < (unsigned)PPW && c < g.N;
+  const int base = (int)(slot < (unsigned)PPW ? slot : 0) * Np;
+  const size_t N = (size_t)g.N;
+  int cx = 0, cy = 0, cz = 0;
+  if (active) decode((unsigned)c, g, cx, cy, cz);
+  const int kx = cx + patch_off<DIM, PATCH>(k, 0), ky = cy + patch_off<DIM, PATCH>(k, 1),
+            kz = cz + patch_off<DIM, PATCH>(k, 2);
+  const bool mem_in = active && inside(g, kx, ky, kz);
+  const long long ik = mem_in ? lin(g, kx, ky, kz) : 0;
+
+  cpx<double> a[Np];
+#pragma unroll
+  for (int m = 0; m < Np; ++m) {
+    a[m] = cmk(0.0, 0.0);
+    if (mem_in) {
+      const int dx = patch_off<DIM, PATCH>(m, 0) - patch_off<DIM, PATCH>(k, 0);
+      const int dy = patch_off<DIM, PATCH>(m, 1) - patch_off<DIM, PATCH>(k, 1);
+      const int dz = patch_off<DIM, PATCH>(m, 2) - patch_off<DIM, PATCH>(k, 2);
+      const int s = shape_index<DIM, SHAPE>(dx, dy, dz);
+      if (s >= 0 && inside(g, kx + dx, ky + dy, kz + dz)) a[m] = A[(size_t)s * N + ik];
+    } else if (m == k) {
+      a[m] = cmk(1.0, 0.0);
+    }
+  }
+
+  bool used = false;
+  int mystep = k;
+  int piv[Np];
+#pragma unroll
+  for (int s = 0; s < Np; ++s) {
+    const double v = used ? -1.0 : (fabs(a[s].re) + fabs(a[s].im));
+    int best = 0;
+    double bv = -2.0;
+#pragma unroll
+    for (int r = 0; r < Np; ++r) {
+      const double vr = shfl_d(v, base + r);
+      if (vr > bv) {
+        bv = vr;
+        best = r;
+      }
+    }
+    piv[s] = best;
+    const bool am = (k == best);
+    if (am) {
+      const cpx<double> inv = cinv(a[s]);
+      a[s] = cmk(1.0, 0.0);
+#pragma unroll
+      for (int m = 0; m < Np; ++m) a[m] = a[m] * inv;
+      used = true;
+      mystep = s;
+    }
+    const cpx<double> f = a[s];
+    const int src = base + best;
+#pragma unroll
+    for (int m = 0; m < Np; ++m) {
+      cpx<double> p;
+      p.re = shfl_d(a[m].re, src);
+      p.im = shfl_d(a[m].im, src);
+      if (!am) {
+        const cpx<double> cur = (m == s) ? cmk(0.0, 0.0) : a[m];
+        a[m] = cur - f * p;
+      }
+    }
+  }
+
+  if (!mem_in) return;
+  // this lane holds row `mystep` of the inverse; destination = member mystep of c
+  const int i = mystep;
+  int ox = 0, oy = 0, oz = 0;
+#pragma unroll
+  for (int q = 0; q < Np; ++q)
+    if (q == i) {
+      ox = patch_off<DIM, PATCH>(q, 0);
+      oy = patch_off<DIM, PATCH>(q, 1);
+      oz = patch_off<DIM, PATCH>(q, 2);
+    }
+  const int jx = cx + ox, jy = cy + oy, jz = cz + oz;
+  if (!inside(g, jx, jy, jz)) return;  // only reachable with non-finite patch entries
+  const long long j = lin(g, jx, jy, jz);
+  const double wt = w / (double)patch_count<DIM, PATCH>(g, jx, jy, jz);
+#pragma unroll
+  for (int s = 0; s < Np; ++s) {
+    const int m = piv[s];
+    G[(size_t)(i * Np + m) * N + j] = ccast<T>(wt * a[s]);
+  }
+}
+
+template <int DIM, int SHAPE, int PATCH>
+static hipError_t vanka_setup_s(Grid g, const cpx<double>* A, double w, int prec, void* G,
+                                hipStream_t s) {
+  constexpr int Np = patch_Np<DIM, PATCH>();
+  constexpr int PPW = 64 / Np;
+  const long long waves = (g.N + PPW - 1) / PPW;
+  const unsigned nb = (unsigned)((waves + 3) / 4);
+  if (prec == PREC_F64)
+    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 256, 0, s>>>(g, A, w, (cpx<double>*)G);
+  else
+    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 256, 0, s>>>(g, A, w, (cpx<float>*)G);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
+                       int prec, void* G, hipStream_t s) {
+#define VH_VS(D, S, P) \
+  if (dim == D && shape == S && patch == P) return vanka_setup_s<D, S, P>(g, A, w, prec, G, s);
+  VH_VS(2, CROSS, PATCH_FULL)
+  VH_VS(2, BOX1, PATCH_FULL)
+  VH_VS(2, BOX2, PATCH_FULL)
+  VH_VS(3, CROSS, PATCH_FULL)
+  VH_VS(3, BOX1, PATCH_FULL)
+  VH_VS(3, BOX2, PATCH_FULL)
+  VH_VS(2, CROSS, PATCH_POINT)
+  VH_VS(2, BOX1, PATCH_POINT)
+  VH_VS(2, BOX2, PATCH_POINT)
+  VH_VS(3, CROSS, PATCH_POINT)
+  VH_VS(3, BOX1, PATCH_POINT)
+  VH_VS(3, BOX2, PATCH_POINT)
+#undef VH_VS
+  return hipErrorInvalidValue;
+}
+
+// Assembled form of the same operator: B[d][i] = sum over (a, m) with
+// off_m - off_a = d of G[(a*Np+m)][i]  (d in the 5^DIM box, FULL patch), summed
+// in FP64.  u += B r is then a 5^DIM-point stencil sweep.
+template <int DIM, class T>
+__global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __restrict__ G,
+                                                        cpx<T>* __restrict__ B) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  constexpr int Np = patch_Np<DIM, PATCH_FULL>();
+  constexpr int K5 = shape_K<DIM, BOX2>();
+  const size_t N = (size_t)g.N;
+  for (int e = 0; e < K5; ++e) {
+    const int dx = shape_off<DIM, BOX2>(e, 0), dy = shape_off<DIM, BOX2>(e, 1),
+              dz = shape_off<DIM, BOX2>(e, 2);
+    cpx<double> acc = cmk(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < Np; ++a) {
+      const int mx = dx + patch_off<DIM, PATCH_FULL>(a, 0),
+                my = dy + patch_off<DIM, PATCH_FULL>(a, 1),
+                mz = dz + patch_off<DIM, PATCH_FULL>(a, 2);
+      const int m = shape_index<DIM, BOX1>(mx, my, mz);
+      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * N + i]);
+    }
+    B[(size_t)e * N + i] = ccast<T>(acc);
+  }
+}
+
+hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+  if (dim == 2) {
+    if (prec == PREC_F64)
+      k_vanka_assemble<2, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, (cpx<double>*)B);
+    else
+      k_vanka_assemble<2, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, (cpx<float>*)B);
+  } else {
+    if (prec == PREC_F64)
+      k_vanka_assemble<3, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, (cpx<double>*)B);
+    else
+      k_vanka_assemble<3, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, (cpx<float>*)B);
+  }
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ Galerkin
+// Sec. 3.1: H_c = R H P, one thread per coarse node I:
+//   H_c[I][J-I] = sum_t r(t) sum_s H[2I+t][s] p(2I+t+off_s - 2J),
+// t over the restriction box, s over the fine stencil, J over the coarse box; the
+// tensor-product weights are compile-time constants after unrolling.  Terms whose
+// fine node 2I+t or coarse node J lie outside the grid are dropped (truncated R, P).
+template <int DIM, int SIN, int SOUT, int RF, int PF>
+__global__ __launch_bounds__(256) void k_galerkin(Grid gf, Grid gc, const cpx<double>* __restrict__ Af,
+                                                  cpx<double>* __restrict__ Ac) {
+  const unsigned I = node_id();
+  if (I >= gc.N) return;
+  int Ix, Iy, Iz;
+  decode(I, gc, Ix, Iy, Iz);
+  constexpr int KI = shape_K<DIM, SIN>();
+  constexpr int KO = shape_K<DIM, SOUT>();
+  constexpr int RR = fam_radius(RF);
+  constexpr int RW = 2 * RR + 1;
+  constexpr int NT = ipow(RW, DIM);
+  constexpr int RO = shape_radius<DIM, SOUT>();
+  const size_t Nf = (size_t)gf.N;
+  cpx<double> acc[KO];
+#pragma unroll
+  for (int e = 0; e < KO; ++e) acc[e] = cmk(0.0, 0.0);
+  bool jok[KO];
+#pragma unroll
+  for (int e = 0; e < KO; ++e)
+    jok[e] = inside(gc, Ix + shape_off<DIM, SOUT>(e, 0), Iy + shape_off<DIM, SOUT>(e, 1),
+                    Iz + shape_off<DIM, SOUT>(e, 2));
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tx = t % RW - RR, ty = (t / RW) % RW - RR, tz = (DIM == 3) ? t / (RW * RW) - RR : 0;
+    const int fx = 2 * Ix + tx, fy = 2 * Iy + ty, fz = 2 * Iz + tz;
+    if (!inside(gf, fx, fy, fz)) continue;
+    const double wr = fam_r(RF, tx) * fam_r(RF, ty) * (DIM == 3 ? fam_r(RF, tz) : 1.0);
+    const long long fi = lin(gf, fx, fy, fz);
+#pragma unroll
+    for (int s = 0; s < KI; ++s) {
+      const int sx = shape_off<DIM, SIN>(s, 0), sy = shape_off<DIM, SIN>(s, 1),
+                sz = shape_off<DIM, SIN>(s, 2);
+      const cpx<double> hv = wr * Af[(size_t)s * Nf + fi];
+#pragma unroll
+      for (int e = 0; e < KO; ++e) {
+        const int ex = shape_off<DIM, SOUT>(e, 0), ey = shape_off<DIM, SOUT>(e, 1),
+                  ez = shape_off<DIM, SOUT>(e, 2);
+        // fine node j = 2I + t + s, coarse node J = I + e: 1D offsets j - 2J
+        const int ux = tx + sx - 2 * ex, uy = ty + sy - 2 * ey, uz = tz + sz - 2 * ez;
+        const double wp = fam_p(PF, ux) * fam_p(PF, uy) * (DIM == 3 ? fam_p(PF, uz) : 1.0);
+        if (wp != 0.0 && jok[e]) acc[e] = cfma(cmk(wp, 0.0), hv, acc[e]);
+      }
+    }
+  }
+  (void)RO;
+  const size_t Nc = (size_t)gc.N;
+#pragma unroll
+  for (int e = 0; e < KO; ++e) Ac[(size_t)e * Nc + I] = acc[e];
+}
+
+hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,
+                    const cpx<double>* Af, cpx<double>* Ac, hipStream_t s) {
+  const unsigned nb = nblocks(gc.N, 256);
+#define VH_GK(D, SI, SO, R, P)                                                         \
+  if (dim == D && sin == SI && sout == SO && rf == R && pf == P) {                     \
+    k_galerkin<D, SI, SO, R, P><<<nb, 256, 0, s>>>(gf, gc, Af, Ac);                    \
+    VH_LAUNCH_CHECK();                                                                 \
+    return hipSuccess;                                                                 \
+  }
+  VH_GK(2, CROSS, BOX2, FAM_CUBIC, FAM_CUBIC)   // level-dependent, finest -> 2nd
+  VH_GK(2, CROSS, BOX2, FAM_LINEAR, FAM_CUBIC)  // mixed from the finest level
+  VH_GK(2, BOX2, BOX2, FAM_LINEAR, FAM_CUBIC)   // level-dependent / mixed below
+  VH_GK(2, CROSS, BOX1, FAM_LINEAR, FAM_LINEAR) // bilinear
+  VH_GK(2, BOX1, BOX1, FAM_LINEAR, FAM_LINEAR)
+  VH_GK(3, CROSS, BOX1, FAM_LINEAR, FAM_LINEAR) // trilinear
+  VH_GK(3, BOX1, BOX1, FAM_LINEAR, FAM_LINEAR)
+#undef VH_GK
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ restriction / prolongation
+template <int DIM, int RF, class T>
+__global__ __launch_bounds__(256) void k_restrict(Grid gf, Grid gc, const cpx<T>* __restrict__ r,
+                                                  cpx<T>* __restrict__ rc) {
+  const unsigned I = node_id();
+  if (I >= gc.N) return;
+  int Ix, Iy, Iz;
+  decode(I, gc, Ix, Iy, Iz);
+  constexpr int RR = fam_radius(RF), RW = 2 * RR + 1, NT = ipow(RW, DIM);
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tx = t % RW - RR, ty = (t / RW) % RW - RR, tz = (DIM == 3) ? t / (RW * RW) - RR : 0;
+    const int fx = 2 * Ix + tx, fy = 2 * Iy + ty, fz = 2 * Iz + tz;
+    if (inside(gf, fx, fy, fz)) {
+      const T w = (T)(fam_r(RF, tx) * fam_r(RF, ty) * (DIM == 3 ? fam_r(RF, tz) : 1.0));
+      acc = cfma(cmk<T>(w, 0), r[lin(gf, fx, fy, fz)], acc);
+    }
+  }
+  rc[I] = acc;
+}
+
+template <int DIM, int PF, class T>
+__global__ __launch_bounds__(256) void k_prolong_add(Grid gf, Grid gc, const cpx<T>* __restrict__ e,
+                                                     cpx<T>* __restrict__ u) {
+  const unsigned i = node_id();
+  if (i >= gf.N) return;
+  int c[3];
+  decode(i, gf, c[0], c[1], c[2]);
+  // per dimension: candidate coarse nodes J0-1, J0, J0+1 (J0 = c/2) and weights p(c - 2J)
+  int J[3][3];
+  T w[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int J0 = c[d] >> 1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      J[d][q] = J0 + q - 1;
+      w[d][q] = (T)fam_p(PF, c[d] - 2 * (J0 + q - 1));
+    }
+  }
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int qz = 0; qz < (DIM == 3 ? 3 : 1); ++qz)
+#pragma unroll
+    for (int qy = 0; qy < 3; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx) {
+        const int Jx = J[0][qx], Jy = J[1][qy], Jz = (DIM == 3) ? J[2][qz] : 0;
+        const T wt = w[0][qx] * w[1][qy] * (DIM == 3 ? w[2][qz] : (T)1);
+        if (wt != (T)0 && inside(gc, Jx, Jy, Jz))
+          acc = cfma(cmk<T>(wt, 0), e[lin(gc, Jx, Jy, Jz)], acc);
+      }
+  u[i] = u[i] + acc;
+}
+
+hipError_t restrict_(int dim, int rf, Grid gf, Grid gc, int prec, const void* r, void* rc,
+                     hipStream_t s) {
+  const unsigned nb = nblocks(gc.N, 256);
+#define VH_RS(D, R, T)                                                                        \
+  if (dim == D && rf == R) {                                                                  \
+    k_restrict<D, R, T><<<nb, 256, 0, s>>>(gf, gc, (const cpx<T>*)r, (cpx<T>*)rc);            \
+    VH_LAUNCH_CHECK();                                                                        \
+    return hipSuccess;                                                                        \
+  }
+  if (prec == PREC_F64) {
+    VH_RS(2, FAM_LINEAR, double) VH_RS(2, FAM_CUBIC, double)
+    VH_RS(3, FAM_LINEAR, double) VH_RS(3, FAM_CUBIC, double)
+  } else {
+    VH_RS(2, FAM_LINEAR, float) VH_RS(2, FAM_CUBIC, float)
+    VH_RS(3, FAM_LINEAR, float) VH_RS(3, FAM_CUBIC, float)
+  }
+#undef VH_RS
+  return hipErrorInvalidValue;
+}
+
+hipError_t prolong_add(int dim, int pf, Grid gf, Grid gc, int prec, const void* e, void* u,
+                       hipStream_t s) {
+  const unsigned nb = nblocks(gf.N, 256);
+#define VH_PA(D, P, T)                                                                         \
+  if (dim == D && pf == P) {                                                                   \
+    k_prolong_add<D, P, T><<<nb, 256, 0, s>>>(gf, gc, (const cpx<T>*)e, (cpx<T>*)u);           \
+    VH_LAUNCH_CHECK();                                                                         \
+    return hipSuccess;                                                                         \
+  }
+  if (prec == PREC_F64) {
+    VH_PA(2, FAM_LINEAR, double) VH_PA(2, FAM_CUBIC, double)
+    VH_PA(3, FAM_LINEAR, double) VH_PA(3, FAM_CUBIC, double)
+  } else {
+    VH_PA(2, FAM_LINEAR, float) VH_PA(2, FAM_CUBIC, float)
+    VH_PA(3, FAM_LINEAR, float) VH_PA(3, FAM_CUBIC, float)
+  }
+#undef VH_PA
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ coarsest grid
+// Dense FP64 copy of the coarsest operator, then an in-place Gauss-Jordan inverse
+// with partial pivoting (explicit row swaps, columns unscrambled in reverse order).
+template <int DIM, int SHAPE>
+__global__ __launch_bounds__(256) void k_dense_assemble(Grid g, const cpx<double>* __restrict__ A,
+                                                        cpx<double>* __restrict__ D) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int cx, cy, cz;
+  decode(i, g, cx, cy, cz);
+  constexpr int K = shape_K<DIM, SHAPE>();
+  const size_t N = (size_t)g.N;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+              dz = shape_off<DIM, SHAPE>(k, 2);
+    if (inside(g, cx + dx, cy + dy, cz + dz)) {
+      const long long j = lin(g, cx + dx, cy + dy, cz + dz);
+      D[(size_t)i * N + j] = A[(size_t)k * N + i];
+    }
+  }
+}
+
+hipError_t dense_assemble(int dim, int shape, Grid g, const cpx<double>* A, cpx<double>* D,
+                          hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+#define VH_DA(DD, S)                                                   \
+  if (dim == DD && shape == S) {                                       \
+    k_dense_assemble<DD, S><<<nb, 256, 0, s>>>(g, A, D);               \
+    VH_LAUNCH_CHECK();                                                 \
+    return hipSuccess;                                                 \
+  }
+  VH_DA(2, CROSS) VH_DA(2, BOX1) VH_DA(2, BOX2) VH_DA(3, CROSS) VH_DA(3, BOX1) VH_DA(3, BOX2)
+#undef VH_DA
+  return hipErrorInvalidValue;
+}
+
+// pivot search in column k (rows >= k), row swap, scaling of the pivot row, and a
+// copy of column k (zero at the pivot row) for the elimination kernel
+__global__ __launch_bounds__(256) void k_gj_pivot(int n, int k, cpx<double>* __restrict__ M,
+                                                  int* __restrict__ perm,
+                                                  cpx<double>* __restrict__ col) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int t = threadIdx.x;
+  double bv = -1.0;
+  int bi = k;
+  for (int r = k + t; r < n; r += 256) {
+    const cpx<double> v = M[(size_t)r * n + k];
+    const double a = fabs(v.re) + fabs(v.im);
+    if (a > bv) {
+      bv = a;
+      bi = r;
+    }
+  }
+  sv[t] = bv;
+  si[t] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      const double ov = sv[t + w];
+      const int oi = si[t + w];
+      if (ov > sv[t] || (ov == sv[t] && oi < si[t])) {
+        sv[t] = ov;
+        si[t] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = si[0];
+  if (t == 0) perm[k] = p;
+  if (p != k) {
+    for (int j = t; j < n; j += 256) {
+      const cpx<double> a = M[(size_t)k * n + j];
+      M[(size_t)k * n + j] = M[(size_t)p * n + j];
+      M[(size_t)p * n + j] = a;
+    }
+  }
+  __syncthreads();
+  const cpx<double> inv = cinv(M[(size_t)k * n + k]);
+  __syncthreads();
+  for (int j = t; j < n; j += 256) {
+    const cpx<double> a = (j == k) ? cmk(1.0, 0.0) : M[(size_t)k * n + j];
+    M[(size_t)k * n + j] = a * inv;
+  }
+  for (int r = t; r < n; r += 256) col[r] = (r == k) ? cmk(0.0, 0.0) : M[(size_t)r * n + k];
+}
+
+__global__ __launch_bounds__(256) void k_gj_elim(int n, int k, cpx<double>* __restrict__ M,
+                                                 const cpx<double>* __restrict__ col) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j >= n || r == k) return;
+  const cpx<double> f = col[r];
+  if (f.re == 0.0 && f.im == 0.0) return;
+  const cpx<double> pk = M[(size_t)k * n + j];
+  if (j == k)
+    M[(size_t)r * n + k] = cmk(0.0, 0.0) - f * pk;
+  else
+    M[(size_t)r * n + j] = M[(size_t)r * n + j] - f * pk;
+}
+
+__global__ __launch_bounds__(256) void k_gj_unscramble(int n, cpx<double>* __restrict__ M,
+                                                       const int* __restrict__ perm) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k) {
+      const cpx<double> a = M[(size_t)r * n + k];
+      M[(size_t)r * n + k] = M[(size_t)r * n + p];
+      M[(size_t)r * n + p] = a;
+    }
+  }
+}
+
+hipError_t gj_invert(int n, cpx<double>* M, int* perm, cpx<double>* col, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, perm, col);
+    VH_LAUNCH_CHECK();
+    dim3 grid((n + 255) / 256, n);
+    k_gj_elim<<<grid, 256, 0, s>>>(n, k, M, col);
+    VH_LAUNCH_CHECK();
+  }
+  k_gj_unscramble<<<(n + 255) / 256, 256, 0, s>>>(n, M, perm);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// y = D x with D the FP64 dense inverse; one wavefront per row, fixed-order reduction
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_matvec(int n, const cpx<double>* __restrict__ D,
+                                                      const cpx<T>* __restrict__ x,
+                                                      cpx<T>* __restrict__ y) {
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  cpx<double> acc = cmk(0.0, 0.0);
+  for (int j = lane; j < n; j += 64) acc = cfma(D[(size_t)row * n + j], ccast<double>(x[j]), acc);
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.re += __shfl_down(acc.re, o, 64);
+    acc.im += __shfl_down(acc.im, o, 64);
+  }
+  if (lane == 0) y[row] = ccast<T>(acc);
+}
+
+hipError_t dense_matvec(int n, const cpx<double>* D, int prec, const void* x, void* y,
+                        hipStream_t s) {
+  const unsigned nb = (unsigned)((n * 64 + 255) / 256);
+  if (prec == PREC_F64)
+    k_dense_matvec<double><<<nb, 256, 0, s>>>(n, D, (const cpx<double>*)x, (cpx<double>*)y);
+  else
+    k_dense_matvec<float><<<nb, 256, 0, s>>>(n, D, (const cpx<float>*)x, (cpx<float>*)y);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ Krylov (FP64)
+// Block-partial multi-dot: part[b][j] = sum over block b's chunk of conj(V_j) w,
+// j < nv (nv <= KMAX).  Chunks are contiguous, partials are reduced in block order.
+constexpr int KMAX = 65;
+
+__device__ __forceinline__ cpx<double> wave_sum(cpx<double> v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_down(v.re, o, 64);
+    v.im += __shfl_down(v.im, o, 64);
+  }
+  return v;
+}
+
+// block reduction of one complex value, result valid in thread 0
+__device__ __forceinline__ cpx<double> block_sum(cpx<double> v, cpx<double>* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  cpx<double> out = cmk(0.0, 0.0);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) out = out + sh[q];
+  return out;
+}
+
+__device__ __forceinline__ void chunk(size_t N, size_t& lo, size_t& hi) {
+  const size_t per = (N + gridDim.x - 1) / gridDim.x;
+  lo = (size_t)blockIdx.x * per;
+  hi = lo + per < N ? lo + per : N;
+}
+
+// mode 0: part = V^H w;  mode 1: w -= V h, part = V^H w (after the update);
+// mode 2: w -= V h, part[0] = ||w||^2.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_cgs(const cpx<double>* __restrict__ V, size_t ldv, int nv,
+                                             const cpx<double>* __restrict__ h,
+                                             cpx<double>* __restrict__ w, size_t N,
+                                             cpx<double>* __restrict__ part) {
+  __shared__ cpx<double> sh[4];
+  __shared__ cpx<double> hs[KMAX];
+  if (MODE != 0) {
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) hs[j] = h[j];
+    __syncthreads();
+  }
+  size_t lo, hi;
+  chunk(N, lo, hi);
+  const int nout = (MODE == 2) ? 1 : nv;
+  // process the outputs in groups of 8 to bound register use
+  for (int j0 = 0; j0 < nout; j0 += 8) {
+    cpx<double> acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = cmk(0.0, 0.0);
+    for (size_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      cpx<double> wi = w[i];
+      if (MODE != 0 && j0 == 0) {
+        for (int j = 0; j < nv; ++j) wi = wi - hs[j] * V[(size_t)j * ldv + i];
+        w[i] = wi;
+      }
+      if (MODE == 2) {
+        acc[0].re += wi.re * wi.re + wi.im * wi.im;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (j0 + q < nv) acc[q] = cfma_conj(V[(size_t)(j0 + q) * ldv + i], wi, acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (j0 + q < nout) {
+        const cpx<double> s = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * KMAX + j0 + q] = s;
+      }
+    }
+    if (MODE != 0) __syncthreads();
+  }
+}
+
+// out[j] = sum_b part[b][j] in block order (one thread per output)
+__global__ void k_reduce_part(const cpx<double>* __restrict__ part, int nb, int nv,
+                              cpx<double>* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= nv) return;
+  cpx<double> s = cmk(0.0, 0.0);
+  for (int b = 0; b < nb; ++b) s = s + part[(size_t)b * KMAX + j];
+  out[j] = s;
+}
+
+hipError_t cgs_pass(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                    cpx<double>* w, size_t N, cpx<double>* part, int nb, cpx<double>* out,
+                    hipStream_t s) {
+  if (mode == 0)
+    k_cgs<0><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+  else if (mode == 1)
+    k_cgs<1><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+  else
+    k_cgs<2><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+  VH_LAUNCH_CHECK();
+  k_reduce_part<<<1, 128, 0, s>>>(part, nb, mode == 2 ? 1 : nv, out);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// Arnoldi column j: H[:,j] = h1 + h2 (CGS2), H[j+1][j] = ||w||; apply the previous
+// Givens rotations, form the new one, update g; status = |g[j+1]|, 1/||w||.
+__global__ void k_arnoldi_finalize(KrylovDev* __restrict__ K, int j, int ldh) {
+  if (threadIdx.x != 0) return;
+  cpx<double>* Hc = K->H + (size_t)j * ldh;
+  for (int i = 0; i <= j; ++i) Hc[i] = K->h1[i] + K->h2[i];
+  const double nrm = sqrt(K->nrm2[0].re);
+  Hc[j + 1] = cmk(nrm, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const cpx<double> a = Hc[i], b = Hc[i + 1];
+    const double c = K->cs[i];
+    const cpx<double> sn = K->sn[i];
+    Hc[i] = c * a + sn * b;
+    Hc[i + 1] = c * b - cmk(sn.re, -sn.im) * a;
+  }
+  const cpx<double> a = Hc[j];
+  const double b = nrm;
+  double c;
+  cpx<double> sn;
+  const double aa = sqrt(a.re * a.re + a.im * a.im);
+  if (aa == 0.0) {
+    c = 0.0;
+    sn = cmk(1.0, 0.0);
+  } else {
+    const double r = sqrt(aa * aa + b * b);
+    c = aa / r;
+    sn = cmk(a.re / aa * b / r, a.im / aa * b / r);  // (a/|a|) * conj(b) / r, b real
+  }
+  K->cs[j] = c;
+  K->sn[j] = sn;
+  Hc[j] = c * a + sn * cmk(b, 0.0);
+  Hc[j + 1] = cmk(0.0, 0.0);
+  const cpx<double> gj = K->g[j];
+  K->g[j + 1] = cmk(0.0, 0.0) - cmk(sn.re, -sn.im) * gj;
+  K->g[j] = c * gj;
+  const cpx<double> gn = K->g[j + 1];
+  K->status[0] = sqrt(gn.re * gn.re + gn.im * gn.im);
+  K->status[1] = nrm;
+  K->inv_nrm = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  const bool bad = !(nrm == nrm) || !(K->status[0] == K->status[0]) || isinf(nrm);
+  K->status[2] = bad ? 1.0 : 0.0;
+}
+
+hipError_t arnoldi_finalize(KrylovDev* K, int j, int ldh, hipStream_t s) {
+  k_arnoldi_finalize<<<1, 64, 0, s>>>(K, j, ldh);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// y = R^{-1} g (k x k upper triangle of H)
+__global__ void k_backsolve(KrylovDev* __restrict__ K, int k, int ldh) {
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    cpx<double> s = K->g[i];
+    for (int q = i + 1; q < k; ++q) s = s - K->H[(size_t)q * ldh + i] * K->y[q];
+    K->y[i] = s * cinv(K->H[(size_t)i * ldh + i]);
+  }
+}
+
+hipError_t backsolve(KrylovDev* K, int k, int ldh, hipStream_t s) {
+  k_backsolve<<<1, 64, 0, s>>>(K, k, ldh);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// x += sum_j y_j Z_j  (Z at the preconditioner precision)
+template <class TZ>
+__global__ __launch_bounds__(256) void k_update_x(const KrylovDev* __restrict__ K, int k,
+                                                  const cpx<TZ>* __restrict__ Z, size_t ldz,
+                                                  cpx<double>* __restrict__ x, size_t N) {
+  __shared__ cpx<double> ys[KMAX];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = K->y[j];
+  __syncthreads();
+  const size_t i = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  cpx<double> a = x[i];
+  for (int j = 0; j < k; ++j) a = cfma(ys[j], ccast<double>(Z[(size_t)j * ldz + i]), a);
+  x[i] = a;
+}
+
+hipError_t update_x(const KrylovDev* K, int k, int pz, const void* Z, size_t ldz,
+                    cpx<double>* x, size_t N, hipStream_t s) {
+  const unsigned nb = nblocks((long long)N, 256);
+  if (pz == PREC_F64)
+    k_update_x<double><<<nb, 256, 0, s>>>(K, k, (const cpx<double>*)Z, ldz, x, N);
+  else
+    k_update_x<float><<<nb, 256, 0, s>>>(K, k, (const cpx<float>*)Z, ldz, x, N);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// v = w * scale (scale read from the device: K->inv_nrm or 1/beta)
+__global__ __launch_bounds__(256) void k_scale(const double* __restrict__ scale,
+                                               const cpx<double>* __restrict__ w,
+                                               cpx<double>* __restrict__ v, size_t N) {
+  const size_t i = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  v[i] = scale[0] * w[i];
+}
+
+hipError_t scale_vec(const double* scale, const cpx<double>* w, cpx<double>* v, size_t N,
+                     hipStream_t s) {
+  k_scale<<<nblocks((long long)N, 256), 256, 0, s>>>(scale, w, v, N);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// new cycle: beta = sqrt(nrm2), inv_nrm = 1/beta, g = (beta, 0, ...)
+__global__ void k_cycle_init(KrylovDev* __restrict__ K, int m) {
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(K->nrm2[0].re);
+  K->g[0] = cmk(beta, 0.0);
+  for (int i = 1; i <= m; ++i) K->g[i] = cmk(0.0, 0.0);
+  K->inv_nrm = beta > 0.0 ? 1.0 / beta : 0.0;
+  K->status[3] = beta;
+}
+
+hipError_t cycle_init(KrylovDev* K, int m, hipStream_t s) {
+  k_cycle_init<<<1, 64, 0, s>>>(K, m);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace vh

@@ -1,0 +1,729 @@
+// vh_runtime.hip -- host runtime and C ABI (include/vh.h) of the gfx950 solver.
+//
+// Owns the device hierarchy, drives the V-cycle (Sec. 2.2) and FGMRES(m)
+// (Sec. 2.3).  Every arithmetic step runs in the kernels of vh_kernels.hip; the
+// host only sequences launches and reads back one residual estimate per Arnoldi
+// step to decide when to stop.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vh.h"
+#include "vh_launch.h"
+
+using namespace vh;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+vh_status fail(vh_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define VH_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(e_ == hipErrorOutOfMemory ? VH_ENOMEM : VH_EDEVICE,                         \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+#define VH_TRY(expr)                \
+  do {                              \
+    vh_status s_ = (expr);          \
+    if (s_ != VH_OK) return s_;     \
+  } while (0)
+
+struct Level {
+  Grid g{};
+  int shape = CROSS;  // stencil shape of H_s^l
+  int K = 0;
+  void* A = nullptr;  // H_s^l, [K][N], preconditioner precision
+  void* B = nullptr;  // smoother entries [E][N] (per-patch or assembled)
+  int E = 0;
+  void* q = nullptr;  // right-hand side, solution, residual (preconditioner precision)
+  void* u = nullptr;
+  void* r = nullptr;
+  int rf = FAM_LINEAR, pf = FAM_LINEAR;  // transfers to level l+1
+  double w = 1.0;                         // damping
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct vh_handle {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  double h = 0, omega = 0, shift = 0;
+  int levels = 1;
+  int patch = VH_PATCH_FULL;
+  vh_options opt{};
+  int prec = PREC_F64;
+  size_t esz = 16;  // bytes per complex at the preconditioner precision
+  hipStream_t s = nullptr;
+  std::vector<Level> L;
+  cpx<double>* Hfine = nullptr;  // unshifted finest operator, FP64 [K0][N]
+  cpx<double>* Dinv = nullptr;   // inverse of the coarsest operator, FP64 dense
+  int nc = 0;
+  // FGMRES workspace
+  int m = 20;
+  cpx<double>* V = nullptr;  // (m+1) x N
+  void* Z = nullptr;         // m x N at the preconditioner precision
+  cpx<double>* part = nullptr;
+  int nred = 512;
+  KrylovDev* K = nullptr;
+  double* hstat = nullptr;  // pinned host copy of K->status
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  ~vh_handle() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hstat) (void)hipHostFree(hstat);
+  }
+  vh_status alloc(void** p, size_t bytes_) {
+    *p = nullptr;
+    if (bytes_ == 0) return VH_OK;
+    hipError_t e = hipMalloc(p, bytes_);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return fail(VH_ENOMEM, "hipMalloc of " + std::to_string(bytes_) + " bytes failed: " +
+                                 hipGetErrorString(e));
+    }
+    allocs.push_back(*p);
+    bytes += bytes_;
+    return VH_OK;
+  }
+  void release(void* p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
+  }
+};
+
+namespace {
+
+int shape_points(int dim, int shape) {
+  if (shape == CROSS) return 2 * dim + 1;
+  int w = 2 * shape + 1;
+  return dim == 2 ? w * w : w * w * w;
+}
+
+void shape_offsets(int dim, int shape, int K, int out[][3]) {
+  for (int k = 0; k < K; ++k) {
+    if (shape == CROSS) {
+      out[k][0] = out[k][1] = out[k][2] = 0;
+      if (k > 0) out[k][(k - 1) / 2] = ((k - 1) % 2 == 0) ? -1 : 1;
+    } else {
+      const int w = 2 * shape + 1;
+      out[k][0] = k % w - shape;
+      out[k][1] = (k / w) % w - shape;
+      out[k][2] = dim == 3 ? k / (w * w) - shape : 0;
+    }
+  }
+}
+
+int patch_size(int dim, int patch) { return patch == VH_PATCH_FULL ? (dim == 2 ? 9 : 27) : 1; }
+
+// damping used when the caller passes none: the full patch values come from LFA on
+// the finest level and an exhaustive per-level search (readings of Table
+// "relaxParam" for the 2nd-order stencil); the point patch from LFA.
+double default_damping(int dim, int patch, int level) {
+  static const double full2[] = {0.94, 1.2, 0.4, 0.6};
+  static const double full3[] = {1.08, 0.9, 0.6, 0.6};
+  static const double point2[] = {0.78, 0.7, 0.4, 0.6};
+  static const double point3[] = {0.84, 0.7, 0.5, 0.5};
+  const double* t = patch == VH_PATCH_FULL ? (dim == 2 ? full2 : full3) : (dim == 2 ? point2 : point3);
+  return t[level < 3 ? level : 3];
+}
+
+vh_status validate(int dim, const int* n, double h, double omega, double shift, int levels,
+                   int patch, const vh_options& o) {
+  if (dim != 2 && dim != 3) return fail(VH_EINVAL, "dim must be 2 or 3");
+  if (!n) return fail(VH_EINVAL, "n is NULL");
+  if (!(h > 0) || !std::isfinite(h)) return fail(VH_EINVAL, "h must be positive");
+  if (!(omega >= 0) || !std::isfinite(omega)) return fail(VH_EINVAL, "omega must be >= 0");
+  if (!(shift >= 0) || !std::isfinite(shift)) return fail(VH_EINVAL, "shift must be >= 0");
+  if (levels < 1 || levels > 16) return fail(VH_EINVAL, "levels must be in [1, 16]");
+  if (patch != VH_PATCH_FULL && patch != VH_PATCH_POINT) return fail(VH_EINVAL, "unknown patch");
+  long long N = 1;
+  for (int d = 0; d < dim; ++d) {
+    if (n[d] < 3) return fail(VH_EINVAL, "every dimension needs >= 3 nodes");
+    const long long c = n[d] - 1;
+    const long long div = 1LL << (levels - 1);
+    if (c % div != 0)
+      return fail(VH_EINVAL, "(n[d]-1) must be divisible by 2^(levels-1)");
+    if (c / div < 2) return fail(VH_EINVAL, "the coarsest level needs >= 3 nodes per dimension");
+    N *= n[d];
+  }
+  if (N >= (1LL << 31)) return fail(VH_EINVAL, "grid too large (N >= 2^31)");
+  if (o.precision != VH_PREC_FP64 && o.precision != VH_PREC_C64)
+    return fail(VH_EINVAL, "unknown precision");
+  if (o.restart < 1 || o.restart > MMAX) return fail(VH_EINVAL, "restart must be in [1, 64]");
+  if (o.maxit < 1) return fail(VH_EINVAL, "maxit must be >= 1");
+  if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 8 || o.nu2 > 8)
+    return fail(VH_EINVAL, "nu1, nu2 must be in [0, 8] with nu1 + nu2 >= 1");
+  if (o.bc != VH_BC_ABC && o.bc != VH_BC_DIRICHLET) return fail(VH_EINVAL, "unknown bc");
+  if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
+    return fail(VH_EINVAL, "unknown smoother");
+  if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
+  // the coarsest level is solved by a dense inverse
+  long long nc = 1;
+  for (int d = 0; d < dim; ++d) nc *= (n[d] - 1) / (1LL << (levels - 1)) + 1;
+  if (nc > 8192) return fail(VH_EINVAL, "coarsest level too large for the dense solve (> 8192 nodes)");
+  return VH_OK;
+}
+
+int resolve_intergrid(int dim, int ig) {
+  if (ig < 0) return dim == 2 ? VH_IG_LEVDEP : VH_IG_LINEAR;
+  return ig;
+}
+
+// (R family, P family, output shape) for the transfer from level l with shape `sin`
+vh_status transfer_plan(int dim, int ig, int l, int sin, int* rf, int* pf, int* sout) {
+  if (ig == VH_IG_LINEAR) {
+    *rf = FAM_LINEAR;
+    *pf = FAM_LINEAR;
+    *sout = BOX1;
+    return VH_OK;
+  }
+  if (dim == 3) return fail(VH_EUNSUPPORTED, "3D supports only the trilinear intergrid");
+  if (ig == VH_IG_LEVDEP) {
+    *rf = (l == 0) ? FAM_CUBIC : FAM_LINEAR;
+    *pf = FAM_CUBIC;
+    *sout = BOX2;
+    return VH_OK;
+  }
+  if (ig == VH_IG_MIXED) {
+    *rf = FAM_LINEAR;
+    *pf = FAM_CUBIC;
+    *sout = BOX2;
+    return VH_OK;
+  }
+  return fail(VH_EINVAL, "unknown intergrid");
+}
+
+size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N * hd->esz; }
+
+// ---------------------------------------------------------------- V-cycle
+vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
+  if (hd->opt.smoother == VH_SMOOTHER_ASSEMBLED) {
+    VH_HIP(stencil(hd->dim, BOX2, Lv.g, zero ? OP_APPLY : OP_ADD, hd->prec, Lv.B, hd->prec, r,
+                   hd->prec, nullptr, u, hd->s));
+  } else {
+    VH_HIP(vanka_patch(hd->dim, hd->patch, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
+  }
+  return VH_OK;
+}
+
+vh_status residual(vh_handle* hd, Level& Lv, const void* q, const void* u, void* r) {
+  VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_RESID, hd->prec, Lv.A, hd->prec, u, hd->prec, q, r,
+                 hd->s));
+  return VH_OK;
+}
+
+vh_status vcycle(vh_handle* hd, int l, const void* q, void* u) {
+  Level& Lv = hd->L[l];
+  if (l == hd->levels - 1) {
+    VH_HIP(dense_matvec(hd->nc, hd->Dinv, hd->prec, q, u, hd->s));
+    return VH_OK;
+  }
+  const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
+  if (nu1 == 0) VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
+  for (int k = 0; k < nu1; ++k) {
+    if (k == 0) {
+      VH_TRY(smooth(hd, Lv, q, u, true));  // u = 0: the residual is q
+    } else {
+      VH_TRY(residual(hd, Lv, q, u, Lv.r));
+      VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+    }
+  }
+  Level& Lc = hd->L[l + 1];
+  VH_TRY(residual(hd, Lv, q, u, Lv.r));
+  VH_HIP(restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s));
+  VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u));
+  VH_HIP(prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, hd->prec, Lc.u, u, hd->s));
+  for (int k = 0; k < nu2; ++k) {
+    VH_TRY(residual(hd, Lv, q, u, Lv.r));
+    VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+  }
+  return VH_OK;
+}
+
+// z (preconditioner precision) = M^{-1} v (FP64)
+vh_status precondition(vh_handle* hd, const cpx<double>* v, void* z) {
+  Level& L0 = hd->L[0];
+  const void* q = v;
+  if (hd->prec != PREC_F64) {
+    VH_HIP(convert(v, PREC_F64, L0.q, hd->prec, (size_t)L0.g.N, hd->s));
+    q = L0.q;
+  }
+  return vcycle(hd, 0, q, z);
+}
+
+vh_status read_status(vh_handle* hd) {
+  VH_HIP(hipMemcpyAsync(hd->hstat, hd->K->status, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                        hd->s));
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+// ---------------------------------------------------------------- FGMRES(m)
+vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double tol,
+                     vh_solve_stats* st) {
+  const size_t N = (size_t)hd->L[0].g.N;
+  const int m = hd->m, ldh = MMAX + 1;
+  KrylovDev* K = hd->K;
+  cpx<double>* V = hd->V;
+  auto Vj = [&](int j) { return V + (size_t)j * N; };
+  auto Zj = [&](int j) { return (void*)((char*)hd->Z + (size_t)j * N * hd->esz); };
+  const int K0 = 2 * hd->dim + 1;
+  (void)K0;
+
+  VH_HIP(fill(x, N, PREC_F64, 0.0, 0.0, hd->s));
+  // r = q (x = 0); beta = ||q||
+  VH_HIP(hipMemcpyAsync(Vj(0), q, N * sizeof(cpx<double>), hipMemcpyDeviceToDevice, hd->s));
+  VH_HIP(cgs_pass(2, V, N, 0, K->h2, Vj(0), N, hd->part, hd->nred, K->nrm2, hd->s));
+  VH_HIP(cycle_init(K, m, hd->s));
+  VH_HIP(scale_vec(&K->inv_nrm, Vj(0), Vj(0), N, hd->s));
+  VH_TRY(read_status(hd));
+  const double bnorm = hd->hstat[3];
+  double beta = bnorm;
+  int its = 0, restarts = 0;
+  bool converged = false;
+  double est = 1.0;
+  if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(VH_EBREAKDOWN, "non-finite right-hand side");
+  if (bnorm == 0.0) {
+    if (st) *st = vh_solve_stats{0, 0, 1, 0.0, 0.0, 0.0};
+    return VH_OK;
+  }
+  while (true) {
+    if (beta / bnorm <= tol) {
+      converged = true;
+      break;
+    }
+    if (its >= hd->opt.maxit) break;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      VH_TRY(precondition(hd, Vj(j), Zj(j)));
+      VH_HIP(stencil(hd->dim, CROSS, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
+                     PREC_F64, nullptr, Vj(j + 1), hd->s));
+      VH_HIP(cgs_pass(0, V, N, j + 1, nullptr, Vj(j + 1), N, hd->part, hd->nred, K->h1, hd->s));
+      VH_HIP(cgs_pass(1, V, N, j + 1, K->h1, Vj(j + 1), N, hd->part, hd->nred, K->h2, hd->s));
+      VH_HIP(cgs_pass(2, V, N, j + 1, K->h2, Vj(j + 1), N, hd->part, hd->nred, K->nrm2, hd->s));
+      VH_HIP(arnoldi_finalize(K, j, ldh, hd->s));
+      VH_HIP(scale_vec(&K->inv_nrm, Vj(j + 1), Vj(j + 1), N, hd->s));
+      ++its;
+      k = j + 1;
+      VH_TRY(read_status(hd));
+      if (hd->hstat[2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
+      est = hd->hstat[0] / bnorm;
+      if (est <= tol || its >= hd->opt.maxit || hd->hstat[1] == 0.0) break;
+    }
+    VH_HIP(backsolve(K, k, ldh, hd->s));
+    VH_HIP(update_x(K, k, hd->prec, hd->Z, N, x, N, hd->s));
+    // true residual r = q - H x (FP64), V_0 = r / ||r||
+    VH_HIP(stencil(hd->dim, CROSS, hd->L[0].g, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, x,
+                   PREC_F64, q, Vj(0), hd->s));
+    VH_HIP(cgs_pass(2, V, N, 0, K->h2, Vj(0), N, hd->part, hd->nred, K->nrm2, hd->s));
+    VH_HIP(cycle_init(K, m, hd->s));
+    VH_HIP(scale_vec(&K->inv_nrm, Vj(0), Vj(0), N, hd->s));
+    VH_TRY(read_status(hd));
+    beta = hd->hstat[3];
+    ++restarts;
+    if (!(beta == beta) || std::isinf(beta)) return fail(VH_EBREAKDOWN, "non-finite residual");
+  }
+  if (st) {
+    st->iterations = its;
+    st->restarts = restarts;
+    st->converged = converged ? 1 : 0;
+    st->relres = beta / bnorm;
+    st->relres_est = est;
+  }
+  return converged ? VH_OK : fail(VH_ENOCONV, "maxit reached before tol");
+}
+
+// ---------------------------------------------------------------- setup
+vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
+  const int dim = hd->dim;
+  const vh_options& o = hd->opt;
+  const int ig = resolve_intergrid(dim, o.intergrid);
+  hipStream_t s = hd->s;
+  hd->L.resize(hd->levels);
+  // grids and transfer plan
+  int nn[3] = {hd->n[0], hd->n[1], dim == 3 ? hd->n[2] : 1};
+  int shape = CROSS;
+  for (int l = 0; l < hd->levels; ++l) {
+    Level& Lv = hd->L[l];
+    Lv.g = make_grid(dim, nn[0], nn[1], nn[2]);
+    Lv.shape = shape;
+    Lv.K = shape_points(dim, shape);
+    Lv.w = (l < o.ndamping) ? o.damping[l]
+                            : (o.ndamping > 0 ? o.damping[o.ndamping - 1]
+                                              : default_damping(dim, hd->patch, l));
+    if (l + 1 < hd->levels) {
+      int sout;
+      VH_TRY(transfer_plan(dim, ig, l, shape, &Lv.rf, &Lv.pf, &sout));
+      shape = sout;
+      for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
+    }
+  }
+  const size_t N0 = (size_t)hd->L[0].g.N;
+  {  // media check: kappa > 0 and gamma >= 0, all finite
+    int* flag = nullptr;
+    VH_TRY(hd->alloc((void**)&flag, sizeof(int)));
+    VH_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    VH_HIP(check_media((long long)N0, kappa, gamma, flag, s));
+    int hflag = 0;
+    VH_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    VH_HIP(hipStreamSynchronize(s));
+    hd->release(flag);
+    hd->bytes -= sizeof(int);
+    if (hflag) return fail(VH_EINVAL, "kappa must be finite and > 0, gamma finite and >= 0");
+  }
+  // finest operator, FP64
+  std::vector<cpx<double>*> A64(hd->levels, nullptr);
+  VH_TRY(hd->alloc((void**)&hd->Hfine, hd->L[0].K * N0 * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&A64[0], hd->L[0].K * N0 * sizeof(cpx<double>)));
+  VH_HIP(fine_operator(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
+                       o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
+  // Galerkin hierarchy, FP64
+  for (int l = 0; l + 1 < hd->levels; ++l) {
+    Level &Lf = hd->L[l], &Lc = hd->L[l + 1];
+    VH_TRY(hd->alloc((void**)&A64[l + 1], (size_t)Lc.K * Lc.g.N * sizeof(cpx<double>)));
+    VH_HIP(galerkin(dim, Lf.shape, Lc.shape, Lf.rf, Lf.pf, Lf.g, Lc.g, A64[l], A64[l + 1], s));
+  }
+  // per level: operator at the preconditioner precision, patch inverses, vectors
+  const int Np = patch_size(dim, hd->patch);
+  for (int l = 0; l < hd->levels; ++l) {
+    Level& Lv = hd->L[l];
+    const size_t N = (size_t)Lv.g.N;
+    if (hd->prec == PREC_F64) {
+      Lv.A = A64[l];
+    } else {
+      VH_TRY(hd->alloc(&Lv.A, (size_t)Lv.K * N * hd->esz));
+      VH_HIP(convert(A64[l], PREC_F64, Lv.A, hd->prec, (size_t)Lv.K * N, s));
+    }
+    VH_TRY(hd->alloc(&Lv.q, N * hd->esz));
+    VH_TRY(hd->alloc(&Lv.u, N * hd->esz));
+    VH_TRY(hd->alloc(&Lv.r, N * hd->esz));
+    VH_HIP(fill(Lv.q, N, hd->prec, 0, 0, s));
+    VH_HIP(fill(Lv.u, N, hd->prec, 0, 0, s));
+    VH_HIP(fill(Lv.r, N, hd->prec, 0, 0, s));
+    Lv.bytes = ((size_t)Lv.K + 3) * N * hd->esz;
+    if (l + 1 == hd->levels) break;
+    void* G = nullptr;
+    VH_TRY(hd->alloc(&G, (size_t)Np * Np * N * hd->esz));
+    VH_HIP(fill(G, (size_t)Np * Np * N, hd->prec, 0, 0, s));
+    VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, Lv.g, A64[l], Lv.w, hd->prec, G, s));
+    if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch == VH_PATCH_FULL) {
+      const int K5 = dim == 2 ? 25 : 125;
+      VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * N * hd->esz));
+      VH_HIP(vanka_assemble(dim, Lv.g, hd->prec, G, Lv.B, s));
+      VH_HIP(hipStreamSynchronize(s));
+      hd->release(G);
+      hd->bytes -= (size_t)Np * Np * N * hd->esz;
+      Lv.E = K5;
+    } else {
+      Lv.B = G;
+      Lv.E = Np * Np;
+    }
+    Lv.bytes += (size_t)Lv.E * N * hd->esz;
+  }
+  if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch != VH_PATCH_FULL)
+    hd->opt.smoother = VH_SMOOTHER_PATCH;  // a 1x1 patch is already a 1-point stencil
+  // coarsest: dense FP64 inverse
+  {
+    Level& Lc = hd->L[hd->levels - 1];
+    const int nc = (int)Lc.g.N;
+    hd->nc = nc;
+    int* perm = nullptr;
+    cpx<double>* col = nullptr;
+    VH_TRY(hd->alloc((void**)&hd->Dinv, (size_t)nc * nc * sizeof(cpx<double>)));
+    VH_TRY(hd->alloc((void**)&perm, (size_t)nc * sizeof(int)));
+    VH_TRY(hd->alloc((void**)&col, (size_t)nc * sizeof(cpx<double>)));
+    VH_HIP(fill(hd->Dinv, (size_t)nc * nc, PREC_F64, 0, 0, s));
+    VH_HIP(dense_assemble(dim, Lc.shape, Lc.g, A64[hd->levels - 1], hd->Dinv, s));
+    VH_HIP(gj_invert(nc, hd->Dinv, perm, col, s));
+    VH_HIP(hipStreamSynchronize(s));
+    hd->release(perm);
+    hd->release(col);
+    hd->bytes -= (size_t)nc * (sizeof(int) + sizeof(cpx<double>));
+  }
+  VH_HIP(hipStreamSynchronize(s));
+  if (hd->prec != PREC_F64)
+    for (int l = 0; l < hd->levels; ++l) {
+      hd->bytes -= (size_t)hd->L[l].K * hd->L[l].g.N * sizeof(cpx<double>);
+      hd->release(A64[l]);
+    }
+  // FGMRES workspace
+  hd->m = o.restart;
+  VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc(&hd->Z, (size_t)hd->m * N0 * hd->esz));
+  VH_TRY(hd->alloc((void**)&hd->part, (size_t)hd->nred * 65 * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&hd->K, sizeof(KrylovDev)));
+  VH_HIP(hipMemsetAsync(hd->K, 0, sizeof(KrylovDev), s));
+  VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
+  VH_HIP(hipStreamSynchronize(s));
+  return VH_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+void vh_options_default(vh_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = VH_PREC_FP64;
+  o->restart = 20;
+  o->maxit = 1000;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->intergrid = -1;
+  o->bc = VH_BC_ABC;
+  o->sponge_width = 20;
+  o->sponge_amp = 1.0;
+  o->smoother = VH_SMOOTHER_PATCH;
+  o->ndamping = 0;
+  o->stream = nullptr;
+}
+
+const char* vh_status_string(vh_status s) {
+  switch (s) {
+    case VH_OK: return "ok";
+    case VH_EINVAL: return "invalid argument";
+    case VH_ENOMEM: return "out of device memory";
+    case VH_ENOCONV: return "not converged";
+    case VH_EBREAKDOWN: return "breakdown (NaN/Inf)";
+    case VH_EDEVICE: return "device error";
+    case VH_EUNSUPPORTED: return "unsupported option combination";
+    default: return "unknown status";
+  }
+}
+
+const char* vh_last_error(void) { return g_last_error.c_str(); }
+
+vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omega,
+                   const double* kappa, const double* gamma, double shift, int levels, int patch,
+                   const vh_options* opt) {
+  if (!out) return fail(VH_EINVAL, "out is NULL");
+  *out = nullptr;
+  vh_options o;
+  if (opt)
+    o = *opt;
+  else
+    vh_options_default(&o);
+  VH_TRY(validate(dim, n, h, omega, shift, levels, patch, o));
+  if (!kappa) return fail(VH_EINVAL, "kappa is NULL");
+  const int ig = resolve_intergrid(dim, o.intergrid);
+  if (ig != VH_IG_LEVDEP && ig != VH_IG_MIXED && ig != VH_IG_LINEAR)
+    return fail(VH_EINVAL, "unknown intergrid");
+  if (dim == 3 && ig != VH_IG_LINEAR)
+    return fail(VH_EUNSUPPORTED, "3D supports only the trilinear intergrid");
+  vh_handle* hd = new (std::nothrow) vh_handle();
+  if (!hd) return fail(VH_ENOMEM, "host allocation failed");
+  hd->dim = dim;
+  for (int d = 0; d < dim; ++d) hd->n[d] = n[d];
+  hd->h = h;
+  hd->omega = omega;
+  hd->shift = shift;
+  hd->levels = levels;
+  hd->patch = patch;
+  hd->opt = o;
+  hd->prec = o.precision == VH_PREC_FP64 ? PREC_F64 : PREC_F32;
+  hd->esz = hd->prec == PREC_F64 ? 16 : 8;
+  hd->s = (hipStream_t)o.stream;
+  vh_status st = build(hd, kappa, gamma);
+  if (st != VH_OK) {
+    (void)hipStreamSynchronize(hd->s);
+    delete hd;
+    return st;
+  }
+  *out = hd;
+  return VH_OK;
+}
+
+vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
+                   vh_solve_stats* stats) {
+  if (!hd || !q || !u) return fail(VH_EINVAL, "NULL argument");
+  if (nsrc < 1) return fail(VH_EINVAL, "nsrc must be >= 1");
+  if (!(tol > 0)) return fail(VH_EINVAL, "tol must be > 0");
+  if (q == u) return fail(VH_EINVAL, "q and u may not alias");
+  const size_t N = (size_t)hd->L[0].g.N;
+  vh_status worst = VH_OK;
+  for (int sidx = 0; sidx < nsrc; ++sidx) {
+    hipEvent_t e0, e1;
+    VH_HIP(hipEventCreate(&e0));
+    VH_HIP(hipEventCreate(&e1));
+    VH_HIP(hipEventRecord(e0, hd->s));
+    vh_solve_stats st{};
+    vh_status r = fgmres_one(hd, (const cpx<double>*)q + sidx * N, (cpx<double>*)u + sidx * N,
+                             tol, &st);
+    (void)hipEventRecord(e1, hd->s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st.solve_ms = ms;
+    if (stats) stats[sidx] = st;
+    if (r != VH_OK && r != VH_ENOCONV) return r;
+    if (r == VH_ENOCONV) worst = VH_ENOCONV;
+  }
+  return worst == VH_OK ? VH_OK : fail(worst, "maxit reached before tol");
+}
+
+vh_status vh_destroy(vh_handle* hd) {
+  if (!hd) return VH_OK;
+  (void)hipStreamSynchronize(hd->s);
+  delete hd;
+  return VH_OK;
+}
+
+int vh_num_levels(const vh_handle* hd) { return hd ? hd->levels : 0; }
+
+vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info) {
+  if (!hd || !info || level < 0 || level >= hd->levels) return fail(VH_EINVAL, "bad level");
+  const Level& Lv = hd->L[level];
+  std::memset(info, 0, sizeof(*info));
+  info->n[0] = Lv.g.nx;
+  info->n[1] = Lv.g.ny;
+  info->n[2] = Lv.g.nz;
+  info->stencil_points = Lv.K;
+  info->smoother_entries = Lv.E;
+  shape_offsets(hd->dim, Lv.shape, Lv.K, info->offsets);
+  info->bytes = Lv.bytes;
+  return VH_OK;
+}
+
+vh_status vh_apply_operator(vh_handle* hd, int level, int which, const void* x, void* y) {
+  if (!hd || !x || !y || level < 0 || level >= hd->levels) return fail(VH_EINVAL, "bad argument");
+  Level& Lv = hd->L[level];
+  const size_t N = (size_t)Lv.g.N;
+  if (which == 0) {
+    if (level != 0) return fail(VH_EINVAL, "the unshifted operator exists on level 0 only");
+    VH_HIP(stencil(hd->dim, CROSS, Lv.g, OP_APPLY, PREC_F64, hd->Hfine, PREC_F64, x, PREC_F64,
+                   nullptr, y, hd->s));
+  } else if (hd->prec == PREC_F64) {
+    VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_APPLY, PREC_F64, Lv.A, PREC_F64, x, PREC_F64,
+                   nullptr, y, hd->s));
+  } else {
+    VH_HIP(convert(x, PREC_F64, Lv.r, hd->prec, N, hd->s));
+    VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_APPLY, hd->prec, Lv.A, hd->prec, Lv.r, hd->prec,
+                   nullptr, Lv.u, hd->s));
+    VH_HIP(convert(Lv.u, hd->prec, y, PREC_F64, N, hd->s));
+  }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+vh_status vh_apply_vcycle(vh_handle* hd, const void* v, void* z) {
+  if (!hd || !v || !z) return fail(VH_EINVAL, "bad argument");
+  Level& L0 = hd->L[0];
+  const size_t N = (size_t)L0.g.N;
+  if (hd->prec == PREC_F64) {
+    VH_TRY(vcycle(hd, 0, v, z));
+  } else {
+    VH_TRY(precondition(hd, (const cpx<double>*)v, L0.u));
+    VH_HIP(convert(L0.u, hd->prec, z, PREC_F64, N, hd->s));
+  }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+vh_status vh_apply_smoother(vh_handle* hd, int level, const void* q, void* u) {
+  if (!hd || !q || !u || level < 0 || level + 1 >= hd->levels)
+    return fail(VH_EINVAL, "bad argument (the coarsest level has no smoother)");
+  Level& Lv = hd->L[level];
+  const size_t N = (size_t)Lv.g.N;
+  if (hd->prec == PREC_F64) {
+    VH_TRY(residual(hd, Lv, q, u, Lv.r));
+    VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+  } else {
+    VH_HIP(convert(q, PREC_F64, Lv.q, hd->prec, N, hd->s));
+    VH_HIP(convert(u, PREC_F64, Lv.u, hd->prec, N, hd->s));
+    VH_TRY(residual(hd, Lv, Lv.q, Lv.u, Lv.r));
+    VH_TRY(smooth(hd, Lv, Lv.r, Lv.u, false));
+    VH_HIP(convert(Lv.u, hd->prec, u, PREC_F64, N, hd->s));
+  }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+vh_status vh_export_level(const vh_handle* hdc, int level, void* coef, void* smoother,
+                          void* coarse_inv) {
+  vh_handle* hd = const_cast<vh_handle*>(hdc);
+  if (!hd || level < 0 || level >= hd->levels) return fail(VH_EINVAL, "bad level");
+  Level& Lv = hd->L[level];
+  const size_t N = (size_t)Lv.g.N;
+  auto copy_out = [&](const void* src, size_t count, void* dst) -> vh_status {
+    if (hd->prec == PREC_F64) {
+      VH_HIP(hipMemcpyAsync(dst, src, count * 16, hipMemcpyDeviceToHost, hd->s));
+    } else {
+      void* tmp = nullptr;
+      VH_HIP(hipMalloc(&tmp, count * 16));
+      hipError_t e = convert(src, hd->prec, tmp, PREC_F64, count, hd->s);
+      if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, count * 16, hipMemcpyDeviceToHost, hd->s);
+      if (e == hipSuccess) e = hipStreamSynchronize(hd->s);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return fail(VH_EDEVICE, hipGetErrorString(e));
+    }
+    return VH_OK;
+  };
+  if (coef) VH_TRY(copy_out(Lv.A, (size_t)Lv.K * N, coef));
+  if (smoother && Lv.B) VH_TRY(copy_out(Lv.B, (size_t)Lv.E * N, smoother));
+  if (coarse_inv) {
+    if (level != hd->levels - 1) return fail(VH_EINVAL, "coarse_inv only on the coarsest level");
+    VH_HIP(hipMemcpyAsync(coarse_inv, hd->Dinv, (size_t)hd->nc * hd->nc * 16,
+                          hipMemcpyDeviceToHost, hd->s));
+  }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, const vh_options* opt) {
+  vh_options o;
+  if (opt)
+    o = *opt;
+  else
+    vh_options_default(&o);
+  if ((dim != 2 && dim != 3) || !n || levels < 1) return 0;
+  const size_t esz = o.precision == VH_PREC_FP64 ? 16 : 8;
+  const int ig = resolve_intergrid(dim, o.intergrid);
+  const int Np = patch_size(dim, patch);
+  size_t nn[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
+  size_t total = 0, N0 = nn[0] * nn[1] * nn[2];
+  int shape = CROSS;
+  total += (size_t)(2 * dim + 1) * N0 * 16;  // unshifted H
+  for (int l = 0; l < levels; ++l) {
+    const size_t N = nn[0] * nn[1] * nn[2];
+    const int K = shape_points(dim, shape);
+    total += (size_t)K * N * esz + 3 * N * esz;
+    if (l + 1 == levels) {
+      total += N * N * 16;
+      break;
+    }
+    const int E = (o.smoother == VH_SMOOTHER_ASSEMBLED && patch == VH_PATCH_FULL)
+                      ? (dim == 2 ? 25 : 125)
+                      : Np * Np;
+    total += (size_t)E * N * esz;
+    shape = (ig == VH_IG_LINEAR) ? BOX1 : BOX2;
+    for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
+  }
+  total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz;
+  total += 512 * 65 * 16 + sizeof(KrylovDev);
+  return total;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-only logic (defaults, status strings, argument validation, footprint) works
+without touching a GPU."""
+import os
+import re
+
+import pytest
+
+from paper_2511_16808_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vh.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vh_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 13
+    L = B.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B._SIGNATURES), "binding and header disagree"
+
+
+def test_defaults_and_status_strings():
+    o = B.vh_options_default()
+    assert (o.precision, o.restart, o.maxit, o.nu1, o.nu2) == (B.VH_PREC_FP64, 20, 1000, 1, 1)
+    assert o.sponge_width == 20 and o.sponge_amp == 1.0 and o.intergrid == -1
+    assert B.vh_status_string(B.VH_ENOCONV) == "not converged"
+    assert B.vh_status_string(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("dim,n,levels,err", [
+    (2, (129, 129), 9, "divisible"),        # 128 cells cannot be halved 8 times
+    (2, (130, 129), 2, "divisible"),        # odd number of cells
+    (2, (2, 129), 1, ">= 3 nodes"),
+    (4, (9, 9), 1, "dim"),
+    (2, (257, 257), 2, "coarsest level too large"),
+])
+def test_setup_rejects_bad_arguments_before_any_device_work(dim, n, levels, err):
+    with pytest.raises(B.VhError) as e:
+        B.vh_setup(dim, n, 1 / 128, 10.0, None, None, 0.1, levels, B.VH_PATCH_FULL)
+    assert e.value.status == B.VH_EINVAL and err in str(e.value)
+
+
+def test_setup_rejects_bad_options():
+    for field, value in (("restart", 0), ("restart", 65), ("precision", 7), ("nu1", -1),
+                         ("bc", 5), ("smoother", 3)):
+        o = B.make_options(**{field: value})
+        with pytest.raises(B.VhError) as e:
+            B.vh_setup(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 3, B.VH_PATCH_FULL, o)
+        assert e.value.status == B.VH_EINVAL, field
+
+
+def test_footprint_matches_the_layout():
+    """C2-shaped 2D FP64 hierarchy: the per-patch inverses dominate (81 c128 per node)."""
+    n = (1025, 1025)
+    fp = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL)
+    N = 1025 * 1025
+    inv_fine = 81 * 16 * N
+    assert inv_fine < fp < 2.6 * inv_fine
+    o = B.make_options(precision=B.VH_PREC_C64)
+    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, o) < 0.62 * fp
+    o = B.make_options(smoother=B.VH_SMOOTHER_ASSEMBLED)
+    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, o) < 0.6 * fp

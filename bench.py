@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the Vanka-smoothed shifted-Laplacian Helmholtz solver on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic input: vh_setup
+(finest operator, Galerkin hierarchy, every patch inverse, coarsest inverse) and
+vh_solve (FGMRES(m) preconditioned by V(1,1) cycles to true relative residual 1e-6)
+from a medium and a source already resident in HBM, then vh_destroy.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+
+Prints ONE JSON line.  Workloads (synthetic media, seeded):
+  c1  2D 129^2 nodes, homogeneous, 4 levels, complex128 (the oracle solves it in seconds)
+  c2  2D 1025^2 layered medium, 7 levels, complex128
+  c3  3D 257^3 geophysical medium, 6 levels, complex64 preconditioner / complex128 FGMRES
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Helmholtz solves/s to rel.res 1e-6 (512^2, 256^3); V-cycle HBM GB/s; p50/p99 ms"
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    "c1": dict(desc="2D homogeneous 129x129 nodes (128^2 cells), kappa=1, 10 ppw, gamma=0.01*omega, "
+                    "ABC, shift 0.1, 4-level V(1,1), Full 3x3 Vanka, FGMRES(20), complex128",
+               dim=2, n=(129, 129), levels=4, alpha=0.1, medium="homogeneous", seed=0,
+               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6],
+               sample=dict(n=(129, 129), levels=4)),
+    "c2": dict(desc="2D layered 1025x1025 nodes (1024^2 cells), 8-14 layers kappa in [0.25,1] + "
+                    "5% smooth noise, 10 ppw at kappa_max, gamma=0.01*omega, ABC, shift 0.1, "
+                    "7-level V(1,1), Full 3x3 Vanka, FGMRES(20), complex128",
+               dim=2, n=(1025, 1025), levels=7, alpha=0.1, medium="layered_2d", seed=2,
+               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6],
+               sample=dict(n=(513, 513), levels=6)),
+    "c3": dict(desc="3D geophysical 257^3 nodes (256^3 cells), v in [1.5,4.5] km/s with dipping "
+                    "layers and a 5 km/s ellipsoid, 10 ppw, gamma=0.01*omega, ABC, shift 0.5, "
+                    "6-level trilinear V(1,1), Full 3x3x3 Vanka, complex64 preconditioner, "
+                    "FGMRES(30) in complex128",
+               dim=3, n=(257, 257, 257), levels=6, alpha=0.5, medium="geophysical_3d", seed=3,
+               precision=1, restart=30, damping=[1.08, 0.9, 0.6, 0.6],
+               sample=dict(n=(33, 33, 33), levels=3)),
+}
+DEFAULT_WORKLOAD = "c3"
+
+
+def make_medium(w, n=None):
+    import numpy as np
+    import synth
+    n = tuple(n or w["n"])
+    if w["medium"] == "homogeneous":
+        kappa = synth.homogeneous(n)
+    elif w["medium"] == "layered_2d":
+        kappa = synth.layered_2d(n, w["seed"])
+    else:
+        kappa = synth.geophysical_3d(n, w["seed"])
+    h = 1.0 / (n[0] - 1)
+    omega = synth.omega_for_ppw(h, 10.0, float(kappa.max()))
+    gamma = 0.01 * omega * np.ones_like(kappa)
+    q = synth.point_source(n).ravel()
+    return n, h, omega, kappa, gamma, q
+
+
+def vcycle_bytes(levels_info, dim, esz, smoother_entries):
+    """Algorithmic HBM bytes of one V(1,1) cycle: each array touched once per kernel."""
+    total = 0
+    L = len(levels_info)
+    for l, info in enumerate(levels_info):
+        N = 1
+        for k in info["n"][:dim]:
+            N *= k
+        if l == L - 1:
+            total += N * N * 16 + 2 * N * esz
+            break
+        Nc = 1
+        for k in levels_info[l + 1]["n"][:dim]:
+            Nc *= k
+        K, E = info["stencil_points"], smoother_entries[l]
+        total += N * esz * (2 * E + 2 * K + 15) + Nc * esz * 2
+    return total
+
+
+def cpu_baseline(w, gpu_iterations):
+    """Times the FP64 oracle (single thread) on a reduced grid of the same recipe:
+    setup + 2 FGMRES iterations, scaled linearly in nodes to the full grid and to the
+    GPU's iteration count."""
+    sample = w["sample"]
+    code = f"""
+import json, sys, time
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from bench import WORKLOADS, make_medium
+from oracle import discretization as D, cycle, krylov
+w = WORKLOADS[{w['key']!r}]
+n, h, omega, kappa, gamma, q = make_medium(w, {tuple(sample['n'])!r})
+t0 = time.perf_counter()
+ops = D.fd2_operator(n, h, omega, kappa, gamma, w['alpha'])
+mg = cycle.Multigrid(ops['Hs'], n, {sample['levels']}, 'levdep' if len(n) == 2 else 'linear',
+                     'full', w['damping'])
+t1 = time.perf_counter()
+its = 2
+krylov.fgmres(lambda v: ops['H'] @ v, mg.apply, q, 1e-30, w['restart'], its)
+t2 = time.perf_counter()
+print(json.dumps(dict(setup_s=t1 - t0, iter_s=(t2 - t1) / its, N=int(np.prod(n)))))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    t0 = time.perf_counter()
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600)
+    wall = time.perf_counter() - t0
+    if out.returncode != 0:
+        return {"error": out.stderr[-400:]}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    Nfull = 1
+    for k in w["n"]:
+        Nfull *= k
+    scale = Nfull / r["N"]
+    t_solve = scale * (r["setup_s"] + gpu_iterations * r["iter_s"])
+    return {
+        "value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle setup + 2 FGMRES iterations on the same recipe at "
+                   f"{'x'.join(map(str, sample['n']))} nodes ({sample['levels']} levels), "
+                   f"setup {r['setup_s']:.1f}s, {r['iter_s']:.2f}s/iteration, scaled x{scale:.1f} "
+                   f"in nodes and to {gpu_iterations} iterations; single thread; "
+                   f"{wall:.1f}s of CPU work"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smoother", default="patch", choices=["patch", "assembled"])
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is design-only, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2511_16808_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_probe_mib > 0:
+        # one elementwise kernel that reads and writes exactly MiB << 20 bytes each
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    w = dict(WORKLOADS[args.workload], key=args.workload)
+    n, h, omega, kappa, gamma, q = make_medium(w)
+    dim = w["dim"]
+    N = int(np.prod(n))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    kt = torch.tensor(kappa.ravel(), dtype=torch.float64, device=dev)
+    gt = torch.tensor(gamma.ravel(), dtype=torch.float64, device=dev)
+    qt = torch.tensor(q, dtype=torch.complex128, device=dev)
+    ut = torch.empty_like(qt)
+    smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
+    opt = B.make_options(precision=w["precision"], restart=w["restart"], damping=w["damping"],
+                         intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR,
+                         smoother=smoother, stream=stream, timing=1)
+    torch.cuda.synchronize()
+
+    def step():
+        t0 = time.perf_counter()
+        hd = B.vh_setup(dim, n, h, omega, kt, gt, w["alpha"], w["levels"], B.VH_PATCH_FULL, opt)
+        t1 = time.perf_counter()
+        st, stats = B.vh_solve(hd, qt, 1, 1e-6, ut)
+        info = [B.vh_get_level_info(hd, l) for l in range(w["levels"])]
+        B.vh_destroy(hd)
+        t2 = time.perf_counter()
+        return dict(status=st, stats=stats[0], setup_ms=1e3 * (t1 - t0),
+                    step_ms=1e3 * (t2 - t0), info=info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    last = runs[-1]
+    st = last["stats"]
+    esz = 16 if w["precision"] == 0 else 8
+    info = last["info"]
+    E = [i["smoother_entries"] for i in info]
+    # dominant kernel: finest-level additive-Vanka sweep u += B r
+    n_l = sum(r["stats"]["smooth1_launches"] for r in runs)
+    ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
+    bytes_per_launch = N * esz * (E[0] + 3)
+    achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get(args.workload)
+    vc_b = vcycle_bytes(info, dim, esz, E)
+    vc_n = sum(r["stats"]["vcycles"] for r in runs)
+    vc_ms = sum(r["stats"]["vcycle_ms"] for r in runs)
+    lat = np.array([r["step_ms"] for r in runs])
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if w["precision"] == 0 else "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w['desc']}", "nodes": N, "levels": w["levels"],
+                   "smoother": args.smoother, "sources": 1},
+        "iterations": st["iterations"],
+        "converged": bool(st["converged"]) and all(r["status"] == 0 for r in runs),
+        "true_relres": st["relres"],
+        "setup_ms": float(np.median([r["setup_ms"] for r in runs])),
+        "solve_ms": float(np.median([r["stats"]["solve_ms"] for r in runs])),
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "vcycle_ms": vc_ms / vc_n if vc_n else None,
+        "vcycle_GBps": (vc_b / (vc_ms / vc_n * 1e-3) / 1e9) if vc_n else None,
+        "vcycle_algorithmic_bytes": vc_b,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "finest-level additive Vanka sweep u += B r (k_vanka_patch)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": ms_l / n_l if n_l else None,
+            "launches": n_l,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, st["iterations"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

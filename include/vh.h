@@ -83,6 +83,9 @@ typedef struct vh_options {
     int ndamping;           /* number of valid entries in damping[]; 0 = defaults      */
     double damping[16];     /* w_l for level l = 0 (finest) ...; the last one repeats   */
     void *stream;           /* hipStream_t; NULL = null stream                         */
+    int timing;             /* 1: vh_solve brackets every V-cycle and every finest-level
+                               smoothing launch with HIP events on `stream` and reports the
+                               summed durations in vh_solve_stats; default 0              */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -92,6 +95,13 @@ typedef struct vh_solve_stats {
     double relres;          /* true ||q - H u|| / ||q||, FP64                          */
     double relres_est;      /* Arnoldi estimate at exit                                */
     double solve_ms;        /* wall time of the solve on the stream (HIP events)       */
+    /* filled when vh_options.timing = 1 (zero otherwise):                              */
+    int vcycles;            /* V-cycle applications                                     */
+    double vcycle_ms;       /* their summed duration                                    */
+    int smooth0_launches;   /* finest-level smoothing launches from u = 0 (u = B q)     */
+    double smooth0_ms;
+    int smooth1_launches;   /* finest-level smoothing launches u += B r                 */
+    double smooth1_ms;
 } vh_solve_stats;
 
 typedef struct vh_level_info {

@@ -38,7 +38,7 @@ class vh_options(ctypes.Structure):
         ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("intergrid", ctypes.c_int),
         ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
         ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
-        ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p),
+        ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
     ]
 
 
@@ -46,6 +46,9 @@ class vh_solve_stats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
         ("relres", ctypes.c_double), ("relres_est", ctypes.c_double), ("solve_ms", ctypes.c_double),
+        ("vcycles", ctypes.c_int), ("vcycle_ms", ctypes.c_double),
+        ("smooth0_launches", ctypes.c_int), ("smooth0_ms", ctypes.c_double),
+        ("smooth1_launches", ctypes.c_int), ("smooth1_ms", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -253,77 +253,103 @@ hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, 
 //     u_i += sum_{a,m} G[(a*Np+m)][i] * r[i - off_a + off_m].
 // Every patch inverse entry is read exactly once per sweep; no atomics.
 // 2D: the 5x5 neighbourhood of r is loaded once into registers.
-template <int DIM, int PATCH, bool ZERO, class T>
-__global__ __launch_bounds__(256) void k_vanka_patch(Grid g, const cpx<T>* __restrict__ G,
+// Streaming loads of the patch inverses: read once per sweep, so they are loaded
+// non-temporally to leave L2 / MALL to the vectors.
+template <class T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load((const v2*)p);
+  return cmk<T>(v.x, v.y);
+}
+
+// Tile of the sweep: TX x TY nodes (x, y) in one z-plane; each wavefront covers 64
+// consecutive nodes of one grid row, so every load of the smoother entries is one
+// contiguous 64-node run.  The residual is staged in LDS with a halo of 2 (patch
+// radius 1 + member radius 1).
+constexpr int VT_X = 64, VT_Y = 4, VT_H = 2;
+
+// Smoother entry sets: the per-patch form (entry a*Np + m reads r at off_m - off_a)
+// and the assembled form (the 5^DIM box).
+enum SmForm : int { SM_FULL = 0, SM_POINT = 1, SM_BOX2 = 2 };
+
+template <int DIM, int FORM>
+__host__ __device__ constexpr int sm_entries() {
+  return FORM == SM_BOX2 ? shape_K<DIM, BOX2>() : patch_Np<DIM, FORM>() * patch_Np<DIM, FORM>();
+}
+template <int DIM, int FORM>
+__host__ __device__ constexpr int sm_off(int e, int c) {
+  return FORM == SM_BOX2 ? shape_off<DIM, BOX2>(e, c)
+                         : patch_off<DIM, FORM>(e % patch_Np<DIM, FORM>(), c) -
+                               patch_off<DIM, FORM>(e / patch_Np<DIM, FORM>(), c);
+}
+
+template <int DIM, int FORM, bool ZERO, class T>
+__global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __restrict__ G,
                                                      const cpx<T>* __restrict__ r,
                                                      cpx<T>* __restrict__ u) {
-  const unsigned i = node_id();
-  if (i >= g.N) return;
-  int cx, cy, cz;
-  decode(i, g, cx, cy, cz);
-  constexpr int Np = patch_Np<DIM, PATCH>();
+  constexpr int SX = VT_X + 2 * VT_H, SY = VT_Y + 2 * VT_H, SZ = (DIM == 3) ? 1 + 2 * VT_H : 1;
+  constexpr int HZ = (DIM == 3) ? VT_H : 0;
+  __shared__ cpx<T> tile[SZ * SY * SX];
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (g.nx + VT_X - 1) / VT_X, nby = (g.ny + VT_Y - 1) / VT_Y;
+  const int bx = (int)(b % (unsigned)nbx), by = (int)((b / (unsigned)nbx) % (unsigned)nby);
+  const int bz = (int)(b / (unsigned)(nbx * nby));
+  const int x0 = bx * VT_X, y0 = by * VT_Y, z0 = bz;
+  for (int e = threadIdx.x; e < SX * SY * SZ; e += blockDim.x) {
+    const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+    const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+    tile[e] = inside(g, gx, gy, gz) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % VT_X, ly = threadIdx.x / VT_X;
+  const int x = x0 + lx, y = y0 + ly, z = z0;
+  if (x >= g.nx || y >= g.ny) return;
+  const long long i = lin(g, x, y, z);
+  constexpr int E = sm_entries<DIM, FORM>();
+  // 3D per-patch form: one patch (27 entries) per iteration, to bound register use
+  constexpr int UNR = (DIM == 3 && FORM == SM_FULL) ? 27 : E;
   const size_t N = (size_t)g.N;
+  const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
   cpx<T> acc = cmk<T>(0, 0);
-  if (DIM == 2) {
-    cpx<T> rn[25];
+#pragma unroll 1
+  for (int e0 = 0; e0 < E; e0 += UNR) {
 #pragma unroll
-    for (int e = 0; e < 25; ++e) {
-      const int dx = e % 5 - 2, dy = e / 5 - 2;
-      rn[e] = inside(g, cx + dx, cy + dy, cz) ? r[(long long)i + dx + (long long)g.nx * dy]
-                                              : cmk<T>(0, 0);
-    }
-#pragma unroll
-    for (int a = 0; a < Np; ++a) {
-#pragma unroll
-      for (int m = 0; m < Np; ++m) {
-        const int dx = patch_off<DIM, PATCH>(m, 0) - patch_off<DIM, PATCH>(a, 0);
-        const int dy = patch_off<DIM, PATCH>(m, 1) - patch_off<DIM, PATCH>(a, 1);
-        acc = cfma(G[(size_t)(a * Np + m) * N + i], rn[(dx + 2) + 5 * (dy + 2)], acc);
-      }
-    }
-  } else {
-#pragma unroll 3
-    for (int a = 0; a < Np; ++a) {
-      const int ax = patch_off<DIM, PATCH>(a, 0), ay = patch_off<DIM, PATCH>(a, 1),
-                az = patch_off<DIM, PATCH>(a, 2);
-#pragma unroll
-      for (int m = 0; m < Np; ++m) {
-        const int dx = patch_off<DIM, PATCH>(m, 0) - ax, dy = patch_off<DIM, PATCH>(m, 1) - ay,
-                  dz = patch_off<DIM, PATCH>(m, 2) - az;
-        if (inside(g, cx + dx, cy + dy, cz + dz)) {
-          const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-          acc = cfma(G[(size_t)(a * Np + m) * N + i], r[j], acc);
-        }
-      }
+    for (int q = 0; q < UNR; ++q) {
+      const int e = e0 + q;
+      const int dx = sm_off<DIM, FORM>(e, 0), dy = sm_off<DIM, FORM>(e, 1),
+                dz = sm_off<DIM, FORM>(e, 2);
+      acc = cfma(ld_stream(G + (size_t)e * N + i), t0[(dz * SY + dy) * SX + dx], acc);
     }
   }
   u[i] = ZERO ? acc : (u[i] + acc);
 }
 
-template <int DIM, int PATCH, class T>
-static hipError_t vanka_patch_t(Grid g, const void* G, const void* r, void* u, bool zero,
+template <int DIM, int FORM, class T>
+static hipError_t vanka_sweep_t(Grid g, const void* G, const void* r, void* u, bool zero,
                                 hipStream_t s) {
-  const unsigned nb = nblocks(g.N, 256);
+  const unsigned nb = (unsigned)(((g.nx + VT_X - 1) / VT_X) * ((g.ny + VT_Y - 1) / VT_Y) * g.nz);
   if (zero)
-    k_vanka_patch<DIM, PATCH, true, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r,
-                                                          (cpx<T>*)u);
+    k_vanka_sweep<DIM, FORM, true, T><<<nb, VT_X * VT_Y, 0, s>>>(g, (const cpx<T>*)G,
+                                                                 (const cpx<T>*)r, (cpx<T>*)u);
   else
-    k_vanka_patch<DIM, PATCH, false, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r,
-                                                           (cpx<T>*)u);
+    k_vanka_sweep<DIM, FORM, false, T><<<nb, VT_X * VT_Y, 0, s>>>(g, (const cpx<T>*)G,
+                                                                  (const cpx<T>*)r, (cpx<T>*)u);
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t vanka_patch(int dim, int patch, Grid g, int prec, const void* G, const void* r, void* u,
+hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const void* r, void* u,
                        bool zero, hipStream_t s) {
-#define VH_VP(D, P)                                                              \
-  if (dim == D && patch == P)                                                    \
-    return prec == PREC_F64 ? vanka_patch_t<D, P, double>(g, G, r, u, zero, s) \
-                            : vanka_patch_t<D, P, float>(g, G, r, u, zero, s);
-  VH_VP(2, PATCH_FULL)
-  VH_VP(3, PATCH_FULL)
-  VH_VP(2, PATCH_POINT)
-  VH_VP(3, PATCH_POINT)
+#define VH_VP(D, F)                                                              \
+  if (dim == D && form == F)                                                     \
+    return prec == PREC_F64 ? vanka_sweep_t<D, F, double>(g, G, r, u, zero, s) \
+                            : vanka_sweep_t<D, F, float>(g, G, r, u, zero, s);
+  VH_VP(2, SM_FULL)
+  VH_VP(3, SM_FULL)
+  VH_VP(2, SM_POINT)
+  VH_VP(3, SM_POINT)
+  VH_VP(2, SM_BOX2)
+  VH_VP(3, SM_BOX2)
 #undef VH_VP
   return hipErrorInvalidValue;
 }
@@ -347,18 +373,35 @@ __device__ __forceinline__ int patch_count(const Grid& g, int x, int y, int z) {
   return c;
 }
 
+// waves per block of the setup kernel: the LDS staging area (Np*Np rows of PB
+// patches) must fit in 64 KB
+template <int DIM, int PATCH, class T>
+__host__ __device__ constexpr int setup_waves() {
+  return (patch_Np<DIM, PATCH>() * patch_Np<DIM, PATCH>() * 4 * (64 / patch_Np<DIM, PATCH>()) *
+              (int)sizeof(cpx<T>) <= 65536)
+             ? 4
+             : 2;
+}
+
 template <int DIM, int SHAPE, int PATCH, class T>
 __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
                                                      double w, cpx<T>* __restrict__ G) {
   constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int PPW = 64 / Np;
+  constexpr int WPB = setup_waves<DIM, PATCH, T>();
+  constexpr int PB = WPB * PPW;  // patches per block
+  __shared__ cpx<T> stage[Np * Np * PB];
+  __shared__ unsigned char okrow[Np * PB];
   const unsigned lane = threadIdx.x & 63u;
-  const unsigned wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const unsigned wib = threadIdx.x >> 6;  // wave in block
   const unsigned slot = lane / Np;
   const int k = (int)(lane % Np);
-  const long long c = (long long)wave * PPW + slot;
-  const bool active = slot < (unsigned)PPW && c < g.N;
-  const int base = (int)(slot < (unsigned)PPW ? slot : 0) * Np;
+  const long long c0 = (long long)blockIdx.x * PB;
+  const int pslot = (int)(wib * PPW + slot);
+  const long long c = c0 + pslot;
+  const bool in_slot = slot < (unsigned)PPW;
+  const bool active = in_slot && c < g.N;
+  const int base = (int)(in_slot ? slot : 0) * Np;
   const size_t N = (size_t)g.N;
   int cx = 0, cy = 0, cz = 0;
   if (active) decode((unsigned)c, g, cx, cy, cz);
@@ -382,12 +425,19 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
     }
   }
 
+  // Gauss-Jordan steps: the step loop stays rolled and every access to the row a[]
+  // uses a compile-time index (select by comparison), so a[] lives in registers.
+  // The pivot sequence of each patch is kept in LDS.
+  __shared__ unsigned char pivs[PB * Np];
   bool used = false;
   int mystep = k;
-  int piv[Np];
-#pragma unroll
+#pragma unroll 1
   for (int s = 0; s < Np; ++s) {
-    const double v = used ? -1.0 : (fabs(a[s].re) + fabs(a[s].im));
+    cpx<double> as = cmk(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < Np; ++m)
+      if (m == s) as = a[m];
+    const double v = used ? -1.0 : (fabs(as.re) + fabs(as.im));
     int best = 0;
     double bv = -2.0;
 #pragma unroll
@@ -398,17 +448,16 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
         best = r;
       }
     }
-    piv[s] = best;
+    if (in_slot && k == 0) pivs[pslot * Np + s] = (unsigned char)best;
     const bool am = (k == best);
     if (am) {
-      const cpx<double> inv = cinv(a[s]);
-      a[s] = cmk(1.0, 0.0);
+      const cpx<double> inv = cinv(as);
 #pragma unroll
-      for (int m = 0; m < Np; ++m) a[m] = a[m] * inv;
+      for (int m = 0; m < Np; ++m) a[m] = ((m == s) ? cmk(1.0, 0.0) : a[m]) * inv;
       used = true;
       mystep = s;
     }
-    const cpx<double> f = a[s];
+    const cpx<double> f = as;
     const int src = base + best;
 #pragma unroll
     for (int m = 0; m < Np; ++m) {
@@ -421,9 +470,11 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
       }
     }
   }
+  __syncthreads();
 
-  if (!mem_in) return;
-  // this lane holds row `mystep` of the inverse; destination = member mystep of c
+  // this lane holds row i = mystep of the inverse; its destination is member i of c.
+  // Stage the weighted row in LDS as [i*Np + m][patch], then write each of the Np*Np
+  // rows for the block's PB consecutive patches as one contiguous run.
   const int i = mystep;
   int ox = 0, oy = 0, oz = 0;
 #pragma unroll
@@ -434,13 +485,22 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
       oz = patch_off<DIM, PATCH>(q, 2);
     }
   const int jx = cx + ox, jy = cy + oy, jz = cz + oz;
-  if (!inside(g, jx, jy, jz)) return;  // only reachable with non-finite patch entries
-  const long long j = lin(g, jx, jy, jz);
-  const double wt = w / (double)patch_count<DIM, PATCH>(g, jx, jy, jz);
+  // destination outside the grid: an out-of-domain member (or, only with
+  // non-finite patch entries, an inconsistent pivot sequence)
+  const bool ok = mem_in && inside(g, jx, jy, jz);
+  if (in_slot) {
+    const double wt = ok ? w / (double)patch_count<DIM, PATCH>(g, jx, jy, jz) : 0.0;
 #pragma unroll
-  for (int s = 0; s < Np; ++s) {
-    const int m = piv[s];
-    G[(size_t)(i * Np + m) * N + j] = ccast<T>(wt * a[s]);
+    for (int s = 0; s < Np; ++s) stage[(pivs[pslot * Np + s] + i * Np) * PB + pslot] = ccast<T>(wt * a[s]);
+    okrow[i * PB + pslot] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < Np * Np * PB; e += blockDim.x) {
+    const int r = e / PB, p = e % PB, ii = r / Np;
+    if (!okrow[ii * PB + p]) continue;
+    const long long off = lin(g, patch_off<DIM, PATCH>(ii, 0), patch_off<DIM, PATCH>(ii, 1),
+                              patch_off<DIM, PATCH>(ii, 2));
+    G[(size_t)r * N + (size_t)(c0 + p + off)] = stage[e];
   }
 }
 
@@ -449,12 +509,15 @@ static hipError_t vanka_setup_s(Grid g, const cpx<double>* A, double w, int prec
                                 hipStream_t s) {
   constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int PPW = 64 / Np;
-  const long long waves = (g.N + PPW - 1) / PPW;
-  const unsigned nb = (unsigned)((waves + 3) / 4);
-  if (prec == PREC_F64)
-    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 256, 0, s>>>(g, A, w, (cpx<double>*)G);
-  else
-    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 256, 0, s>>>(g, A, w, (cpx<float>*)G);
+  if (prec == PREC_F64) {
+    constexpr int WPB = setup_waves<DIM, PATCH, double>();
+    const unsigned nb = (unsigned)((g.N + WPB * PPW - 1) / (WPB * PPW));
+    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<double>*)G);
+  } else {
+    constexpr int WPB = setup_waves<DIM, PATCH, float>();
+    const unsigned nb = (unsigned)((g.N + WPB * PPW - 1) / (WPB * PPW));
+    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<float>*)G);
+  }
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -931,14 +994,21 @@ __global__ __launch_bounds__(256) void k_cgs(const cpx<double>* __restrict__ V, 
   }
 }
 
-// out[j] = sum_b part[b][j] in block order (one thread per output)
-__global__ void k_reduce_part(const cpx<double>* __restrict__ part, int nb, int nv,
-                              cpx<double>* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= nv) return;
+// out[j] = sum_b part[b][j]: one block per output, fixed-order strided sums then a
+// fixed-order tree (bitwise reproducible)
+__global__ __launch_bounds__(256) void k_reduce_part(const cpx<double>* __restrict__ part, int nb,
+                                                     cpx<double>* __restrict__ out) {
+  __shared__ cpx<double> sh[256];
+  const int j = blockIdx.x, t = threadIdx.x;
   cpx<double> s = cmk(0.0, 0.0);
-  for (int b = 0; b < nb; ++b) s = s + part[(size_t)b * KMAX + j];
-  out[j] = s;
+  for (int b = t; b < nb; b += 256) s = s + part[(size_t)b * KMAX + j];
+  sh[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = sh[t] + sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[j] = sh[0];
 }
 
 hipError_t cgs_pass(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
@@ -951,7 +1021,7 @@ hipError_t cgs_pass(int mode, const cpx<double>* V, size_t ldv, int nv, const cp
   else
     k_cgs<2><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
   VH_LAUNCH_CHECK();
-  k_reduce_part<<<1, 128, 0, s>>>(part, nb, mode == 2 ? 1 : nv, out);
+  k_reduce_part<<<mode == 2 ? 1 : nv, 256, 0, s>>>(part, nb, out);
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }

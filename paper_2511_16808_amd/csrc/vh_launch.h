@@ -36,7 +36,8 @@ hipError_t check_media(long long N, const double* kappa, const double* gamma, in
                        hipStream_t s);
 hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, int px,
                    const void* x, int py, const void* b, void* y, hipStream_t s);
-hipError_t vanka_patch(int dim, int patch, Grid g, int prec, const void* G, const void* r, void* u,
+// form: 0 = per-patch Full (Np*Np entries), 1 = per-patch point, 2 = assembled 5^dim box
+hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const void* r, void* u,
                        bool zero, hipStream_t s);
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
                        int prec, void* G, hipStream_t s);

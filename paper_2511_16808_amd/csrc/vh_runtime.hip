@@ -81,10 +81,40 @@ struct vh_handle {
   double* hstat = nullptr;  // pinned host copy of K->status
   std::vector<void*> allocs;
   size_t bytes = 0;
+  // optional event timing (vh_options.timing): pairs of events with a kind tag
+  // (0 = finest smoothing from u = 0, 1 = finest smoothing u += B r, 2 = V-cycle)
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double t_ms[3] = {0, 0, 0};
+  int t_n[3] = {0, 0, 0};
 
   ~vh_handle() {
     for (void* p : allocs) (void)hipFree(p);
     if (hstat) (void)hipHostFree(hstat);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  // returns the index of a free event pair, or -1 if timing is off / the pool is full
+  int tbegin(int kind) {
+    if (!opt.timing || ev_used >= (int)ev_kind.size()) return -1;
+    const int k = ev_used++;
+    ev_kind[k] = kind;
+    (void)hipEventRecord(ev[2 * k], s);
+    return k;
+  }
+  void tend(int k) {
+    if (k >= 0) (void)hipEventRecord(ev[2 * k + 1], s);
+  }
+  // call only after the stream has been synchronised
+  void tflush() {
+    for (int k = 0; k < ev_used; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
+        t_ms[ev_kind[k]] += ms;
+        t_n[ev_kind[k]] += 1;
+      }
+    }
+    ev_used = 0;
   }
   vh_status alloc(void** p, size_t bytes_) {
     *p = nullptr;
@@ -216,12 +246,11 @@ size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N *
 
 // ---------------------------------------------------------------- V-cycle
 vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
-  if (hd->opt.smoother == VH_SMOOTHER_ASSEMBLED) {
-    VH_HIP(stencil(hd->dim, BOX2, Lv.g, zero ? OP_APPLY : OP_ADD, hd->prec, Lv.B, hd->prec, r,
-                   hd->prec, nullptr, u, hd->s));
-  } else {
-    VH_HIP(vanka_patch(hd->dim, hd->patch, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
-  }
+  const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(zero ? 0 : 1) : -1;
+  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2
+                   : (hd->patch == VH_PATCH_FULL ? 0 : 1);
+  VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
+  hd->tend(tk);
   return VH_OK;
 }
 
@@ -267,13 +296,17 @@ vh_status precondition(vh_handle* hd, const cpx<double>* v, void* z) {
     VH_HIP(convert(v, PREC_F64, L0.q, hd->prec, (size_t)L0.g.N, hd->s));
     q = L0.q;
   }
-  return vcycle(hd, 0, q, z);
+  const int tk = hd->tbegin(2);
+  VH_TRY(vcycle(hd, 0, q, z));
+  hd->tend(tk);
+  return VH_OK;
 }
 
 vh_status read_status(vh_handle* hd) {
   VH_HIP(hipMemcpyAsync(hd->hstat, hd->K->status, 4 * sizeof(double), hipMemcpyDeviceToHost,
                         hd->s));
   VH_HIP(hipStreamSynchronize(hd->s));
+  hd->tflush();
   return VH_OK;
 }
 
@@ -303,7 +336,10 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
   double est = 1.0;
   if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(VH_EBREAKDOWN, "non-finite right-hand side");
   if (bnorm == 0.0) {
-    if (st) *st = vh_solve_stats{0, 0, 1, 0.0, 0.0, 0.0};
+    if (st) {
+      *st = vh_solve_stats{};
+      st->converged = 1;
+    }
     return VH_OK;
   }
   while (true) {
@@ -473,6 +509,11 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   VH_TRY(hd->alloc((void**)&hd->K, sizeof(KrylovDev)));
   VH_HIP(hipMemsetAsync(hd->K, 0, sizeof(KrylovDev), s));
   VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
+  if (o.timing) {
+    hd->ev.assign(128, nullptr);
+    hd->ev_kind.assign(64, 0);
+    for (auto& e : hd->ev) VH_HIP(hipEventCreate(&e));
+  }
   VH_HIP(hipStreamSynchronize(s));
   return VH_OK;
 }
@@ -568,6 +609,11 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
     VH_HIP(hipEventCreate(&e1));
     VH_HIP(hipEventRecord(e0, hd->s));
     vh_solve_stats st{};
+    for (int k = 0; k < 3; ++k) {
+      hd->t_ms[k] = 0;
+      hd->t_n[k] = 0;
+    }
+    hd->ev_used = 0;
     vh_status r = fgmres_one(hd, (const cpx<double>*)q + sidx * N, (cpx<double>*)u + sidx * N,
                              tol, &st);
     (void)hipEventRecord(e1, hd->s);
@@ -577,6 +623,13 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     st.solve_ms = ms;
+    hd->tflush();
+    st.smooth0_launches = hd->t_n[0];
+    st.smooth0_ms = hd->t_ms[0];
+    st.smooth1_launches = hd->t_n[1];
+    st.smooth1_ms = hd->t_ms[1];
+    st.vcycles = hd->t_n[2];
+    st.vcycle_ms = hd->t_ms[2];
     if (stats) stats[sidx] = st;
     if (r != VH_OK && r != VH_ENOCONV) return r;
     if (r == VH_ENOCONV) worst = VH_ENOCONV;

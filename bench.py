@@ -12,6 +12,7 @@ Prints ONE JSON line.  Workloads (synthetic media, seeded):
   c1  2D 129^2 nodes, homogeneous, 4 levels, complex128 (the oracle solves it in seconds)
   c2  2D 1025^2 layered medium, 7 levels, complex128
   c3  3D 257^3 geophysical medium, 6 levels, complex64 preconditioner / complex128 FGMRES
+  c4  2D 513^2 layered medium, 64 sources sharing one hierarchy and every V-cycle sweep
 """
 import argparse
 import json
@@ -37,6 +38,13 @@ WORKLOADS = {
                     "7-level V(1,1), Full 3x3 Vanka, FGMRES(20), complex128",
                dim=2, n=(1025, 1025), levels=7, alpha=0.1, medium="layered_2d", seed=2,
                precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6],
+               sample=dict(n=(1025, 1025), levels=7)),
+    "c4": dict(desc="2D layered 513x513 nodes (512^2 cells), recipe of c2 with seed 4, 64 point "
+                    "sources at row 2, columns 4+8k; one shared hierarchy, shift 0.2, 6-level "
+                    "V(1,1), Full 3x3 Vanka, sources batched through every V-cycle sweep, "
+                    "complex64 preconditioner, FGMRES(20) per source in complex128",
+               dim=2, n=(513, 513), levels=6, alpha=0.2, medium="layered_2d", seed=4,
+               precision=1, restart=20, damping=[0.94, 1.2, 0.4, 0.6], nsrc=64, batch=1,
                sample=dict(n=(513, 513), levels=6)),
     "c3": dict(desc="3D geophysical 257^3 nodes (256^3 cells), v in [1.5,4.5] km/s with dipping "
                     "layers and a 5 km/s ellipsoid, 10 ppw, gamma=0.01*omega, ABC, shift 0.5, "
@@ -44,7 +52,7 @@ WORKLOADS = {
                     "FGMRES(30) in complex128",
                dim=3, n=(257, 257, 257), levels=6, alpha=0.5, medium="geophysical_3d", seed=3,
                precision=1, restart=30, damping=[1.08, 0.9, 0.6, 0.6],
-               sample=dict(n=(33, 33, 33), levels=3)),
+               sample=dict(n=(65, 65, 65), levels=4)),
 }
 DEFAULT_WORKLOAD = "c3"
 
@@ -62,7 +70,14 @@ def make_medium(w, n=None):
     h = 1.0 / (n[0] - 1)
     omega = synth.omega_for_ppw(h, 10.0, float(kappa.max()))
     gamma = 0.01 * omega * np.ones_like(kappa)
-    q = synth.point_source(n).ravel()
+    nsrc = w.get("nsrc", 1)
+    if nsrc == 1:
+        q = synth.point_source(n).ravel()
+    else:
+        q = np.zeros((nsrc, int(np.prod(n))), dtype=complex)
+        for k in range(nsrc):
+            q[k] = synth.point_source(n, (4 + 8 * k, 2)).ravel()
+        q = q.ravel()
     return n, h, omega, kappa, gamma, q
 
 
@@ -88,7 +103,8 @@ def vcycle_bytes(levels_info, dim, esz, smoother_entries):
 def cpu_baseline(w, gpu_iterations):
     """Times the FP64 oracle (single thread) on a reduced grid of the same recipe:
     setup + 2 FGMRES iterations, scaled linearly in nodes to the full grid and to the
-    GPU's iteration count."""
+    GPU's iteration count (summed over the sources: one setup, then one solve per
+    source)."""
     sample = w["sample"]
     code = f"""
 import json, sys, time
@@ -97,7 +113,7 @@ import numpy as np
 from bench import WORKLOADS, make_medium
 from oracle import discretization as D, cycle, krylov
 w = WORKLOADS[{w['key']!r}]
-n, h, omega, kappa, gamma, q = make_medium(w, {tuple(sample['n'])!r})
+n, h, omega, kappa, gamma, q = make_medium(dict(w, nsrc=1), {tuple(sample['n'])!r})
 t0 = time.perf_counter()
 ops = D.fd2_operator(n, h, omega, kappa, gamma, w['alpha'])
 mg = cycle.Multigrid(ops['Hs'], n, {sample['levels']}, 'levdep' if len(n) == 2 else 'linear',
@@ -120,13 +136,15 @@ print(json.dumps(dict(setup_s=t1 - t0, iter_s=(t2 - t1) / its, N=int(np.prod(n))
     for k in w["n"]:
         Nfull *= k
     scale = Nfull / r["N"]
+    nsrc = w.get("nsrc", 1)
     t_solve = scale * (r["setup_s"] + gpu_iterations * r["iter_s"])
     return {
-        "value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "value": nsrc / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle setup + 2 FGMRES iterations on the same recipe at "
                    f"{'x'.join(map(str, sample['n']))} nodes ({sample['levels']} levels), "
                    f"setup {r['setup_s']:.1f}s, {r['iter_s']:.2f}s/iteration, scaled x{scale:.1f} "
-                   f"in nodes and to {gpu_iterations} iterations; single thread; "
+                   f"in nodes and to {gpu_iterations} iterations"
+                   f"{' summed over ' + str(nsrc) + ' sources' if nsrc > 1 else ''}; single thread; "
                    f"{wall:.1f}s of CPU work"),
     }
 
@@ -139,6 +157,10 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother", default="patch", choices=["patch", "assembled"])
+    ap.add_argument("--batch", type=int, default=None, choices=[0, 1],
+                    help="override: sources one after another (0) or sharing each sweep (1)")
+    ap.add_argument("--precision", default=None, choices=["c128", "c64"],
+                    help="override the preconditioner precision")
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per launch of the dominant kernel")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -175,20 +197,23 @@ def main():
     qt = torch.tensor(q, dtype=torch.complex128, device=dev)
     ut = torch.empty_like(qt)
     smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
-    opt = B.make_options(precision=w["precision"], restart=w["restart"], damping=w["damping"],
+    nsrc = w.get("nsrc", 1)
+    batch = w.get("batch", 0) if args.batch is None else args.batch
+    precision = w["precision"] if args.precision is None else {"c128": 0, "c64": 1}[args.precision]
+    opt = B.make_options(precision=precision, restart=w["restart"], damping=w["damping"],
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR,
-                         smoother=smoother, stream=stream, timing=1)
+                         smoother=smoother, stream=stream, timing=1, batch=batch)
     torch.cuda.synchronize()
 
     def step():
         t0 = time.perf_counter()
         hd = B.vh_setup(dim, n, h, omega, kt, gt, w["alpha"], w["levels"], B.VH_PATCH_FULL, opt)
         t1 = time.perf_counter()
-        st, stats = B.vh_solve(hd, qt, 1, 1e-6, ut)
+        st, stats = B.vh_solve(hd, qt, nsrc, 1e-6, ut)
         info = [B.vh_get_level_info(hd, l) for l in range(w["levels"])]
         B.vh_destroy(hd)
         t2 = time.perf_counter()
-        return dict(status=st, stats=stats[0], setup_ms=1e3 * (t1 - t0),
+        return dict(status=st, stats=stats[0], all_stats=stats, setup_ms=1e3 * (t1 - t0),
                     step_ms=1e3 * (t2 - t0), info=info)
 
     for _ in range(args.warmup):
@@ -201,13 +226,18 @@ def main():
 
     last = runs[-1]
     st = last["stats"]
-    esz = 16 if w["precision"] == 0 else 8
+    esz = 16 if precision == 0 else 8
+    its_all = [x["iterations"] for x in last["all_stats"]]
+    S = 1
+    while S < nsrc:
+        S *= 2
+    width = S if batch else 1   # sources per sweep launch
     info = last["info"]
     E = [i["smoother_entries"] for i in info]
     # dominant kernel: finest-level additive-Vanka sweep u += B r
     n_l = sum(r["stats"]["smooth1_launches"] for r in runs)
     ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
-    bytes_per_launch = N * esz * (E[0] + 3)
+    bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
@@ -218,7 +248,7 @@ def main():
     lat = np.array([r["step_ms"] for r in runs])
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": nsrc * args.steps / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -227,13 +257,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if w["precision"] == 0 else "c64+c128",
+        "dtype": "c128" if precision == 0 else "c64+c128",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "nodes": N, "levels": w["levels"],
-                   "smoother": args.smoother, "sources": 1},
-        "iterations": st["iterations"],
-        "converged": bool(st["converged"]) and all(r["status"] == 0 for r in runs),
-        "true_relres": st["relres"],
+                   "smoother": args.smoother, "sources": nsrc, "batched": bool(batch)},
+        "iterations": st["iterations"] if nsrc == 1 else
+        {"mean": float(np.mean(its_all)), "min": int(min(its_all)), "max": int(max(its_all))},
+        "converged": all(x["converged"] for x in last["all_stats"]) and
+        all(r["status"] == 0 for r in runs),
+        "true_relres": max(x["relres"] for x in last["all_stats"]),
         "setup_ms": float(np.median([r["setup_ms"] for r in runs])),
         "solve_ms": float(np.median([r["stats"]["solve_ms"] for r in runs])),
         "p50_ms": float(np.percentile(lat, 50)),
@@ -243,7 +275,8 @@ def main():
         "vcycle_algorithmic_bytes": vc_b,
         "roofline": {
             "bound": "hbm",
-            "kernel": "finest-level additive Vanka sweep u += B r (k_vanka_patch)",
+            "kernel": ("finest-level additive Vanka sweep u += B r, "
+                       + ("k_vanka_sweep" if width == 1 else f"kb_sweep over {width} sources")),
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -255,7 +288,7 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, st["iterations"])
+        out["cpu_baseline"] = cpu_baseline(w, int(sum(its_all)))
     print(json.dumps(out))
 
 

@@ -86,6 +86,10 @@ typedef struct vh_options {
     int timing;             /* 1: vh_solve brackets every V-cycle and every finest-level
                                smoothing launch with HIP events on `stream` and reports the
                                summed durations in vh_solve_stats; default 0              */
+    int batch;              /* 0: vh_solve handles the sources one after another (default);
+                               1: in groups of up to 64 sources that share every V-cycle
+                               sweep (each coefficient and patch-inverse entry is read once
+                               per group), each source with its own FP64 FGMRES state    */
 } vh_options;
 
 typedef struct vh_solve_stats {

@@ -1,0 +1,635 @@
+// vh_batch.hip -- multi-source (batched right-hand side) kernels.
+//
+// Many sources share one hierarchy (the paper's many-right-hand-side remark after
+// its 3D timings: the setup is amortised over all sources).  Vectors of a batch of
+// S sources (S a power of two <= 64) are stored node-major, source-fastest: element
+// (node i, source s) at i*S + s.  A wavefront covers 64/S nodes x S sources, so every
+// operator coefficient and every patch-inverse entry is loaded once per node and
+// broadcast to the S lanes of that node, and neighbour reads are contiguous runs of S
+// sources.  Krylov quantities are per source and reduced across the nodes of a block
+// with lane shuffles (stride S) and a fixed-order tree: a source's result does not
+// depend on the values of the other sources, only (through the summation order) on
+// the batch width S.
+#include "vh_launch.h"
+
+namespace vh {
+
+namespace {
+
+__device__ __forceinline__ void decode_b(unsigned i, const Grid& g, int& x, int& y, int& z) {
+  x = (int)(i % (unsigned)g.nx);
+  const unsigned t = i / (unsigned)g.nx;
+  y = (int)(t % (unsigned)g.ny);
+  z = (int)(t / (unsigned)g.ny);
+}
+__device__ __forceinline__ bool inside_b(const Grid& g, int x, int y, int z) {
+  return (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
+}
+__device__ __forceinline__ long long lin_b(const Grid& g, int x, int y, int z) {
+  return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+__device__ __forceinline__ long long linp_b(const Grid& g, int x, int y, int z) {
+  return (long long)x + (long long)g.nxp * ((long long)y + (long long)g.ny * z);
+}
+inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define VHB_CHECK()                             \
+  do {                                          \
+    hipError_t e__ = hipGetLastError();         \
+    if (e__ != hipSuccess) return e__;          \
+  } while (0)
+
+// (node, source) of this thread; log2 of S passed as `ls`
+__device__ __forceinline__ bool thread_ns(const Grid& g, int ls, unsigned& node, int& s) {
+  const unsigned long long t =
+      (unsigned long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  node = (unsigned)(t >> ls);
+  s = (int)(t & ((1u << ls) - 1u));
+  return node < (unsigned long long)g.N;
+}
+
+}  // namespace
+
+// q[s][N] (c128) -> Q[N][S] (c128, sources >= nsrc zero); and back
+__global__ __launch_bounds__(256) void kb_gather(long long N, int S, int nsrc,
+                                                 const cpx<double>* __restrict__ q,
+                                                 cpx<double>* __restrict__ Q) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * S) return;
+  const long long i = t / S;
+  const int s = (int)(t % S);
+  Q[t] = s < nsrc ? q[(size_t)s * N + i] : cmk(0.0, 0.0);
+}
+__global__ __launch_bounds__(256) void kb_scatter(long long N, int S, int nsrc,
+                                                  const cpx<double>* __restrict__ X,
+                                                  cpx<double>* __restrict__ u) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * nsrc) return;
+  const int s = (int)(t / N);
+  const long long i = t % N;
+  u[t] = X[i * S + s];
+}
+hipError_t batch_gather(long long N, int S, int nsrc, const cpx<double>* q, cpx<double>* Q,
+                        hipStream_t st) {
+  kb_gather<<<nblk(N * S, 256), 256, 0, st>>>(N, S, nsrc, q, Q);
+  VHB_CHECK();
+  return hipSuccess;
+}
+hipError_t batch_scatter(long long N, int S, int nsrc, const cpx<double>* X, cpx<double>* u,
+                         hipStream_t st) {
+  kb_scatter<<<nblk(N * nsrc, 256), 256, 0, st>>>(N, S, nsrc, X, u);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ stencil sweep, batched
+template <int DIM, int SHAPE, int MODE, class TC, class TX, class TY>
+__global__ __launch_bounds__(256) void kb_stencil(Grid g, int ls, const cpx<TC>* __restrict__ A,
+                                                  const cpx<TX>* __restrict__ x,
+                                                  const cpx<TY>* __restrict__ b,
+                                                  cpx<TY>* __restrict__ y) {
+  unsigned i;
+  int s;
+  if (!thread_ns(g, ls, i, s)) return;
+  int cx, cy, cz;
+  decode_b(i, g, cx, cy, cz);
+  constexpr int K = shape_K<DIM, SHAPE>();
+  const size_t N = (size_t)g.N;
+  const int S = 1 << ls;
+  cpx<TC> acc = cmk<TC>(0, 0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+              dz = shape_off<DIM, SHAPE>(k, 2);
+    if (inside_b(g, cx + dx, cy + dy, cz + dz)) {
+      const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+      acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[(size_t)j * S + s]), acc);
+    }
+  }
+  const size_t o = (size_t)i * S + s;
+  if (MODE == OP_APPLY)
+    y[o] = ccast<TY>(acc);
+  else if (MODE == OP_RESID)
+    y[o] = ccast<TY>(ccast<TC>(b[o]) - acc);
+  else
+    y[o] = ccast<TY>(ccast<TC>(y[o]) + acc);
+}
+
+template <int DIM, int SHAPE, class TC, class TX, class TY>
+static hipError_t bstencil_t(Grid g, int ls, int mode, const void* A, const void* x, const void* b,
+                             void* y, hipStream_t st) {
+  const unsigned nb = nblk(g.N << ls, 256);
+  auto Ap = (const cpx<TC>*)A;
+  auto xp = (const cpx<TX>*)x;
+  auto bp = (const cpx<TY>*)b;
+  auto yp = (cpx<TY>*)y;
+  if (mode == OP_APPLY)
+    kb_stencil<DIM, SHAPE, OP_APPLY, TC, TX, TY><<<nb, 256, 0, st>>>(g, ls, Ap, xp, bp, yp);
+  else if (mode == OP_RESID)
+    kb_stencil<DIM, SHAPE, OP_RESID, TC, TX, TY><<<nb, 256, 0, st>>>(g, ls, Ap, xp, bp, yp);
+  else
+    kb_stencil<DIM, SHAPE, OP_ADD, TC, TX, TY><<<nb, 256, 0, st>>>(g, ls, Ap, xp, bp, yp);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+template <int DIM, int SHAPE>
+static hipError_t bstencil_p(Grid g, int ls, int mode, int pc, const void* A, int px,
+                             const void* x, int py, const void* b, void* y, hipStream_t st) {
+  if (pc == PREC_F64 && px == PREC_F64 && py == PREC_F64)
+    return bstencil_t<DIM, SHAPE, double, double, double>(g, ls, mode, A, x, b, y, st);
+  if (pc == PREC_F32 && px == PREC_F32 && py == PREC_F32)
+    return bstencil_t<DIM, SHAPE, float, float, float>(g, ls, mode, A, x, b, y, st);
+  if (pc == PREC_F64 && px == PREC_F32 && py == PREC_F64)
+    return bstencil_t<DIM, SHAPE, double, float, double>(g, ls, mode, A, x, b, y, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,
+                         int px, const void* x, int py, const void* b, void* y, hipStream_t st) {
+  if (dim == 2) {
+    if (shape == CROSS) return bstencil_p<2, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == BOX1) return bstencil_p<2, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == BOX2) return bstencil_p<2, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st);
+  } else {
+    if (shape == CROSS) return bstencil_p<3, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == BOX1) return bstencil_p<3, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == BOX2) return bstencil_p<3, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ additive Vanka, batched
+// u[i][s] (+)= sum_e G[e][i] r[i + d_e][s]: the same gather as the single-source sweep;
+// each entry G[e][i] is loaded once per node and used for all S sources.
+template <int DIM, int FORM>
+__host__ __device__ constexpr int bsm_entries() {
+  return FORM == 2 ? shape_K<DIM, BOX2>() : patch_Np<DIM, FORM>() * patch_Np<DIM, FORM>();
+}
+template <int DIM, int FORM>
+__host__ __device__ constexpr int bsm_off(int e, int c) {
+  return FORM == 2 ? shape_off<DIM, BOX2>(e, c)
+                   : patch_off<DIM, FORM>(e % patch_Np<DIM, FORM>(), c) -
+                         patch_off<DIM, FORM>(e / patch_Np<DIM, FORM>(), c);
+}
+
+template <int DIM, int FORM, bool ZERO, class T>
+__global__ __launch_bounds__(256) void kb_sweep(Grid g, int ls, const cpx<T>* __restrict__ G,
+                                                const cpx<T>* __restrict__ r,
+                                                cpx<T>* __restrict__ u) {
+  unsigned i;
+  int s;
+  if (!thread_ns(g, ls, i, s)) return;
+  int cx, cy, cz;
+  decode_b(i, g, cx, cy, cz);
+  const long long ip = linp_b(g, cx, cy, cz);
+  const size_t Np = (size_t)g.Np;
+  const int S = 1 << ls;
+  constexpr int E = bsm_entries<DIM, FORM>();
+  constexpr int UNR = (DIM == 3 && FORM == 0) ? 27 : E;
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll 1
+  for (int e0 = 0; e0 < E; e0 += UNR) {
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+      const int e = e0 + q;
+      const int dx = bsm_off<DIM, FORM>(e, 0), dy = bsm_off<DIM, FORM>(e, 1),
+                dz = bsm_off<DIM, FORM>(e, 2);
+      if (inside_b(g, cx + dx, cy + dy, cz + dz)) {
+        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+        acc = cfma(G[(size_t)e * Np + ip], r[(size_t)j * S + s], acc);
+      }
+    }
+  }
+  const size_t o = (size_t)i * S + s;
+  u[o] = ZERO ? acc : (u[o] + acc);
+}
+
+// 2D: one block = one row segment of 256/S nodes x S sources; the residual of the
+// segment with a halo of 2 (all S sources) is staged in LDS once, so the Np*Np
+// neighbour reads of every (node, source) pair come from LDS.
+template <int FORM, bool ZERO, class T>
+__global__ __launch_bounds__(256) void kb_sweep2d(Grid g, int ls, const cpx<T>* __restrict__ G,
+                                                  const cpx<T>* __restrict__ r,
+                                                  cpx<T>* __restrict__ u) {
+  extern __shared__ unsigned char smem[];
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);
+  const int S = 1 << ls, NB = 256 >> ls, SX = NB + 4;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (g.nx + NB - 1) / NB;
+  const int x0 = (int)(b % (unsigned)nbx) * NB, y0 = (int)(b / (unsigned)nbx);
+  for (int e = threadIdx.x; e < SX * 5 * S; e += 256) {
+    const int pos = e >> ls, s = e & (S - 1);
+    const int gx = x0 + pos % SX - 2, gy = y0 + pos / SX - 2;
+    tile[e] = inside_b(g, gx, gy, 0) ? r[(size_t)lin_b(g, gx, gy, 0) * S + s] : cmk<T>(0, 0);
+  }
+  __syncthreads();
+  const int ns = threadIdx.x >> ls, s = threadIdx.x & (S - 1);
+  const int x = x0 + ns, y = y0;
+  if (x >= g.nx) return;
+  const long long i = lin_b(g, x, y, 0), ip = linp_b(g, x, y, 0);
+  const size_t Np = (size_t)g.Np;
+  constexpr int E = bsm_entries<2, FORM>();
+  const cpx<T>* t0 = tile + ((size_t)(ns + 2) + (size_t)SX * 2) * S + s;
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
+    acc = cfma(G[(size_t)e * Np + ip], t0[(dx + SX * dy) * S], acc);
+  }
+  const size_t o = (size_t)i * S + s;
+  u[o] = ZERO ? acc : (u[o] + acc);
+}
+
+template <int DIM, int FORM, class T>
+static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u, bool zero,
+                           hipStream_t st) {
+  if (DIM == 2) {
+    const int NB = 256 >> ls;
+    const unsigned nb = (unsigned)(((g.nx + NB - 1) / NB) * g.ny);
+    const size_t lds = (size_t)(NB + 4) * 5 * ((size_t)1 << ls) * sizeof(cpx<T>);
+    if (zero)
+      kb_sweep2d<FORM, true, T><<<nb, 256, lds, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                      (cpx<T>*)u);
+    else
+      kb_sweep2d<FORM, false, T><<<nb, 256, lds, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                       (cpx<T>*)u);
+    VHB_CHECK();
+    return hipSuccess;
+  }
+  const unsigned nb = nblk(g.N << ls, 256);
+  if (zero)
+    kb_sweep<DIM, FORM, true, T><<<nb, 256, 0, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                     (cpx<T>*)u);
+  else
+    kb_sweep<DIM, FORM, false, T><<<nb, 256, 0, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                      (cpx<T>*)u);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* G, const void* r,
+                       void* u, bool zero, hipStream_t st) {
+#define VHB_SW(D, F)                                                          \
+  if (dim == D && form == F)                                                  \
+    return prec == PREC_F64 ? bsweep_t<D, F, double>(g, ls, G, r, u, zero, st) \
+                            : bsweep_t<D, F, float>(g, ls, G, r, u, zero, st);
+  VHB_SW(2, 0) VHB_SW(3, 0) VHB_SW(2, 1) VHB_SW(3, 1) VHB_SW(2, 2) VHB_SW(3, 2)
+#undef VHB_SW
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ transfers, batched
+template <int DIM, int RF, class T>
+__global__ __launch_bounds__(256) void kb_restrict(Grid gf, Grid gc, int ls,
+                                                   const cpx<T>* __restrict__ r,
+                                                   cpx<T>* __restrict__ rc) {
+  unsigned I;
+  int s;
+  if (!thread_ns(gc, ls, I, s)) return;
+  int Ix, Iy, Iz;
+  decode_b(I, gc, Ix, Iy, Iz);
+  const int S = 1 << ls;
+  constexpr int RR = fam_radius(RF), RW = 2 * RR + 1, NT = ipow(RW, DIM);
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tx = t % RW - RR, ty = (t / RW) % RW - RR, tz = (DIM == 3) ? t / (RW * RW) - RR : 0;
+    const int fx = 2 * Ix + tx, fy = 2 * Iy + ty, fz = 2 * Iz + tz;
+    if (inside_b(gf, fx, fy, fz)) {
+      const T w = (T)(fam_r(RF, tx) * fam_r(RF, ty) * (DIM == 3 ? fam_r(RF, tz) : 1.0));
+      acc = cfma(cmk<T>(w, 0), r[(size_t)lin_b(gf, fx, fy, fz) * S + s], acc);
+    }
+  }
+  rc[(size_t)I * S + s] = acc;
+}
+
+template <int DIM, int PF, class T>
+__global__ __launch_bounds__(256) void kb_prolong_add(Grid gf, Grid gc, int ls,
+                                                      const cpx<T>* __restrict__ e,
+                                                      cpx<T>* __restrict__ u) {
+  unsigned i;
+  int s;
+  if (!thread_ns(gf, ls, i, s)) return;
+  int c[3];
+  decode_b(i, gf, c[0], c[1], c[2]);
+  const int S = 1 << ls;
+  int J[3][3];
+  T w[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int J0 = c[d] >> 1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      J[d][q] = J0 + q - 1;
+      w[d][q] = (T)fam_p(PF, c[d] - 2 * (J0 + q - 1));
+    }
+  }
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int qz = 0; qz < (DIM == 3 ? 3 : 1); ++qz)
+#pragma unroll
+    for (int qy = 0; qy < 3; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx) {
+        const int Jx = J[0][qx], Jy = J[1][qy], Jz = (DIM == 3) ? J[2][qz] : 0;
+        const T wt = w[0][qx] * w[1][qy] * (DIM == 3 ? w[2][qz] : (T)1);
+        if (wt != (T)0 && inside_b(gc, Jx, Jy, Jz))
+          acc = cfma(cmk<T>(wt, 0), e[(size_t)lin_b(gc, Jx, Jy, Jz) * S + s], acc);
+      }
+  const size_t o = (size_t)i * S + s;
+  u[o] = u[o] + acc;
+}
+
+hipError_t batch_restrict(int dim, int rf, Grid gf, Grid gc, int ls, int prec, const void* r,
+                          void* rc, hipStream_t st) {
+  const unsigned nb = nblk(gc.N << ls, 256);
+#define VHB_RS(D, R, T)                                                                          \
+  if (dim == D && rf == R) {                                                                     \
+    kb_restrict<D, R, T><<<nb, 256, 0, st>>>(gf, gc, ls, (const cpx<T>*)r, (cpx<T>*)rc);          \
+    VHB_CHECK();                                                                                 \
+    return hipSuccess;                                                                           \
+  }
+  if (prec == PREC_F64) {
+    VHB_RS(2, FAM_LINEAR, double) VHB_RS(2, FAM_CUBIC, double)
+    VHB_RS(3, FAM_LINEAR, double) VHB_RS(3, FAM_CUBIC, double)
+  } else {
+    VHB_RS(2, FAM_LINEAR, float) VHB_RS(2, FAM_CUBIC, float)
+    VHB_RS(3, FAM_LINEAR, float) VHB_RS(3, FAM_CUBIC, float)
+  }
+#undef VHB_RS
+  return hipErrorInvalidValue;
+}
+
+hipError_t batch_prolong_add(int dim, int pf, Grid gf, Grid gc, int ls, int prec, const void* e,
+                             void* u, hipStream_t st) {
+  const unsigned nb = nblk(gf.N << ls, 256);
+#define VHB_PA(D, P, T)                                                                          \
+  if (dim == D && pf == P) {                                                                     \
+    kb_prolong_add<D, P, T><<<nb, 256, 0, st>>>(gf, gc, ls, (const cpx<T>*)e, (cpx<T>*)u);        \
+    VHB_CHECK();                                                                                 \
+    return hipSuccess;                                                                           \
+  }
+  if (prec == PREC_F64) {
+    VHB_PA(2, FAM_LINEAR, double) VHB_PA(2, FAM_CUBIC, double)
+    VHB_PA(3, FAM_LINEAR, double) VHB_PA(3, FAM_CUBIC, double)
+  } else {
+    VHB_PA(2, FAM_LINEAR, float) VHB_PA(2, FAM_CUBIC, float)
+    VHB_PA(3, FAM_LINEAR, float) VHB_PA(3, FAM_CUBIC, float)
+  }
+#undef VHB_PA
+  return hipErrorInvalidValue;
+}
+
+// Y[row][s] = sum_j D[row][j] X[j][s], D the FP64 coarsest inverse (one thread per (row, s))
+template <class T>
+__global__ __launch_bounds__(256) void kb_dense(int n, int ls, const cpx<double>* __restrict__ D,
+                                                const cpx<T>* __restrict__ X,
+                                                cpx<T>* __restrict__ Y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ((long long)n << ls)) return;
+  const int row = (int)(t >> ls), s = (int)(t & ((1 << ls) - 1));
+  const int S = 1 << ls;
+  cpx<double> acc = cmk(0.0, 0.0);
+  for (int j = 0; j < n; ++j)
+    acc = cfma(D[(size_t)row * n + j], ccast<double>(X[(size_t)j * S + s]), acc);
+  Y[t] = ccast<T>(acc);
+}
+
+hipError_t batch_dense(int n, int ls, const cpx<double>* D, int prec, const void* X, void* Y,
+                       hipStream_t st) {
+  const unsigned nb = nblk((long long)n << ls, 256);
+  if (prec == PREC_F64)
+    kb_dense<double><<<nb, 256, 0, st>>>(n, ls, D, (const cpx<double>*)X, (cpx<double>*)Y);
+  else
+    kb_dense<float><<<nb, 256, 0, st>>>(n, ls, D, (const cpx<float>*)X, (cpx<float>*)Y);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ Krylov, batched (FP64)
+// Block-partial per-source multi-dots over a contiguous chunk of nodes:
+//   mode 0: part[b][j][s] = sum_i conj(V_j[i][s]) w[i][s]
+//   mode 1: w -= sum_j h[j][s] V_j, then the same dots with the updated w
+//   mode 2: w -= sum_j h[j][s] V_j, part[b][0][s] = ||w[., s]||^2
+constexpr int BKMAX = 65;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void kb_cgs(const cpx<double>* __restrict__ V, size_t ldv, int nv,
+                                              const cpx<double>* __restrict__ h,
+                                              cpx<double>* __restrict__ w, long long N, int ls,
+                                              cpx<double>* __restrict__ part) {
+  __shared__ cpx<double> red[4][64];
+  const int S = 1 << ls;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = lane & (S - 1);
+  const int nodes_per_block = 256 >> ls;
+  const int sub = threadIdx.x >> ls;  // node slot within the block
+  const long long per = (N + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = lo + per < N ? lo + per : N;
+  const int nout = (MODE == 2) ? 1 : nv;
+  for (int j0 = 0; j0 < nout; j0 += 8) {
+    cpx<double> acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = cmk(0.0, 0.0);
+    for (long long i = lo + sub; i < hi; i += nodes_per_block) {
+      const size_t o = (size_t)i * S + s;
+      cpx<double> wi = w[o];
+      if (MODE != 0 && j0 == 0) {
+        for (int j = 0; j < nv; ++j) wi = wi - h[(size_t)j * 64 + s] * V[(size_t)j * ldv + o];
+        w[o] = wi;
+      }
+      if (MODE == 2) {
+        acc[0].re += wi.re * wi.re + wi.im * wi.im;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (j0 + q < nv) acc[q] = cfma_conj(V[(size_t)(j0 + q) * ldv + o], wi, acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (j0 + q >= nout) break;
+      cpx<double> v = acc[q];
+      // lanes with the same source: stride S within the wavefront
+      for (int o = 32; o >= S; o >>= 1) {
+        v.re += __shfl_down(v.re, o, 64);
+        v.im += __shfl_down(v.im, o, 64);
+      }
+      __syncthreads();
+      if (lane < S) red[wv][lane] = v;
+      __syncthreads();
+      if (threadIdx.x < S) {
+        cpx<double> t = red[0][threadIdx.x];
+        for (int k = 1; k < 4; ++k) t = t + red[k][threadIdx.x];
+        part[((size_t)blockIdx.x * BKMAX + j0 + q) * 64 + threadIdx.x] = t;
+      }
+    }
+    if (MODE != 0) __syncthreads();
+  }
+}
+
+// out[j][s] = sum_b part[b][j][s]: block per j, (256/S) block groups x S sources,
+// strided then tree reduction, fixed order
+__global__ __launch_bounds__(256) void kb_reduce(const cpx<double>* __restrict__ part, int nb,
+                                                 int ls, cpx<double>* __restrict__ out) {
+  __shared__ cpx<double> sh[256];
+  const int S = 1 << ls;
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int s = t & (S - 1), grp = t >> ls, ngrp = 256 >> ls;
+  cpx<double> acc = cmk(0.0, 0.0);
+  for (int b = grp; b < nb; b += ngrp) acc = acc + part[((size_t)b * BKMAX + j) * 64 + s];
+  sh[t] = acc;
+  __syncthreads();
+  for (int w = 128; w >= S; w >>= 1) {
+    if (t < w) sh[t] = sh[t] + sh[t + w];
+    __syncthreads();
+  }
+  if (t < S) out[(size_t)j * 64 + t] = sh[t];
+}
+
+hipError_t batch_cgs(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                     cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
+                     cpx<double>* out, hipStream_t st) {
+  if (mode == 0)
+    kb_cgs<0><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  else if (mode == 1)
+    kb_cgs<1><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  else
+    kb_cgs<2><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  VHB_CHECK();
+  kb_reduce<<<mode == 2 ? 1 : nv, 256, 0, st>>>(part, nb, ls, out);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+// Arnoldi column j for every source (one thread per source): same algebra as the
+// single-source kernel, on the per-source arrays of BatchKrylovDev.
+__global__ void kb_finalize(BatchKrylovDev* __restrict__ K, int j, int S) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  const int ldh = MMAX + 1;
+  auto H = [&](int col, int row) -> cpx<double>& {
+    return K->H[((size_t)col * ldh + row) * 64 + s];
+  };
+  for (int i = 0; i <= j; ++i) H(j, i) = K->h1[i * 64 + s] + K->h2[i * 64 + s];
+  const double nrm = sqrt(K->nrm2[s].re);
+  H(j, j + 1) = cmk(nrm, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const cpx<double> a = H(j, i), b = H(j, i + 1);
+    const double c = K->cs[i * 64 + s];
+    const cpx<double> sn = K->sn[i * 64 + s];
+    H(j, i) = c * a + sn * b;
+    H(j, i + 1) = c * b - cmk(sn.re, -sn.im) * a;
+  }
+  const cpx<double> a = H(j, j);
+  const double b = nrm;
+  double c;
+  cpx<double> sn;
+  const double aa = sqrt(a.re * a.re + a.im * a.im);
+  if (aa == 0.0) {
+    c = 0.0;
+    sn = cmk(1.0, 0.0);
+  } else {
+    const double r = sqrt(aa * aa + b * b);
+    c = aa / r;
+    sn = cmk(a.re / aa * b / r, a.im / aa * b / r);
+  }
+  K->cs[j * 64 + s] = c;
+  K->sn[j * 64 + s] = sn;
+  H(j, j) = c * a + sn * cmk(b, 0.0);
+  H(j, j + 1) = cmk(0.0, 0.0);
+  const cpx<double> gj = K->g[j * 64 + s];
+  K->g[(j + 1) * 64 + s] = cmk(0.0, 0.0) - cmk(sn.re, -sn.im) * gj;
+  K->g[j * 64 + s] = c * gj;
+  const cpx<double> gn = K->g[(j + 1) * 64 + s];
+  const double est = sqrt(gn.re * gn.re + gn.im * gn.im);
+  K->status[s * 4 + 0] = est;
+  K->status[s * 4 + 1] = nrm;
+  K->inv_nrm[s] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  K->status[s * 4 + 2] = (!(nrm == nrm) || !(est == est) || isinf(nrm)) ? 1.0 : 0.0;
+}
+
+__global__ void kb_cycle_init(BatchKrylovDev* __restrict__ K, int m, int S) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  const double beta = sqrt(K->nrm2[s].re);
+  K->g[s] = cmk(beta, 0.0);
+  for (int i = 1; i <= m; ++i) K->g[i * 64 + s] = cmk(0.0, 0.0);
+  K->inv_nrm[s] = beta > 0.0 ? 1.0 / beta : 0.0;
+  K->status[s * 4 + 3] = beta;
+}
+
+// y = R^{-1} g over the first kcols[s] columns of source s (0: nothing to update)
+__global__ void kb_backsolve(BatchKrylovDev* __restrict__ K, int S) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  const int ldh = MMAX + 1;
+  const int k = K->kcols[s];
+  for (int i = k - 1; i >= 0; --i) {
+    cpx<double> acc = K->g[i * 64 + s];
+    for (int q = i + 1; q < k; ++q)
+      acc = acc - K->H[((size_t)q * ldh + i) * 64 + s] * K->y[q * 64 + s];
+    K->y[i * 64 + s] = acc * cinv(K->H[((size_t)i * ldh + i) * 64 + s]);
+  }
+}
+
+// x[i][s] += sum_{j < kcols[s]} y[j][s] Z_j[i][s]
+template <class TZ>
+__global__ __launch_bounds__(256) void kb_update_x(const BatchKrylovDev* __restrict__ K, int kmax,
+                                                   const cpx<TZ>* __restrict__ Z, size_t ldz,
+                                                   cpx<double>* __restrict__ x, long long N,
+                                                   int ls) {
+  const long long t = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= (N << ls)) return;
+  const int s = (int)(t & ((1 << ls) - 1));
+  const int k = K->kcols[s];
+  cpx<double> a = x[t];
+  for (int j = 0; j < kmax; ++j)
+    if (j < k) a = cfma(K->y[j * 64 + s], ccast<double>(Z[(size_t)j * ldz + t]), a);
+  x[t] = a;
+}
+
+// v[i][s] = w[i][s] * inv_nrm[s]
+__global__ __launch_bounds__(256) void kb_scale(const BatchKrylovDev* __restrict__ K,
+                                                const cpx<double>* __restrict__ w,
+                                                cpx<double>* __restrict__ v, long long N, int ls) {
+  const long long t = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= (N << ls)) return;
+  v[t] = K->inv_nrm[t & ((1 << ls) - 1)] * w[t];
+}
+
+hipError_t batch_finalize(BatchKrylovDev* K, int j, int S, hipStream_t st) {
+  kb_finalize<<<1, 64, 0, st>>>(K, j, S);
+  VHB_CHECK();
+  return hipSuccess;
+}
+hipError_t batch_cycle_init(BatchKrylovDev* K, int m, int S, hipStream_t st) {
+  kb_cycle_init<<<1, 64, 0, st>>>(K, m, S);
+  VHB_CHECK();
+  return hipSuccess;
+}
+hipError_t batch_backsolve(BatchKrylovDev* K, int S, hipStream_t st) {
+  kb_backsolve<<<1, 64, 0, st>>>(K, S);
+  VHB_CHECK();
+  return hipSuccess;
+}
+hipError_t batch_update_x(const BatchKrylovDev* K, int kmax, int pz, const void* Z, size_t ldz,
+                          cpx<double>* x, long long N, int ls, hipStream_t st) {
+  const unsigned nb = nblk(N << ls, 256);
+  if (pz == PREC_F64)
+    kb_update_x<double><<<nb, 256, 0, st>>>(K, kmax, (const cpx<double>*)Z, ldz, x, N, ls);
+  else
+    kb_update_x<float><<<nb, 256, 0, st>>>(K, kmax, (const cpx<float>*)Z, ldz, x, N, ls);
+  VHB_CHECK();
+  return hipSuccess;
+}
+hipError_t batch_scale(const BatchKrylovDev* K, const cpx<double>* w, cpx<double>* v, long long N,
+                       int ls, hipStream_t st) {
+  kb_scale<<<nblk(N << ls, 256), 256, 0, st>>>(K, w, v, N, ls);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace vh

@@ -74,8 +74,15 @@ __host__ __device__ __forceinline__ cpx<T> cinv(cpx<T> a) {
 struct Grid {
   int nx, ny, nz;  // nodes per dimension (nz = 1 in 2D)
   int dim;
-  long long N;  // nx*ny*nz
+  long long N;    // nx*ny*nz
+  int nxp;        // x extent of the padded layout used by the smoother arrays
+  long long Np;   // nxp*ny*nz
 };
+
+// Smoother arrays ([entry][node], one row per entry) use rows of nxp = nx rounded up
+// to 32 nodes, so that every 64-node run a wavefront loads starts on a cache-line
+// boundary whatever nx is.
+constexpr int ROW_ALIGN = 32;
 
 __host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int nz) {
   Grid g;
@@ -84,6 +91,8 @@ __host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int 
   g.nz = (dim == 3) ? nz : 1;
   g.dim = dim;
   g.N = (long long)g.nx * g.ny * g.nz;
+  g.nxp = (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+  g.Np = (long long)g.nxp * g.ny * g.nz;
   return g;
 }
 

@@ -22,6 +22,10 @@ __device__ __forceinline__ bool inside(const Grid& g, int x, int y, int z) {
 __device__ __forceinline__ long long lin(const Grid& g, int x, int y, int z) {
   return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
+// linear index in the padded layout of the smoother arrays
+__device__ __forceinline__ long long linp(const Grid& g, int x, int y, int z) {
+  return (long long)x + (long long)g.nxp * ((long long)y + (long long)g.ny * z);
+}
 __device__ __forceinline__ unsigned node_id() {
   return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 }
@@ -305,10 +309,13 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   const int x = x0 + lx, y = y0 + ly, z = z0;
   if (x >= g.nx || y >= g.ny) return;
   const long long i = lin(g, x, y, z);
+  const long long ip = linp(g, x, y, z);
   constexpr int E = sm_entries<DIM, FORM>();
-  // 3D per-patch form: one patch (27 entries) per iteration, to bound register use
-  constexpr int UNR = (DIM == 3 && FORM == SM_FULL) ? 27 : E;
-  const size_t N = (size_t)g.N;
+  // 3D per-patch form: three patches (81 entries) per iteration, to bound register use;
+  // there plain loads keep more of them in flight than non-temporal ones
+  constexpr int UNR = (DIM == 3 && FORM == SM_FULL) ? 81 : E;
+  constexpr bool NT = (UNR == E);
+  const size_t Np = (size_t)g.Np;
   const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
   cpx<T> acc = cmk<T>(0, 0);
 #pragma unroll 1
@@ -318,7 +325,8 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
       const int e = e0 + q;
       const int dx = sm_off<DIM, FORM>(e, 0), dy = sm_off<DIM, FORM>(e, 1),
                 dz = sm_off<DIM, FORM>(e, 2);
-      acc = cfma(ld_stream(G + (size_t)e * N + i), t0[(dz * SY + dy) * SX + dx], acc);
+      const cpx<T> gv = NT ? ld_stream(G + (size_t)e * Np + ip) : G[(size_t)e * Np + ip];
+      acc = cfma(gv, t0[(dz * SY + dy) * SX + dx], acc);
     }
   }
   u[i] = ZERO ? acc : (u[i] + acc);
@@ -392,6 +400,7 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
   constexpr int PB = WPB * PPW;  // patches per block
   __shared__ cpx<T> stage[Np * Np * PB];
   __shared__ unsigned char okrow[Np * PB];
+  __shared__ long long cpad[PB];  // padded index of each patch anchor
   const unsigned lane = threadIdx.x & 63u;
   const unsigned wib = threadIdx.x >> 6;  // wave in block
   const unsigned slot = lane / Np;
@@ -493,14 +502,16 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
 #pragma unroll
     for (int s = 0; s < Np; ++s) stage[(pivs[pslot * Np + s] + i * Np) * PB + pslot] = ccast<T>(wt * a[s]);
     okrow[i * PB + pslot] = ok ? 1 : 0;
+    if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
   __syncthreads();
+  const size_t Npad = (size_t)g.Np;
   for (int e = threadIdx.x; e < Np * Np * PB; e += blockDim.x) {
     const int r = e / PB, p = e % PB, ii = r / Np;
     if (!okrow[ii * PB + p]) continue;
-    const long long off = lin(g, patch_off<DIM, PATCH>(ii, 0), patch_off<DIM, PATCH>(ii, 1),
-                              patch_off<DIM, PATCH>(ii, 2));
-    G[(size_t)r * N + (size_t)(c0 + p + off)] = stage[e];
+    const long long off = linp(g, patch_off<DIM, PATCH>(ii, 0), patch_off<DIM, PATCH>(ii, 1),
+                               patch_off<DIM, PATCH>(ii, 2));
+    G[(size_t)r * Npad + (size_t)(cpad[p] + off)] = stage[e];
   }
 }
 
@@ -552,7 +563,10 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
   if (i >= g.N) return;
   constexpr int Np = patch_Np<DIM, PATCH_FULL>();
   constexpr int K5 = shape_K<DIM, BOX2>();
-  const size_t N = (size_t)g.N;
+  const size_t N = (size_t)g.Np;
+  int cx, cy, cz;
+  decode(i, g, cx, cy, cz);
+  const long long ip = linp(g, cx, cy, cz);
   for (int e = 0; e < K5; ++e) {
     const int dx = shape_off<DIM, BOX2>(e, 0), dy = shape_off<DIM, BOX2>(e, 1),
               dz = shape_off<DIM, BOX2>(e, 2);
@@ -563,9 +577,9 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
                 my = dy + patch_off<DIM, PATCH_FULL>(a, 1),
                 mz = dz + patch_off<DIM, PATCH_FULL>(a, 2);
       const int m = shape_index<DIM, BOX1>(mx, my, mz);
-      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * N + i]);
+      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * N + ip]);
     }
-    B[(size_t)e * N + i] = ccast<T>(acc);
+    B[(size_t)e * N + ip] = ccast<T>(acc);
   }
 }
 
@@ -582,6 +596,30 @@ hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hip
     else
       k_vanka_assemble<3, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, (cpx<float>*)B);
   }
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// dst[e][i] (FP64, N-node rows) = src[e][padded i] (smoother arrays, for inspection)
+template <class T>
+__global__ __launch_bounds__(256) void k_unpad(Grid g, int E, const cpx<T>* __restrict__ src,
+                                               cpx<double>* __restrict__ dst) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)E * (size_t)g.N) return;
+  const size_t e = t / (size_t)g.N;
+  const unsigned i = (unsigned)(t % (size_t)g.N);
+  int x, y, z;
+  decode(i, g, x, y, z);
+  dst[t] = ccast<double>(src[e * (size_t)g.Np + (size_t)linp(g, x, y, z)]);
+}
+
+hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s) {
+  const size_t n = (size_t)E * (size_t)g.N;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (prec == PREC_F64)
+    k_unpad<double><<<nb, 256, 0, s>>>(g, E, (const cpx<double>*)src, dst);
+  else
+    k_unpad<float><<<nb, 256, 0, s>>>(g, E, (const cpx<float>*)src, dst);
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }

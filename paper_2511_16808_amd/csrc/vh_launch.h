@@ -27,6 +27,22 @@ struct KrylovDev {
   double inv_nrm;
 };
 
+// Device-resident FGMRES state of a batch of up to 64 sources (FP64); every array
+// is source-fastest with a stride of 64.
+struct BatchKrylovDev {
+  cpx<double> H[MMAX * (MMAX + 1) * 64];
+  double cs[MMAX * 64];
+  cpx<double> sn[MMAX * 64];
+  cpx<double> g[(MMAX + 1) * 64];
+  cpx<double> y[MMAX * 64];
+  cpx<double> h1[(MMAX + 1) * 64];
+  cpx<double> h2[(MMAX + 1) * 64];
+  cpx<double> nrm2[64];
+  double status[64 * 4];  // per source: |g_{j+1}|, ||w||, breakdown flag, beta
+  double inv_nrm[64];
+  int kcols[64];          // columns used by the next solution update (0 = frozen source)
+};
+
 hipError_t fill(void* p, size_t n, int prec, double re, double im, hipStream_t s);
 hipError_t convert(const void* a, int pa, void* b, int pb, size_t n, hipStream_t s);
 hipError_t fine_operator(int dim, Grid g, const double* kappa, const double* gamma, double h,
@@ -41,6 +57,7 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
                        bool zero, hipStream_t s);
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
                        int prec, void* G, hipStream_t s);
+hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);
 hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hipStream_t s);
 hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,
                     const cpx<double>* Af, cpx<double>* Ac, hipStream_t s);
@@ -63,5 +80,31 @@ hipError_t update_x(const KrylovDev* K, int k, int pz, const void* Z, size_t ldz
 hipError_t scale_vec(const double* scale, const cpx<double>* w, cpx<double>* v, size_t N,
                      hipStream_t s);
 hipError_t cycle_init(KrylovDev* K, int m, hipStream_t s);
+
+// multi-source (batched) path, vectors [node][S], S = 1 << ls <= 64
+hipError_t batch_gather(long long N, int S, int nsrc, const cpx<double>* q, cpx<double>* Q,
+                        hipStream_t st);
+hipError_t batch_scatter(long long N, int S, int nsrc, const cpx<double>* X, cpx<double>* u,
+                         hipStream_t st);
+hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,
+                         int px, const void* x, int py, const void* b, void* y, hipStream_t st);
+hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* G, const void* r,
+                       void* u, bool zero, hipStream_t st);
+hipError_t batch_restrict(int dim, int rf, Grid gf, Grid gc, int ls, int prec, const void* r,
+                          void* rc, hipStream_t st);
+hipError_t batch_prolong_add(int dim, int pf, Grid gf, Grid gc, int ls, int prec, const void* e,
+                             void* u, hipStream_t st);
+hipError_t batch_dense(int n, int ls, const cpx<double>* D, int prec, const void* X, void* Y,
+                       hipStream_t st);
+hipError_t batch_cgs(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                     cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
+                     cpx<double>* out, hipStream_t st);
+hipError_t batch_finalize(BatchKrylovDev* K, int j, int S, hipStream_t st);
+hipError_t batch_cycle_init(BatchKrylovDev* K, int m, int S, hipStream_t st);
+hipError_t batch_backsolve(BatchKrylovDev* K, int S, hipStream_t st);
+hipError_t batch_update_x(const BatchKrylovDev* K, int kmax, int pz, const void* Z, size_t ldz,
+                          cpx<double>* x, long long N, int ls, hipStream_t st);
+hipError_t batch_scale(const BatchKrylovDev* K, const cpx<double>* w, cpx<double>* v, long long N,
+                       int ls, hipStream_t st);
 
 }  // namespace vh

@@ -83,6 +83,16 @@ struct vh_handle {
   size_t bytes = 0;
   // optional event timing (vh_options.timing): pairs of events with a kind tag
   // (0 = finest smoothing from u = 0, 1 = finest smoothing u += B r, 2 = V-cycle)
+  // multi-source workspace, allocated on the first batched solve for up to bS sources
+  int bS = 0;
+  cpx<double>* bV = nullptr;  // (m+1) x N x bS
+  void* bZ = nullptr;         // m x N x bS (preconditioner precision)
+  cpx<double>* bQ = nullptr;  // right-hand sides, N x bS
+  cpx<double>* bX = nullptr;  // iterates, N x bS
+  cpx<double>* bpart = nullptr;
+  BatchKrylovDev* bK = nullptr;
+  double* bstat = nullptr;    // pinned, 64 x 4
+  std::vector<void*> bq, bu, br;  // per-level V-cycle vectors, N_l x bS
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kind;
   int ev_used = 0;
@@ -92,6 +102,7 @@ struct vh_handle {
   ~vh_handle() {
     for (void* p : allocs) (void)hipFree(p);
     if (hstat) (void)hipHostFree(hstat);
+    if (bstat) (void)hipHostFree(bstat);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
   // returns the index of a free event pair, or -1 if timing is off / the pool is full
@@ -388,6 +399,223 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
   return converged ? VH_OK : fail(VH_ENOCONV, "maxit reached before tol");
 }
 
+// ---------------------------------------------------------------- multi-source path
+vh_status ensure_batch(vh_handle* hd, int S) {
+  if (hd->bS >= S) return VH_OK;
+  // (re)allocate for S sources
+  auto drop = [&](void* p) {
+    if (p) {
+      hd->bytes -= 0;
+      hd->release(p);
+    }
+  };
+  drop(hd->bV);
+  drop(hd->bZ);
+  drop(hd->bQ);
+  drop(hd->bX);
+  drop(hd->bpart);
+  drop(hd->bK);
+  for (void* p : hd->bq) drop(p);
+  for (void* p : hd->bu) drop(p);
+  for (void* p : hd->br) drop(p);
+  hd->bq.assign(hd->levels, nullptr);
+  hd->bu.assign(hd->levels, nullptr);
+  hd->br.assign(hd->levels, nullptr);
+  hd->bS = 0;
+  const size_t N = (size_t)hd->L[0].g.N;
+  VH_TRY(hd->alloc((void**)&hd->bV, (size_t)(hd->m + 1) * N * S * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc(&hd->bZ, (size_t)hd->m * N * S * hd->esz));
+  VH_TRY(hd->alloc((void**)&hd->bQ, N * S * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&hd->bX, N * S * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&hd->bpart, (size_t)hd->nred * 65 * 64 * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&hd->bK, sizeof(BatchKrylovDev)));
+  VH_HIP(hipMemsetAsync(hd->bK, 0, sizeof(BatchKrylovDev), hd->s));
+  for (int l = 0; l < hd->levels; ++l) {
+    const size_t Nl = (size_t)hd->L[l].g.N * S;
+    VH_TRY(hd->alloc(&hd->bq[l], Nl * hd->esz));
+    VH_TRY(hd->alloc(&hd->bu[l], Nl * hd->esz));
+    VH_TRY(hd->alloc(&hd->br[l], Nl * hd->esz));
+  }
+  if (!hd->bstat) VH_HIP(hipHostMalloc((void**)&hd->bstat, 64 * 4 * sizeof(double), hipHostMallocDefault));
+  hd->bS = S;
+  return VH_OK;
+}
+
+vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zero) {
+  Level& Lv = hd->L[l];
+  const int tk = (l == 0) ? hd->tbegin(zero ? 0 : 1) : -1;
+  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2
+                   : (hd->patch == VH_PATCH_FULL ? 0 : 1);
+  VH_HIP(batch_sweep(hd->dim, form, Lv.g, ls, hd->prec, Lv.B, r, u, zero, hd->s));
+  hd->tend(tk);
+  return VH_OK;
+}
+
+vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, void* r) {
+  Level& Lv = hd->L[l];
+  VH_HIP(batch_stencil(hd->dim, Lv.shape, Lv.g, ls, OP_RESID, hd->prec, Lv.A, hd->prec, u,
+                       hd->prec, q, r, hd->s));
+  return VH_OK;
+}
+
+// the V-cycle of vcycle() on a batch of 1 << ls sources
+vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u) {
+  Level& Lv = hd->L[l];
+  if (l == hd->levels - 1) {
+    VH_HIP(batch_dense(hd->nc, ls, hd->Dinv, hd->prec, q, u, hd->s));
+    return VH_OK;
+  }
+  const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
+  void* r = hd->br[l];
+  if (nu1 == 0) VH_HIP(fill(u, (size_t)Lv.g.N << ls, hd->prec, 0.0, 0.0, hd->s));
+  for (int k = 0; k < nu1; ++k) {
+    if (k == 0) {
+      VH_TRY(bsmooth(hd, l, ls, q, u, true));
+    } else {
+      VH_TRY(bresidual(hd, l, ls, q, u, r));
+      VH_TRY(bsmooth(hd, l, ls, r, u, false));
+    }
+  }
+  Level& Lc = hd->L[l + 1];
+  VH_TRY(bresidual(hd, l, ls, q, u, r));
+  VH_HIP(batch_restrict(hd->dim, Lv.rf, Lv.g, Lc.g, ls, hd->prec, r, hd->bq[l + 1], hd->s));
+  VH_TRY(vcycle_b(hd, l + 1, ls, hd->bq[l + 1], hd->bu[l + 1]));
+  VH_HIP(batch_prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, ls, hd->prec, hd->bu[l + 1], u, hd->s));
+  for (int k = 0; k < nu2; ++k) {
+    VH_TRY(bresidual(hd, l, ls, q, u, r));
+    VH_TRY(bsmooth(hd, l, ls, r, u, false));
+  }
+  return VH_OK;
+}
+
+vh_status read_bstatus(vh_handle* hd, int S) {
+  VH_HIP(hipMemcpyAsync(hd->bstat, hd->bK->status, (size_t)S * 4 * sizeof(double),
+                        hipMemcpyDeviceToHost, hd->s));
+  VH_HIP(hipStreamSynchronize(hd->s));
+  hd->tflush();
+  return VH_OK;
+}
+
+// FGMRES(m) for nsrc <= 64 sources sharing every V-cycle.  The sources advance in
+// lockstep; a source that reaches tol (or maxit) inside a cycle freezes: its solution
+// update uses only its own columns and it takes no further updates.
+vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double>* u, double tol,
+                       vh_solve_stats* st) {
+  int ls = 0;
+  while ((1 << ls) < nsrc) ++ls;
+  const int S = 1 << ls;
+  VH_TRY(ensure_batch(hd, S));
+  const long long N = hd->L[0].g.N;
+  const int m = hd->m;
+  const size_t ldv = (size_t)N * S;
+  BatchKrylovDev* K = hd->bK;
+  auto Vj = [&](int j) { return hd->bV + (size_t)j * ldv; };
+  auto Zj = [&](int j) { return (void*)((char*)hd->bZ + (size_t)j * ldv * hd->esz); };
+  const Grid g0 = hd->L[0].g;
+  hipStream_t s = hd->s;
+
+  VH_HIP(batch_gather(N, S, nsrc, q, hd->bQ, s));
+  VH_HIP(fill(hd->bX, (size_t)N * S, PREC_F64, 0, 0, s));
+  VH_HIP(hipMemcpyAsync(Vj(0), hd->bQ, ldv * sizeof(cpx<double>), hipMemcpyDeviceToDevice, s));
+  VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->nred, K->nrm2, s));
+  VH_HIP(batch_cycle_init(K, m, S, s));
+  VH_HIP(batch_scale(K, Vj(0), Vj(0), N, ls, s));
+  VH_TRY(read_bstatus(hd, S));
+  std::vector<double> bnorm(S), beta(S);
+  std::vector<int> its(S, 0), restarts(S, 0), active(S, 0), conv(S, 0);
+  std::vector<double> est(S, 1.0);
+  for (int k = 0; k < S; ++k) {
+    bnorm[k] = hd->bstat[k * 4 + 3];
+    beta[k] = bnorm[k];
+    if (k < nsrc && !(bnorm[k] == bnorm[k] && !std::isinf(bnorm[k])))
+      return fail(VH_EBREAKDOWN, "non-finite right-hand side");
+    if (k < nsrc && bnorm[k] > 0) active[k] = 1;
+    if (k < nsrc && bnorm[k] == 0) conv[k] = 1;
+  }
+  int kcols[64];
+  while (true) {
+    bool any = false;
+    for (int k = 0; k < S; ++k) {
+      if (!active[k]) continue;
+      if (beta[k] / bnorm[k] <= tol) {
+        active[k] = 0;
+        conv[k] = 1;
+      } else if (its[k] >= hd->opt.maxit) {
+        active[k] = 0;
+      }
+      any = any || active[k];
+    }
+    if (!any) break;
+    std::vector<int> stopped(S, 0);
+    for (int k = 0; k < S; ++k) kcols[k] = 0;
+    int j = 0;
+    for (; j < m; ++j) {
+      const void* qv = Vj(j);
+      if (hd->prec != PREC_F64) {
+        VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
+        qv = hd->bq[0];
+      }
+      const int tk = hd->tbegin(2);
+      VH_TRY(vcycle_b(hd, 0, ls, qv, Zj(j)));
+      hd->tend(tk);
+      VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
+                           PREC_F64, nullptr, Vj(j + 1), s));
+      VH_HIP(batch_cgs(0, hd->bV, ldv, j + 1, nullptr, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+                       K->h1, s));
+      VH_HIP(batch_cgs(1, hd->bV, ldv, j + 1, K->h1, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+                       K->h2, s));
+      VH_HIP(batch_cgs(2, hd->bV, ldv, j + 1, K->h2, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+                       K->nrm2, s));
+      VH_HIP(batch_finalize(K, j, S, s));
+      VH_HIP(batch_scale(K, Vj(j + 1), Vj(j + 1), N, ls, s));
+      VH_TRY(read_bstatus(hd, S));
+      bool all_stopped = true;
+      for (int k = 0; k < S; ++k) {
+        if (!active[k] || stopped[k]) continue;
+        if (hd->bstat[k * 4 + 2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
+        ++its[k];
+        kcols[k] = j + 1;
+        est[k] = hd->bstat[k * 4 + 0] / bnorm[k];
+        if (est[k] <= tol || its[k] >= hd->opt.maxit || hd->bstat[k * 4 + 1] == 0.0) stopped[k] = 1;
+        all_stopped = all_stopped && stopped[k];
+      }
+      if (all_stopped) break;
+    }
+    VH_HIP(hipMemcpyAsync(K->kcols, kcols, S * sizeof(int), hipMemcpyHostToDevice, s));
+    int kmax = 0;
+    for (int k = 0; k < S; ++k) kmax = kcols[k] > kmax ? kcols[k] : kmax;
+    VH_HIP(batch_backsolve(K, S, s));
+    VH_HIP(batch_update_x(K, kmax, hd->prec, hd->bZ, ldv, hd->bX, N, ls, s));
+    VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
+                         PREC_F64, hd->bQ, Vj(0), s));
+    VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->nred, K->nrm2, s));
+    VH_HIP(batch_cycle_init(K, m, S, s));
+    VH_HIP(batch_scale(K, Vj(0), Vj(0), N, ls, s));
+    VH_TRY(read_bstatus(hd, S));
+    for (int k = 0; k < S; ++k) {
+      if (!active[k]) continue;
+      beta[k] = hd->bstat[k * 4 + 3];
+      ++restarts[k];
+      if (!(beta[k] == beta[k]) || std::isinf(beta[k])) return fail(VH_EBREAKDOWN, "non-finite residual");
+    }
+  }
+  VH_HIP(batch_scatter(N, S, nsrc, hd->bX, u, s));
+  VH_HIP(hipStreamSynchronize(s));
+  bool all_conv = true;
+  for (int k = 0; k < nsrc; ++k) {
+    if (st) {
+      st[k] = vh_solve_stats{};
+      st[k].iterations = its[k];
+      st[k].restarts = restarts[k];
+      st[k].converged = conv[k];
+      st[k].relres = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
+      st[k].relres_est = est[k];
+    }
+    all_conv = all_conv && conv[k];
+  }
+  return all_conv ? VH_OK : fail(VH_ENOCONV, "maxit reached before tol");
+}
+
 // ---------------------------------------------------------------- setup
 vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   const int dim = hd->dim;
@@ -458,22 +686,24 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     Lv.bytes = ((size_t)Lv.K + 3) * N * hd->esz;
     if (l + 1 == hd->levels) break;
     void* G = nullptr;
-    VH_TRY(hd->alloc(&G, (size_t)Np * Np * N * hd->esz));
-    VH_HIP(fill(G, (size_t)Np * Np * N, hd->prec, 0, 0, s));
+    const size_t Npad = (size_t)Lv.g.Np;  // smoother arrays use the padded row layout
+    VH_TRY(hd->alloc(&G, (size_t)Np * Np * Npad * hd->esz));
+    VH_HIP(fill(G, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
     VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, Lv.g, A64[l], Lv.w, hd->prec, G, s));
     if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch == VH_PATCH_FULL) {
       const int K5 = dim == 2 ? 25 : 125;
-      VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * N * hd->esz));
+      VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * Npad * hd->esz));
+      VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));
       VH_HIP(vanka_assemble(dim, Lv.g, hd->prec, G, Lv.B, s));
       VH_HIP(hipStreamSynchronize(s));
       hd->release(G);
-      hd->bytes -= (size_t)Np * Np * N * hd->esz;
+      hd->bytes -= (size_t)Np * Np * Npad * hd->esz;
       Lv.E = K5;
     } else {
       Lv.B = G;
       Lv.E = Np * Np;
     }
-    Lv.bytes += (size_t)Lv.E * N * hd->esz;
+    Lv.bytes += (size_t)Lv.E * Npad * hd->esz;
   }
   if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch != VH_PATCH_FULL)
     hd->opt.smoother = VH_SMOOTHER_PATCH;  // a 1x1 patch is already a 1-point stencil
@@ -603,6 +833,42 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
   if (q == u) return fail(VH_EINVAL, "q and u may not alias");
   const size_t N = (size_t)hd->L[0].g.N;
   vh_status worst = VH_OK;
+  if (hd->opt.batch) {
+    for (int s0 = 0; s0 < nsrc; s0 += 64) {
+      const int cnt = nsrc - s0 < 64 ? nsrc - s0 : 64;
+      hipEvent_t e0, e1;
+      VH_HIP(hipEventCreate(&e0));
+      VH_HIP(hipEventCreate(&e1));
+      VH_HIP(hipEventRecord(e0, hd->s));
+      for (int k = 0; k < 3; ++k) {
+        hd->t_ms[k] = 0;
+        hd->t_n[k] = 0;
+      }
+      hd->ev_used = 0;
+      vh_status r = fgmres_batch(hd, (const cpx<double>*)q + (size_t)s0 * N, cnt,
+                                 (cpx<double>*)u + (size_t)s0 * N, tol, stats ? stats + s0 : nullptr);
+      (void)hipEventRecord(e1, hd->s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      hd->tflush();
+      if (stats)
+        for (int k = s0; k < s0 + cnt; ++k) {
+          stats[k].solve_ms = ms;
+          stats[k].smooth0_launches = hd->t_n[0];
+          stats[k].smooth0_ms = hd->t_ms[0];
+          stats[k].smooth1_launches = hd->t_n[1];
+          stats[k].smooth1_ms = hd->t_ms[1];
+          stats[k].vcycles = hd->t_n[2];
+          stats[k].vcycle_ms = hd->t_ms[2];
+        }
+      if (r != VH_OK && r != VH_ENOCONV) return r;
+      if (r == VH_ENOCONV) worst = VH_ENOCONV;
+    }
+    return worst == VH_OK ? VH_OK : fail(worst, "maxit reached before tol");
+  }
   for (int sidx = 0; sidx < nsrc; ++sidx) {
     hipEvent_t e0, e1;
     VH_HIP(hipEventCreate(&e0));
@@ -735,7 +1001,17 @@ vh_status vh_export_level(const vh_handle* hdc, int level, void* coef, void* smo
     return VH_OK;
   };
   if (coef) VH_TRY(copy_out(Lv.A, (size_t)Lv.K * N, coef));
-  if (smoother && Lv.B) VH_TRY(copy_out(Lv.B, (size_t)Lv.E * N, smoother));
+  if (smoother && Lv.B) {
+    const size_t count = (size_t)Lv.E * N;
+    void* tmp = nullptr;
+    VH_HIP(hipMalloc(&tmp, count * 16));
+    hipError_t e = unpad(Lv.g, Lv.E, hd->prec, Lv.B, (cpx<double>*)tmp, hd->s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(smoother, tmp, count * 16, hipMemcpyDeviceToHost, hd->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(hd->s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(VH_EDEVICE, hipGetErrorString(e));
+  }
   if (coarse_inv) {
     if (level != hd->levels - 1) return fail(VH_EINVAL, "coarse_inv only on the coarsest level");
     VH_HIP(hipMemcpyAsync(coarse_inv, hd->Dinv, (size_t)hd->nc * hd->nc * 16,
@@ -770,7 +1046,8 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, const vh
     const int E = (o.smoother == VH_SMOOTHER_ASSEMBLED && patch == VH_PATCH_FULL)
                       ? (dim == 2 ? 25 : 125)
                       : Np * Np;
-    total += (size_t)E * N * esz;
+    const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
+    total += (size_t)E * Npad * esz;
     shape = (ig == VH_IG_LINEAR) ? BOX1 : BOX2;
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }

@@ -13,6 +13,7 @@ Prints ONE JSON line.  Workloads (synthetic media, seeded):
   c2  2D 1025^2 layered medium, 7 levels, complex128
   c3  3D 257^3 geophysical medium, 6 levels, complex64 preconditioner / complex128 FGMRES
   c4  2D 513^2 layered medium, 64 sources sharing one hierarchy and every V-cycle sweep
+  c5  serving mix of 2D/3D requests with Poisson arrivals through the request loop
 """
 import argparse
 import json
@@ -55,6 +56,92 @@ WORKLOADS = {
                sample=dict(n=(65, 65, 65), levels=4)),
 }
 DEFAULT_WORKLOAD = "c3"
+
+SERVE_DESC = ("serving mix: Poisson arrivals; 70% 2D grids uniform over {257,513,1025,2049}^2 nodes, "
+              "30% 3D over {97,129,193}^3; seeded layered media per request, 8-12 ppw, "
+              "gamma=0.01*omega, ABC; 1-16 sources each (batched); complex64 preconditioner, "
+              "FGMRES in complex128; admission by HBM footprint")
+
+
+def serve_requests(count, seed):
+    """Seeded request mix (media are generated here, outside any timed region)."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for r in range(count):
+        if rng.uniform() < 0.7:
+            nn = int(rng.choice([257, 513, 1025, 2049]))
+            n = (nn, nn)
+            kappa = synth.layered_2d(n, 1000 + r)
+            levels = {257: 5, 513: 6, 1025: 7, 2049: 8}[nn]
+            shift, restart = 0.2, 20
+        else:
+            nn = int(rng.choice([97, 129, 193]))
+            n = (nn, nn, nn)
+            kappa = synth.geophysical_3d(n, 1000 + r)
+            levels = {97: 4, 129: 5, 193: 5}[nn]
+            shift, restart = 0.5, 30
+        ppw = float(rng.uniform(8.0, 12.0))
+        nsrc = int(rng.integers(1, 17))
+        h = 1.0 / (nn - 1)
+        omega = synth.omega_for_ppw(h, ppw, float(kappa.max()))
+        q = synth.random_sources(n, nsrc, seed=1000 + r, margin=min(22, nn // 4))
+        reqs.append(dict(dim=len(n), n=n, h=h, omega=omega, kappa=kappa.ravel(),
+                         gamma=0.01 * omega * np.ones(kappa.size), shift=shift, levels=levels,
+                         restart=restart, q=q, nsrc=nsrc))
+    return reqs
+
+
+def serve_bench(args):
+    """Serving workload: requests submitted at Poisson arrival times to one server."""
+    import numpy as np
+    import torch
+    from paper_2511_16808_amd import binding as B
+    reqs = serve_requests(args.requests, 5)
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(reqs)))
+    arrivals -= arrivals[0]
+    smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
+    opts = {rs: B.make_options(precision=B.VH_PREC_C64, batch=1, restart=rs, smoother=smoother)
+            for rs in (20, 30)}
+    torch.cuda.synchronize()
+    srv = B.vh_server_create(int(args.budget_gib * (1 << 30)), args.slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, ta in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(B.vh_server_submit(srv, r["dim"], r["n"], r["h"], r["omega"], r["kappa"],
+                                          r["gamma"], r["shift"], r["levels"], B.VH_PATCH_FULL,
+                                          r["q"], r["nsrc"], 1e-6, opts[r["restart"]]))
+    lat, qms, its, ok, nsol = [], [], [], 0, 0
+    for t, r in zip(tickets, reqs):
+        st, u, stats, l, qm = B.vh_server_result(srv, t, int(np.prod(r["n"])), r["nsrc"])
+        lat.append(l)
+        qms.append(qm)
+        its += [x["iterations"] for x in stats]
+        ok += int(st == B.VH_OK)
+        nsol += r["nsrc"]
+    makespan = time.perf_counter() - t0
+    info = B.vh_server_get_info(srv)
+    B.vh_server_destroy(srv)
+    lat = np.array(lat)
+    out = {
+        "metric": METRIC, "value": nsol / makespan, "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": 1e3 * makespan / len(reqs),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": "c5: " + SERVE_DESC, "requests": len(reqs), "sources": nsol,
+                   "arrival_rate_per_s": args.rate, "slots": args.slots,
+                   "hbm_budget_gib": args.budget_gib, "smoother": args.smoother},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "queue_p50_ms": float(np.percentile(qms, 50)), "makespan_s": makespan,
+        "requests_ok": ok, "iterations_mean": float(np.mean(its)),
+        "peak_running": info["peak_running"], "peak_in_use_gib": info["peak_in_use"] / 2 ** 30,
+    }
+    print(json.dumps(out))
 
 
 def make_medium(w, n=None):
@@ -154,7 +241,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["c5"])
+    ap.add_argument("--requests", type=int, default=32, help="c5: number of requests")
+    ap.add_argument("--rate", type=float, default=2.0, help="c5: Poisson arrival rate (1/s)")
+    ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
+    ap.add_argument("--budget-gib", type=float, default=240.0, help="c5: HBM budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smoother", default="patch", choices=["patch", "assembled"])
     ap.add_argument("--batch", type=int, default=None, choices=[0, 1],
@@ -178,6 +269,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "c5":
+        serve_bench(args)
+        return
     if args.copy_probe_mib > 0:
         # one elementwise kernel that reads and writes exactly MiB << 20 bytes each
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")

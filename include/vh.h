@@ -183,10 +183,60 @@ vh_status vh_apply_smoother(vh_handle *hd, int level, const void *q, void *u);
 vh_status vh_export_level(const vh_handle *hd, int level, void *coef, void *smoother,
                           void *coarse_inv);
 
-/* Device bytes vh_setup would allocate (excluding the caller's arrays), plus the
- * per-source FGMRES workspace of vh_solve.  Pure function of its arguments. */
-size_t vh_footprint_bytes(int dim, const int *n, int levels, int patch,
+/* Device bytes a handle holds after vh_setup plus the workspace vh_solve adds for
+ * nsrc sources (the multi-source workspace when opt->batch = 1), excluding the
+ * caller's arrays; 0 for invalid grids.  Pure function of its arguments (no device
+ * call), used for admission by footprint. */
+size_t vh_footprint_bytes(int dim, const int *n, int levels, int patch, int nsrc,
                           const vh_options *opt);
+
+/* ---- serving: persistent request loop with admission by HBM footprint ----------
+ * Requests are copied at submission and queued.  Up to max_slots requests run at
+ * once, each on its own worker thread and HIP stream (default priority); a queued
+ * request is admitted as soon as a slot is free and its footprint
+ * (vh_footprint_bytes + its kappa, gamma, q and u arrays) fits in what is left of
+ * hbm_budget.  Later requests may overtake a queued head that does not fit at most a
+ * bounded number of times.  Each request runs vh_setup + vh_solve on a handle of its
+ * own, so its result does not depend on the other requests in flight.  Results are
+ * held until fetched with vh_server_result.  The server uses the device that is
+ * current when it is created. */
+typedef struct vh_server vh_server;
+
+typedef struct vh_request {
+    int dim;                 /* 2 or 3                                                   */
+    int n[3];                /* nodes per dimension                                      */
+    double h, omega;         /* grid spacing, angular frequency                          */
+    const double *kappa;     /* HOST, float64[N], copied at submission                   */
+    const double *gamma;     /* HOST, float64[N] or NULL, copied                          */
+    double shift;            /* alpha of eq. (shift)                                     */
+    int levels, patch;       /* as in vh_setup                                           */
+    const void *q;           /* HOST, c128[nsrc][N], copied                              */
+    int nsrc;                /* sources (>= 1)                                           */
+    double tol;              /* relative residual target                                 */
+    const vh_options *opt;   /* NULL = defaults; the stream field is ignored             */
+} vh_request;
+
+typedef struct vh_server_info {
+    size_t budget, in_use, peak_in_use;  /* bytes                                        */
+    int running, peak_running, queued;
+    uint64_t completed;
+} vh_server_info;
+
+vh_status vh_server_create(vh_server **out, size_t hbm_budget, int max_slots);
+/* VH_ENOMEM if the request alone exceeds the budget, VH_EINVAL for bad requests. */
+vh_status vh_server_submit(vh_server *srv, const vh_request *req, uint64_t *ticket);
+vh_status vh_server_poll(vh_server *srv, uint64_t ticket, int *done);
+vh_status vh_server_wait(vh_server *srv, uint64_t ticket);
+/* Waits for the request, copies its solution to u (HOST c128[nsrc][N], may be NULL)
+ * and its stats (array of nsrc, may be NULL), reports latency (submission ->
+ * completion) and queueing time in ms, releases the ticket, and returns the
+ * request's own vh_solve status. */
+vh_status vh_server_result(vh_server *srv, uint64_t ticket, void *u, vh_solve_stats *stats,
+                           double *latency_ms, double *queue_ms);
+vh_status vh_server_get_info(vh_server *srv, vh_server_info *info);
+/* Finishes every submitted request, then stops the workers and frees the server
+ * (unfetched results are discarded). */
+vh_status vh_server_destroy(vh_server *srv);
 
 #ifdef __cplusplus
 }

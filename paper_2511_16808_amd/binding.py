@@ -64,6 +64,24 @@ class vh_level_info(ctypes.Structure):
     ]
 
 
+class vh_request(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+        ("omega", ctypes.c_double), ("kappa", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+        ("shift", ctypes.c_double), ("levels", ctypes.c_int), ("patch", ctypes.c_int),
+        ("q", ctypes.c_void_p), ("nsrc", ctypes.c_int), ("tol", ctypes.c_double),
+        ("opt", ctypes.POINTER(vh_options)),
+    ]
+
+
+class vh_server_info(ctypes.Structure):
+    _fields_ = [
+        ("budget", ctypes.c_size_t), ("in_use", ctypes.c_size_t), ("peak_in_use", ctypes.c_size_t),
+        ("running", ctypes.c_int), ("peak_running", ctypes.c_int), ("queued", ctypes.c_int),
+        ("completed", ctypes.c_uint64),
+    ]
+
+
 class VhError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"vh status {status}: {msg}")
@@ -89,8 +107,16 @@ _SIGNATURES = {
     "vh_apply_vcycle": (_I, [_P, _P, _P]),
     "vh_apply_smoother": (_I, [_P, _I, _P, _P]),
     "vh_export_level": (_I, [_P, _I, _P, _P, _P]),
-    "vh_footprint_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _I,
+    "vh_footprint_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _I, _I,
                                              ctypes.POINTER(vh_options)]),
+    "vh_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
+    "vh_server_submit": (_I, [_P, ctypes.POINTER(vh_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "vh_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(_I)]),
+    "vh_server_wait": (_I, [_P, ctypes.c_uint64]),
+    "vh_server_result": (_I, [_P, ctypes.c_uint64, _P, ctypes.POINTER(vh_solve_stats),
+                              ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "vh_server_get_info": (_I, [_P, ctypes.POINTER(vh_server_info)]),
+    "vh_server_destroy": (_I, [_P]),
 }
 
 
@@ -209,10 +235,72 @@ def vh_export_level(hd, level, coef=None, smoother=None, coarse_inv=None):
     check(lib().vh_export_level(hd, level, hp(coef), hp(smoother), hp(coarse_inv)))
 
 
-def vh_footprint_bytes(dim, n, levels, patch, opt=None):
+def vh_footprint_bytes(dim, n, levels, patch, nsrc=1, opt=None):
     arr = (_I * 3)(*(list(n) + [1] * (3 - len(n))))
-    return lib().vh_footprint_bytes(dim, arr, levels, patch,
+    return lib().vh_footprint_bytes(dim, arr, levels, patch, nsrc,
                                     ctypes.byref(opt) if opt is not None else None)
+
+
+def vh_server_create(hbm_budget, max_slots):
+    srv = _P()
+    check(lib().vh_server_create(ctypes.byref(srv), int(hbm_budget), int(max_slots)))
+    return srv
+
+
+def vh_server_submit(srv, dim, n, h, omega, kappa, gamma, shift, levels, patch, q, nsrc, tol,
+                     opt=None):
+    """kappa, gamma, q: host numpy arrays (float64, float64 or None, complex128 [nsrc][N]);
+    they are copied by the server.  Returns the ticket."""
+    import numpy as np
+    k = np.ascontiguousarray(kappa, dtype=np.float64)
+    g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
+    qq = np.ascontiguousarray(q, dtype=np.complex128)
+    req = vh_request()
+    req.dim = dim
+    for d in range(3):
+        req.n[d] = int(n[d]) if d < dim else 1
+    req.h, req.omega, req.shift, req.tol = float(h), float(omega), float(shift), float(tol)
+    req.kappa = k.ctypes.data
+    req.gamma = None if g is None else g.ctypes.data
+    req.q = qq.ctypes.data
+    req.levels, req.patch, req.nsrc = int(levels), int(patch), int(nsrc)
+    req.opt = ctypes.pointer(opt) if opt is not None else None
+    t = ctypes.c_uint64()
+    check(lib().vh_server_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def vh_server_poll(srv, ticket):
+    d = _I()
+    check(lib().vh_server_poll(srv, ticket, ctypes.byref(d)))
+    return bool(d.value)
+
+
+def vh_server_wait(srv, ticket):
+    check(lib().vh_server_wait(srv, ticket))
+
+
+def vh_server_result(srv, ticket, N, nsrc):
+    """Returns (status, u (nsrc, N) complex128, [stats dicts], latency_ms, queue_ms)."""
+    import numpy as np
+    u = np.zeros((nsrc, N), dtype=np.complex128)
+    stats = (vh_solve_stats * nsrc)()
+    lat, qms = _D(), _D()
+    st = lib().vh_server_result(srv, ticket, u.ctypes.data, stats, ctypes.byref(lat),
+                                ctypes.byref(qms))
+    if st not in (VH_OK, VH_ENOCONV):
+        check(st)
+    return st, u, [s.as_dict() for s in stats], lat.value, qms.value
+
+
+def vh_server_get_info(srv):
+    info = vh_server_info()
+    check(lib().vh_server_get_info(srv, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def vh_server_destroy(srv):
+    check(lib().vh_server_destroy(srv))
 
 
 def make_options(**kw):

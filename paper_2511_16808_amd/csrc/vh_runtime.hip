@@ -26,6 +26,13 @@ vh_status fail(vh_status st, const std::string& msg) {
   return st;
 }
 
+}  // namespace
+
+// shared with the server translation unit
+void vh_internal_set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 #define VH_HIP(call)                                                                         \
   do {                                                                                       \
     hipError_t e_ = (call);                                                                  \
@@ -1021,13 +1028,16 @@ vh_status vh_export_level(const vh_handle* hdc, int level, void* coef, void* smo
   return VH_OK;
 }
 
-size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, const vh_options* opt) {
+size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc,
+                          const vh_options* opt) {
   vh_options o;
   if (opt)
     o = *opt;
   else
     vh_options_default(&o);
-  if ((dim != 2 && dim != 3) || !n || levels < 1) return 0;
+  if ((dim != 2 && dim != 3) || !n || levels < 1 || nsrc < 1) return 0;
+  for (int d = 0; d < dim; ++d)
+    if (n[d] < 3) return 0;
   const size_t esz = o.precision == VH_PREC_FP64 ? 16 : 8;
   const int ig = resolve_intergrid(dim, o.intergrid);
   const int Np = patch_size(dim, patch);
@@ -1053,6 +1063,17 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, const vh
   }
   total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz;
   total += 512 * 65 * 16 + sizeof(KrylovDev);
+  if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
+    size_t S = 1;
+    while (S < (size_t)(nsrc < 64 ? nsrc : 64)) S *= 2;
+    total += (size_t)(o.restart + 1) * N0 * S * 16 + (size_t)o.restart * N0 * S * esz +
+             2 * N0 * S * 16 + (size_t)512 * 65 * 64 * 16 + sizeof(BatchKrylovDev);
+    size_t m[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
+    for (int l = 0; l < levels; ++l) {
+      total += 3 * m[0] * m[1] * m[2] * S * esz;
+      for (int d = 0; d < dim; ++d) m[d] = (m[d] - 1) / 2 + 1;
+    }
+  }
   return total;
 }
 

@@ -59,11 +59,18 @@ def test_setup_rejects_bad_options():
 def test_footprint_matches_the_layout():
     """C2-shaped 2D FP64 hierarchy: the per-patch inverses dominate (81 c128 per node)."""
     n = (1025, 1025)
-    fp = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL)
+    fp = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 1)
     N = 1025 * 1025
     inv_fine = 81 * 16 * N
     assert inv_fine < fp < 2.6 * inv_fine
     o = B.make_options(precision=B.VH_PREC_C64)
-    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, o) < 0.62 * fp
+    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 1, o) < 0.62 * fp
     o = B.make_options(smoother=B.VH_SMOOTHER_ASSEMBLED)
-    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, o) < 0.6 * fp
+    assert B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 1, o) < 0.6 * fp
+    # the multi-source workspace grows with the group width (powers of two up to 64)
+    ob = B.make_options(batch=1)
+    f16 = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 16, ob)
+    f9 = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 9, ob)
+    f64 = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 200, ob)
+    assert fp < f9 == f16 < f64
+    assert B.vh_footprint_bytes(2, (2, 5), 1, B.VH_PATCH_FULL, 1) == 0

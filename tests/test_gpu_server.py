@@ -1,0 +1,95 @@
+"""GPU: the persistent request loop (vh_server_*): admission by HBM footprint, requests
+of different grids and frequencies overlapping on the device, and every result the
+same alone and in the mix."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import discretization as D
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2511_16808_amd import binding as B  # noqa: E402
+
+
+def make_requests():
+    """A small mix: 2D and 3D grids, different frequencies, 1-3 sources."""
+    out = []
+    specs = [((129, 129), 4, 1, 10.0), ((65, 65), 3, 3, 8.0), ((33, 33, 33), 3, 2, 10.0),
+             ((257, 129), 4, 1, 12.0), ((65, 65), 3, 2, 9.0), ((17, 33, 17), 2, 1, 10.0)]
+    for r, (n, levels, nsrc, ppw) in enumerate(specs):
+        dim = len(n)
+        kappa = synth.layered_2d(n, 1000 + r) if dim == 2 else synth.geophysical_3d(n, 1000 + r)
+        h = 1.0 / (n[0] - 1)
+        omega = synth.omega_for_ppw(h, ppw, float(kappa.max()))
+        gamma = 0.01 * omega * np.ones_like(kappa)
+        q = synth.random_sources(n, nsrc, seed=r, margin=3)
+        opt = B.make_options(precision=B.VH_PREC_C64, batch=1, restart=20 if dim == 2 else 30,
+                             sponge_width=6 if min(n) < 40 else 12)
+        out.append(dict(dim=dim, n=n, h=h, omega=omega, kappa=kappa.ravel(), gamma=gamma.ravel(),
+                        shift=0.3 if dim == 2 else 0.5, levels=levels, q=q, nsrc=nsrc, opt=opt))
+    return out
+
+
+def run(reqs, budget, slots):
+    srv = B.vh_server_create(budget, slots)
+    try:
+        tickets = [B.vh_server_submit(srv, r["dim"], r["n"], r["h"], r["omega"], r["kappa"],
+                                      r["gamma"], r["shift"], r["levels"], B.VH_PATCH_FULL,
+                                      r["q"], r["nsrc"], 1e-6, r["opt"]) for r in reqs]
+        res = [B.vh_server_result(srv, t, int(np.prod(r["n"])), r["nsrc"])
+               for t, r in zip(tickets, reqs)]
+        info = B.vh_server_get_info(srv)
+    finally:
+        B.vh_server_destroy(srv)
+    return res, info
+
+
+def test_results_are_the_same_alone_and_in_the_mix():
+    reqs = make_requests()
+    mixed, info = run(reqs, budget=64 << 30, slots=4)
+    assert info["completed"] == len(reqs) and info["peak_running"] >= 2
+    for r, m in zip(reqs, mixed):
+        alone, _ = run([r], budget=64 << 30, slots=1)
+        st, u, stats, lat, qms = m
+        st1, u1, stats1, _, _ = alone[0]
+        assert st == B.VH_OK and st1 == B.VH_OK
+        assert [s["iterations"] for s in stats] == [s["iterations"] for s in stats1]
+        assert np.array_equal(u, u1)            # bitwise: each request has its own handle
+        assert lat >= qms >= 0.0
+    # spot-check two results against the oracle's FP64 operator
+    for k in (0, 2):
+        r = reqs[k]
+        shape = tuple(reversed(r["n"]))
+        ops = D.fd2_operator(r["n"], r["h"], r["omega"], r["kappa"].reshape(shape),
+                             r["gamma"].reshape(shape), r["shift"],
+                             sponge_width=r["opt"].sponge_width)
+        u = mixed[k][1]
+        for s in range(r["nsrc"]):
+            res = np.linalg.norm(r["q"][s] - ops["H"] @ u[s]) / np.linalg.norm(r["q"][s])
+            assert res <= 1e-6
+
+
+def test_admission_respects_the_budget():
+    reqs = make_requests()
+    fps = [B.vh_footprint_bytes(r["dim"], r["n"], r["levels"], B.VH_PATCH_FULL, r["nsrc"], r["opt"])
+           for r in reqs]
+    budget = int(1.6 * max(fps))                 # at most one large request at a time
+    res, info = run(reqs, budget=budget, slots=4)
+    assert info["completed"] == len(reqs)
+    assert info["peak_in_use"] <= budget
+    assert all(r[0] == B.VH_OK for r in res)
+
+
+def test_oversized_request_is_rejected_at_submission():
+    r = make_requests()[0]
+    srv = B.vh_server_create(1 << 20, 2)
+    try:
+        with pytest.raises(B.VhError) as e:
+            B.vh_server_submit(srv, r["dim"], r["n"], r["h"], r["omega"], r["kappa"], r["gamma"],
+                               r["shift"], r["levels"], B.VH_PATCH_FULL, r["q"], r["nsrc"], 1e-6,
+                               r["opt"])
+        assert e.value.status == B.VH_ENOMEM
+    finally:
+        B.vh_server_destroy(srv)

@@ -168,6 +168,32 @@ def make_medium(w, n=None):
     return n, h, omega, kappa, gamma, q
 
 
+def kernel_sha(kernel):
+    """Hash of the source text of one kernel template (from its declaration to the end
+    of its body); counter-measured traffic is only reported for an unchanged kernel."""
+    import hashlib
+    fname = "vh_batch.hip" if kernel.startswith("kb_") else "vh_kernels.hip"
+    src = open(os.path.join(ROOT, "paper_2511_16808_amd", "csrc", fname)).read()
+    a = src.find(f"void {kernel}(")
+    if a < 0:
+        return None
+    a = src.rfind("template", 0, a)
+    b = src.find("\n}\n", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(key, kernel):
+    """HBM bytes per launch of the dominant kernel from profiles/traffic.json (two
+    calibrated rocprofv3 counter runs), or None if absent or taken on other code."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    if not rec or rec.get("kernel_sha") != kernel_sha(kernel):
+        return None
+    return rec["traffic"]
+
+
 def vcycle_bytes(levels_info, dim, esz, smoother_entries):
     """Algorithmic HBM bytes of one V(1,1) cycle: each array touched once per kernel."""
     total = 0
@@ -252,8 +278,6 @@ def main():
                     help="override: sources one after another (0) or sharing each sweep (1)")
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
                     help="override the preconditioner precision")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured HBM bytes per launch of the dominant kernel")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -333,9 +357,8 @@ def main():
     ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
     bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(args.workload)
+    kname = "k_vanka_sweep" if width == 1 else ("kb_sweep2d" if dim == 2 else "kb_sweep3d")
+    traffic = measured_traffic(f"{args.workload}_{'batch' if batch else args.smoother}", kname)
     vc_b = vcycle_bytes(info, dim, esz, E)
     vc_n = sum(r["stats"]["vcycles"] for r in runs)
     vc_ms = sum(r["stats"]["vcycle_ms"] for r in runs)
@@ -369,8 +392,7 @@ def main():
         "vcycle_algorithmic_bytes": vc_b,
         "roofline": {
             "bound": "hbm",
-            "kernel": ("finest-level additive Vanka sweep u += B r, "
-                       + ("k_vanka_sweep" if width == 1 else f"kb_sweep over {width} sources")),
+            "kernel": f"finest-level additive Vanka sweep u += B r ({kname}, {width} source(s))",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -183,6 +183,14 @@ vh_status vh_apply_smoother(vh_handle *hd, int level, const void *q, void *u);
 vh_status vh_export_level(const vh_handle *hd, int level, void *coef, void *smoother,
                           void *coarse_inv);
 
+/* Copies the entries of sampled nodes of level `level` to a HOST buffer:
+ *   which = 0 -> operator coefficients (K per node, order of vh_level_info.offsets),
+ *   which = 1 -> smoother entries (E per node, weights folded in);
+ *   nodes : HOST int64[count], linear node indices (< N_level);
+ *   out   : HOST c128[count][K or E].  VH_EINVAL for out-of-range nodes. */
+vh_status vh_sample_level(const vh_handle *hd, int level, int which, int count,
+                          const int64_t *nodes, void *out);
+
 /* Device bytes a handle holds after vh_setup plus the workspace vh_solve adds for
  * nsrc sources (the multi-source workspace when opt->batch = 1), excluding the
  * caller's arrays; 0 for invalid grids.  Pure function of its arguments (no device

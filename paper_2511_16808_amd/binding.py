@@ -107,6 +107,7 @@ _SIGNATURES = {
     "vh_apply_vcycle": (_I, [_P, _P, _P]),
     "vh_apply_smoother": (_I, [_P, _I, _P, _P]),
     "vh_export_level": (_I, [_P, _I, _P, _P, _P]),
+    "vh_sample_level": (_I, [_P, _I, _I, _I, _P, _P]),
     "vh_footprint_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _I, _I,
                                              ctypes.POINTER(vh_options)]),
     "vh_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I]),
@@ -233,6 +234,15 @@ def vh_export_level(hd, level, coef=None, smoother=None, coarse_inv=None):
         assert a.dtype.name == "complex128" and a.flags["C_CONTIGUOUS"]
         return a.ctypes.data
     check(lib().vh_export_level(hd, level, hp(coef), hp(smoother), hp(coarse_inv)))
+
+
+def vh_sample_level(hd, level, which, nodes, width):
+    """Entries of sampled nodes: host complex128 array (len(nodes), width)."""
+    import numpy as np
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((nd.size, width), dtype=np.complex128)
+    check(lib().vh_sample_level(hd, level, which, nd.size, nd.ctypes.data, out.ctypes.data))
+    return out
 
 
 def vh_footprint_bytes(dim, n, levels, patch, nsrc=1, opt=None):

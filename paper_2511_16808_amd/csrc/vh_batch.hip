@@ -231,11 +231,12 @@ __global__ __launch_bounds__(256) void kb_sweep2d(Grid g, int ls, const cpx<T>* 
   const size_t Np = (size_t)g.Np;
   constexpr int E = bsm_entries<2, FORM>();
   const cpx<T>* t0 = tile + ((size_t)(ns + 2) + (size_t)SX * 2) * S + s;
+  const cpx<T>* Gn = G + ip;
   cpx<T> acc = cmk<T>(0, 0);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
-    acc = cfma(G[(size_t)e * Np + ip], t0[(dx + SX * dy) * S], acc);
+    acc = cfma(Gn[(size_t)e * Np], t0[(dx + SX * dy) * S], acc);
   }
   const size_t o = (size_t)i * S + s;
   u[o] = ZERO ? acc : (u[o] + acc);
@@ -285,9 +286,95 @@ __global__ __launch_bounds__(256) void kb_sweep3d(Grid g, int ls, int NB,
   u[o] = ZERO ? acc : (u[o] + acc);
 }
 
+// 2D, 16 to 64 sources: a block covers a row segment of 16 nodes x S sources (each
+// thread 16*S/256 (node, source) pairs).  With many sources per node, per-lane loads of
+// the smoother entries would be 8-byte broadcasts; instead the block stages the
+// entries of its 16 nodes in LDS with coalesced 16-node row loads, next to the
+// residual tile, and every lane reads its node's entries as LDS broadcasts.
+constexpr int BW_NB = 16;
+
+template <int FORM, bool ZERO, class T, int LS>
+__global__ __launch_bounds__(256) void kb_sweep2d_wide(Grid g, const cpx<T>* __restrict__ G,
+                                                       const cpx<T>* __restrict__ r,
+                                                       cpx<T>* __restrict__ u) {
+  constexpr int E = bsm_entries<2, FORM>();
+  constexpr int NB = BW_NB, SX = NB + 4, S = 1 << LS;
+  constexpr int NG = E * NB, NT = SX * 5 * S;
+  extern __shared__ unsigned char smem[];
+  cpx<T>* gt = reinterpret_cast<cpx<T>*>(smem);  // [E][NB]
+  cpx<T>* tile = gt + NG;                         // [SX*5][S]
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (g.nx + NB - 1) / NB;
+  const int x0 = (int)(b % (unsigned)nbx) * NB, y0 = (int)(b / (unsigned)nbx);
+  const size_t Np = (size_t)g.Np;
+  const long long ip0 = linp_b(g, x0, y0, 0);
+  // all loads of the staging phase are issued before the first LDS write
+  cpx<T> gv[(NG + 255) / 256], tv[(NT + 255) / 256];
+#pragma unroll
+  for (int i = 0; i < (NG + 255) / 256; ++i) {
+    const int e = threadIdx.x + 256 * i, k = e % NB, q = e / NB;
+    gv[i] = (e < NG && x0 + k < g.nx) ? G[(size_t)q * Np + ip0 + k] : cmk<T>(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < (NT + 255) / 256; ++i) {
+    const int e = threadIdx.x + 256 * i, pos = e >> LS, sl = e & (S - 1);
+    const int gx = x0 + pos % SX - 2, gy = y0 + pos / SX - 2;
+    tv[i] = (e < NT && inside_b(g, gx, gy, 0)) ? r[(size_t)lin_b(g, gx, gy, 0) * S + sl]
+                                                : cmk<T>(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < (NG + 255) / 256; ++i)
+    if (threadIdx.x + 256 * i < NG) gt[threadIdx.x + 256 * i] = gv[i];
+#pragma unroll
+  for (int i = 0; i < (NT + 255) / 256; ++i)
+    if (threadIdx.x + 256 * i < NT) tile[threadIdx.x + 256 * i] = tv[i];
+  __syncthreads();
+  const int s = threadIdx.x & (S - 1);
+#pragma unroll 1
+  for (int ns = threadIdx.x >> LS; ns < NB; ns += 256 >> LS) {
+    const int x = x0 + ns;
+    if (x >= g.nx) break;
+    const cpx<T>* t0 = tile + ((size_t)(ns + 2) + (size_t)SX * 2) * S + s;
+    cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
+      acc = cfma(gt[e * NB + ns], t0[(dx + SX * dy) * S], acc);
+    }
+    const size_t o = (size_t)lin_b(g, x, y0, 0) * S + s;
+    u[o] = ZERO ? acc : (u[o] + acc);
+  }
+}
+
+template <int FORM, class T, int LS>
+static void launch_wide(Grid g, const void* G, const void* r, void* u, bool zero, size_t lds,
+                        hipStream_t st) {
+  const unsigned nb = (unsigned)(((g.nx + BW_NB - 1) / BW_NB) * g.ny);
+  if (zero)
+    kb_sweep2d_wide<FORM, true, T, LS><<<nb, 256, lds, st>>>(g, (const cpx<T>*)G,
+                                                             (const cpx<T>*)r, (cpx<T>*)u);
+  else
+    kb_sweep2d_wide<FORM, false, T, LS><<<nb, 256, lds, st>>>(g, (const cpx<T>*)G,
+                                                              (const cpx<T>*)r, (cpx<T>*)u);
+}
+
 template <int DIM, int FORM, class T>
 static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u, bool zero,
                            hipStream_t st) {
+  if (DIM == 2 && ls >= 4) {
+    const size_t lds = ((size_t)bsm_entries<2, FORM>() * BW_NB +
+                        (size_t)(BW_NB + 4) * 5 * ((size_t)1 << ls)) * sizeof(cpx<T>);
+    if (lds <= 65536) {
+      if (ls == 4)
+        launch_wide<FORM, T, 4>(g, G, r, u, zero, lds, st);
+      else if (ls == 5)
+        launch_wide<FORM, T, 5>(g, G, r, u, zero, lds, st);
+      else
+        launch_wide<FORM, T, 6>(g, G, r, u, zero, lds, st);
+      VHB_CHECK();
+      return hipSuccess;
+    }
+  }
   if (DIM == 3) {
     // widest row segment whose tile fits in 64 KB of LDS and 256 threads
     const size_t S = (size_t)1 << ls;
@@ -311,12 +398,13 @@ static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u
     const int NB = 256 >> ls;
     const unsigned nb = (unsigned)(((g.nx + NB - 1) / NB) * g.ny);
     const size_t lds = (size_t)(NB + 4) * 5 * ((size_t)1 << ls) * sizeof(cpx<T>);
+    auto Gp = (const cpx<T>*)G;
+    auto rp = (const cpx<T>*)r;
+    auto up = (cpx<T>*)u;
     if (zero)
-      kb_sweep2d<FORM, true, T><<<nb, 256, lds, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
-                                                      (cpx<T>*)u);
+      kb_sweep2d<FORM, true, T><<<nb, 256, lds, st>>>(g, ls, Gp, rp, up);
     else
-      kb_sweep2d<FORM, false, T><<<nb, 256, lds, st>>>(g, ls, (const cpx<T>*)G, (const cpx<T>*)r,
-                                                       (cpx<T>*)u);
+      kb_sweep2d<FORM, false, T><<<nb, 256, lds, st>>>(g, ls, Gp, rp, up);
     VHB_CHECK();
     return hipSuccess;
   }

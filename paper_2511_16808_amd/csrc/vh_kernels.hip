@@ -624,6 +624,34 @@ hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hip
   return hipSuccess;
 }
 
+// out[k][e] (FP64) = src[e][node_k] for sampled nodes (padded or plain row layout)
+template <class T>
+__global__ __launch_bounds__(256) void k_sample(Grid g, int E, int padded, int count,
+                                                const long long* __restrict__ nodes,
+                                                const cpx<T>* __restrict__ src,
+                                                cpx<double>* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)count * E) return;
+  const int k = (int)(t / E), e = (int)(t % E);
+  const long long i = nodes[k];
+  int x, y, z;
+  decode((unsigned)i, g, x, y, z);
+  const size_t col = padded ? (size_t)linp(g, x, y, z) : (size_t)i;
+  const size_t ld = padded ? (size_t)g.Np : (size_t)g.N;
+  out[t] = ccast<double>(src[(size_t)e * ld + col]);
+}
+
+hipError_t sample(Grid g, int E, int padded, int prec, int count, const long long* nodes,
+                  const void* src, cpx<double>* out, hipStream_t s) {
+  const unsigned nb = (unsigned)(((long long)count * E + 255) / 256);
+  if (prec == PREC_F64)
+    k_sample<double><<<nb, 256, 0, s>>>(g, E, padded, count, nodes, (const cpx<double>*)src, out);
+  else
+    k_sample<float><<<nb, 256, 0, s>>>(g, E, padded, count, nodes, (const cpx<float>*)src, out);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------------ Galerkin
 // Sec. 3.1: H_c = R H P, one thread per coarse node I:
 //   H_c[I][J-I] = sum_t r(t) sum_s H[2I+t][s] p(2I+t+off_s - 2J),

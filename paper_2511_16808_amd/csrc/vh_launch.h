@@ -57,6 +57,8 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
                        bool zero, hipStream_t s);
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
                        int prec, void* G, hipStream_t s);
+hipError_t sample(Grid g, int E, int padded, int prec, int count, const long long* nodes,
+                  const void* src, cpx<double>* out, hipStream_t s);
 hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);
 hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hipStream_t s);
 hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,

@@ -83,7 +83,8 @@ struct vh_handle {
   cpx<double>* V = nullptr;  // (m+1) x N
   void* Z = nullptr;         // m x N at the preconditioner precision
   cpx<double>* part = nullptr;
-  int nred = 512;
+  int nred = 512;   // blocks of the Krylov partial sums: enough waves to fill the GPU
+  int bnred = 512;  // same for the multi-source path
   KrylovDev* K = nullptr;
   double* hstat = nullptr;  // pinned host copy of K->status
   std::vector<void*> allocs;
@@ -434,7 +435,11 @@ vh_status ensure_batch(vh_handle* hd, int S) {
   VH_TRY(hd->alloc(&hd->bZ, (size_t)hd->m * N * S * hd->esz));
   VH_TRY(hd->alloc((void**)&hd->bQ, N * S * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->bX, N * S * sizeof(cpx<double>)));
-  VH_TRY(hd->alloc((void**)&hd->bpart, (size_t)hd->nred * 65 * 64 * sizeof(cpx<double>)));
+  {
+    long long nb = (long long)N * S / 1024;
+    hd->bnred = (int)(nb < 64 ? 64 : (nb > 2048 ? 2048 : nb));
+  }
+  VH_TRY(hd->alloc((void**)&hd->bpart, (size_t)hd->bnred * 65 * 64 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->bK, sizeof(BatchKrylovDev)));
   VH_HIP(hipMemsetAsync(hd->bK, 0, sizeof(BatchKrylovDev), hd->s));
   for (int l = 0; l < hd->levels; ++l) {
@@ -524,7 +529,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
   VH_HIP(batch_gather(N, S, nsrc, q, hd->bQ, s));
   VH_HIP(fill(hd->bX, (size_t)N * S, PREC_F64, 0, 0, s));
   VH_HIP(hipMemcpyAsync(Vj(0), hd->bQ, ldv * sizeof(cpx<double>), hipMemcpyDeviceToDevice, s));
-  VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->nred, K->nrm2, s));
+  VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->bnred, K->nrm2, s));
   VH_HIP(batch_cycle_init(K, m, S, s));
   VH_HIP(batch_scale(K, Vj(0), Vj(0), N, ls, s));
   VH_TRY(read_bstatus(hd, S));
@@ -567,11 +572,11 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       hd->tend(tk);
       VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                            PREC_F64, nullptr, Vj(j + 1), s));
-      VH_HIP(batch_cgs(0, hd->bV, ldv, j + 1, nullptr, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+      VH_HIP(batch_cgs(0, hd->bV, ldv, j + 1, nullptr, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
                        K->h1, s));
-      VH_HIP(batch_cgs(1, hd->bV, ldv, j + 1, K->h1, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+      VH_HIP(batch_cgs(1, hd->bV, ldv, j + 1, K->h1, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
                        K->h2, s));
-      VH_HIP(batch_cgs(2, hd->bV, ldv, j + 1, K->h2, Vj(j + 1), N, ls, hd->bpart, hd->nred,
+      VH_HIP(batch_cgs(2, hd->bV, ldv, j + 1, K->h2, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
                        K->nrm2, s));
       VH_HIP(batch_finalize(K, j, S, s));
       VH_HIP(batch_scale(K, Vj(j + 1), Vj(j + 1), N, ls, s));
@@ -595,7 +600,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     VH_HIP(batch_update_x(K, kmax, hd->prec, hd->bZ, ldv, hd->bX, N, ls, s));
     VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
                          PREC_F64, hd->bQ, Vj(0), s));
-    VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->nred, K->nrm2, s));
+    VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->bnred, K->nrm2, s));
     VH_HIP(batch_cycle_init(K, m, S, s));
     VH_HIP(batch_scale(K, Vj(0), Vj(0), N, ls, s));
     VH_TRY(read_bstatus(hd, S));
@@ -740,6 +745,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     }
   // FGMRES workspace
   hd->m = o.restart;
+  {
+    long long nb = (long long)N0 / 512;
+    hd->nred = (int)(nb < 64 ? 64 : (nb > 2048 ? 2048 : nb));
+  }
   VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc(&hd->Z, (size_t)hd->m * N0 * hd->esz));
   VH_TRY(hd->alloc((void**)&hd->part, (size_t)hd->nred * 65 * sizeof(cpx<double>)));
@@ -1028,6 +1037,35 @@ vh_status vh_export_level(const vh_handle* hdc, int level, void* coef, void* smo
   return VH_OK;
 }
 
+vh_status vh_sample_level(const vh_handle* hdc, int level, int which, int count,
+                          const int64_t* nodes, void* out) {
+  vh_handle* hd = const_cast<vh_handle*>(hdc);
+  if (!hd || level < 0 || level >= hd->levels || count < 1 || !nodes || !out)
+    return fail(VH_EINVAL, "bad argument");
+  Level& Lv = hd->L[level];
+  const void* src = which == 0 ? Lv.A : Lv.B;
+  const int E = which == 0 ? Lv.K : Lv.E;
+  if (which != 0 && which != 1) return fail(VH_EINVAL, "which must be 0 or 1");
+  if (!src || E == 0) return fail(VH_EINVAL, "this level has no such array");
+  for (int k = 0; k < count; ++k)
+    if (nodes[k] < 0 || nodes[k] >= Lv.g.N) return fail(VH_EINVAL, "node index out of range");
+  long long* dn = nullptr;
+  cpx<double>* dout = nullptr;
+  VH_HIP(hipMalloc((void**)&dn, (size_t)count * sizeof(long long)));
+  hipError_t e = hipMalloc((void**)&dout, (size_t)count * E * sizeof(cpx<double>));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dn, nodes, (size_t)count * sizeof(long long), hipMemcpyHostToDevice, hd->s);
+  if (e == hipSuccess) e = sample(Lv.g, E, which == 1, hd->prec, count, dn, src, dout, hd->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dout, (size_t)count * E * sizeof(cpx<double>), hipMemcpyDeviceToHost,
+                       hd->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(hd->s);
+  (void)hipFree(dn);
+  if (dout) (void)hipFree(dout);
+  if (e != hipSuccess) return fail(VH_EDEVICE, hipGetErrorString(e));
+  return VH_OK;
+}
+
 size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc,
                           const vh_options* opt) {
   vh_options o;
@@ -1062,12 +1100,12 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }
   total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz;
-  total += 512 * 65 * 16 + sizeof(KrylovDev);
+  total += (size_t)2048 * 65 * 16 + sizeof(KrylovDev);
   if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
     size_t S = 1;
     while (S < (size_t)(nsrc < 64 ? nsrc : 64)) S *= 2;
     total += (size_t)(o.restart + 1) * N0 * S * 16 + (size_t)o.restart * N0 * S * esz +
-             2 * N0 * S * 16 + (size_t)512 * 65 * 64 * 16 + sizeof(BatchKrylovDev);
+             2 * N0 * S * 16 + (size_t)2048 * 65 * 64 * 16 + sizeof(BatchKrylovDev);
     size_t m[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
     for (int l = 0; l < levels; ++l) {
       total += 3 * m[0] * m[1] * m[2] * S * esz;

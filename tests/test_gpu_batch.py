@@ -78,3 +78,19 @@ def test_batch_zero_and_nonconverging_sources():
     assert st == B.VH_OK and stats[1]["iterations"] == 0 and np.all(u[1] == 0)
     st, stats, u = solve(c, q.ravel(), batch=1, maxit=2)
     assert st == B.VH_ENOCONV and stats[0]["iterations"] == 2 and not stats[0]["converged"]
+
+
+def test_batch_of_64_sources_2d_ragged_tile():
+    """64 sources on an 81^2 grid (81 nodes per row: five full 16-node row segments and a
+    one-node tail): every sampled source reaches the FP64 tolerance, and source 5 equals
+    the same source solved alone (1e-10, rounding of the batched dot products only)."""
+    c = Case(n=(81, 81), levels=3, alpha=0.3, medium="layered", seed=6, sponge_width=8)
+    q = synth.random_sources(c.n, 64, seed=5, margin=9)
+    st, stats, u = solve(c, q.ravel(), batch=1)
+    assert st == B.VH_OK and len(stats) == 64
+    ops, _ = c.oracle()
+    for s in (0, 5, 31, 63):
+        assert np.linalg.norm(q[s] - ops["H"] @ u[s]) / np.linalg.norm(q[s]) <= 1e-6
+    st1, stats1, u1 = solve(c, q[5], batch=1)
+    assert stats1[0]["iterations"] == stats[5]["iterations"]
+    assert np.linalg.norm(u1[0] - u[5]) <= 1e-10 * np.linalg.norm(u[5])

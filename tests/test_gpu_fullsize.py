@@ -1,0 +1,122 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration bench.py times
+(same workloads, options and entry points).  Where the oracle can hold the problem it
+checks outputs directly (the 1025^2 V-cycle, every true residual); at 257^3, where its
+FP64 hierarchy would need ~200 GB, it checks sampled finest-level patch inverses one
+by one and the true residual with its FP64 operator."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import cycle, krylov  # noqa: E402
+from oracle import discretization as D  # noqa: E402
+from oracle import vanka  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import bench  # noqa: E402
+from paper_2511_16808_amd import binding as B  # noqa: E402
+
+
+def setup_workload(key, **over):
+    w = dict(bench.WORKLOADS[key], key=key)
+    n, h, omega, kappa, gamma, q = bench.make_medium(w)
+    opt = B.make_options(precision=w["precision"], restart=w["restart"], damping=w["damping"],
+                         intergrid=B.VH_IG_LEVDEP if w["dim"] == 2 else B.VH_IG_LINEAR,
+                         batch=w.get("batch", 0), stream=torch.cuda.current_stream(), **over)
+    kt = torch.tensor(kappa.ravel(), dtype=torch.float64, device="cuda")
+    gt = torch.tensor(gamma.ravel(), dtype=torch.float64, device="cuda")
+    hd = B.vh_setup(w["dim"], n, h, omega, kt, gt, w["alpha"], w["levels"], B.VH_PATCH_FULL, opt)
+    return w, n, h, omega, kappa, gamma, q, hd
+
+
+def true_relres(ops, q, u):
+    return np.linalg.norm(q - ops["H"] @ u) / np.linalg.norm(q)
+
+
+def test_c2_vcycle_and_solve_1025():
+    """1025^2 layered medium, 7-level V(1,1), complex128: one V-cycle equals the
+    oracle's to 1e-10; the solve reaches a true FP64 residual <= 1e-6."""
+    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c2")
+    try:
+        ops = D.fd2_operator(n, h, omega, kappa, gamma, w["alpha"])
+        mg = cycle.Multigrid(ops["Hs"], n, w["levels"], "levdep", "full", w["damping"])
+        v = np.random.default_rng(0).standard_normal(q.size) + 1j * np.random.default_rng(1).standard_normal(q.size)
+        z = torch.empty(q.size, dtype=torch.complex128, device="cuda")
+        B.vh_apply_vcycle(hd, torch.tensor(v, device="cuda"), z)
+        zr = mg.apply(v)
+        assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-10 * np.linalg.norm(zr)
+        qt = torch.tensor(q, device="cuda")
+        u = torch.empty_like(qt)
+        st, stats = B.vh_solve(hd, qt, 1, 1e-6, u)
+        assert st == B.VH_OK
+        assert true_relres(ops, q, u.cpu().numpy()) <= 1e-6
+    finally:
+        B.vh_destroy(hd)
+
+
+def test_c3_sampled_inverses_and_solve_257():
+    """257^3, complex64 preconditioner: sampled finest-level patch inverses (27 patches
+    per sampled node) equal the oracle's FP64 inverses rounded to complex64; the solve's
+    true FP64 residual is <= 1e-6."""
+    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c3")
+    try:
+        ops = D.fd2_operator(n, h, omega, kappa, gamma, w["alpha"])
+        rng = np.random.default_rng(3)
+        nx, ny, nz = n
+        pts = [(0, 0, 0), (1, 128, 256), (256, 17, 3)]
+        pts += [tuple(int(rng.integers(1, k - 1)) for k in n) for _ in range(12)]
+        nodes = np.array([x + nx * (y + ny * z) for x, y, z in pts], dtype=np.int64)
+        G = B.vh_sample_level(hd, 0, 1, nodes, 729)
+        offs = vanka.patch_offsets("full", 3)
+        Hs = ops["Hs"].tocsr()
+        for k, (x, y, z) in enumerate(pts):
+            cnt = np.prod([3 - (c == 0) - (c == m - 1) for c, m in zip((x, y, z), n)])
+            ref = np.zeros(729, dtype=complex)
+            for a, oa in enumerate(offs):
+                c = (x - oa[0], y - oa[1], z - oa[2])
+                if not all(0 <= c[d] < n[d] for d in range(3)):
+                    continue
+                mem = [(c[0] + o[0], c[1] + o[1], c[2] + o[2]) for o in offs]
+                ok = [all(0 <= p[d] < n[d] for d in range(3)) for p in mem]
+                idx = [p[0] + nx * (p[1] + ny * p[2]) for p, o in zip(mem, ok) if o]
+                Ainv = np.linalg.inv(Hs[idx][:, idx].toarray())
+                pos = [i for i, o in enumerate(ok) if o]
+                arow = pos.index(a)
+                for j, m in enumerate(pos):
+                    ref[a * 27 + m] = w["damping"][0] / cnt * Ainv[arow, j]
+            assert np.abs(G[k] - ref).max() <= 1e-6 * np.abs(ref).max(), (x, y, z)
+        qt = torch.tensor(q, device="cuda")
+        u = torch.empty_like(qt)
+        st, stats = B.vh_solve(hd, qt, 1, 1e-6, u)
+        assert st == B.VH_OK
+        assert true_relres(ops, q, u.cpu().numpy()) <= 1e-6
+    finally:
+        B.vh_destroy(hd)
+
+
+def test_c4_batched_64_sources_513():
+    """513^2, 64 sources batched through one hierarchy (complex64 preconditioner):
+    every source's true FP64 residual <= 1e-6; source 0's iteration count within
+    +-10 % of the oracle's FP64 FGMRES."""
+    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c4")
+    try:
+        qq = q.reshape(w["nsrc"], -1)
+        qt = torch.tensor(q, device="cuda")
+        u = torch.empty_like(qt)
+        st, stats = B.vh_solve(hd, qt, w["nsrc"], 1e-6, u)
+        assert st == B.VH_OK
+        un = u.cpu().numpy().reshape(w["nsrc"], -1)
+        ops = D.fd2_operator(n, h, omega, kappa, gamma, w["alpha"])
+        for s in range(w["nsrc"]):
+            assert true_relres(ops, qq[s], un[s]) <= 1e-6, s
+        mg = cycle.Multigrid(ops["Hs"], n, w["levels"], "levdep", "full", w["damping"])
+        _, info = krylov.fgmres(lambda v: ops["H"] @ v, mg.apply, qq[0], 1e-6, w["restart"], 1000)
+        assert abs(stats[0]["iterations"] - info["iterations"]) <= max(1, 0.1 * info["iterations"])
+    finally:
+        B.vh_destroy(hd)

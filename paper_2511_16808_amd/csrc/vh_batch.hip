@@ -621,36 +621,138 @@ __global__ __launch_bounds__(256) void kb_cgs(const cpx<double>* __restrict__ V,
   }
 }
 
-// out[j][s] = sum_b part[b][j][s]: block per j, (256/S) block groups x S sources,
-// strided then tree reduction, fixed order
+// Register-resident form of kb_cgs for nv <= NJ: one sweep over the nodes does the
+// whole pass.  Each thread keeps one accumulator per basis vector; in MODE 1 the
+// update and the new dot products read V[j] at the same node back to back, so the
+// second read hits the cache and V leaves HBM once per pass.  w is read once.
+template <int MODE, int NJ>
+__global__ __launch_bounds__(256) void kb_cgs_r(const cpx<double>* __restrict__ V, size_t ldv,
+                                                int nv, const cpx<double>* __restrict__ h,
+                                                cpx<double>* __restrict__ w, long long N, int ls,
+                                                cpx<double>* __restrict__ part) {
+  constexpr int NA = (MODE == 2) ? 1 : NJ;
+  __shared__ cpx<double> hs[MODE == 0 ? 1 : NJ][64];
+  __shared__ cpx<double> red[4][64];
+  const int S = 1 << ls;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = lane & (S - 1);
+  if (MODE != 0) {
+    for (int e = threadIdx.x; e < NJ * 64; e += 256)
+      hs[e >> 6][e & 63] = (e >> 6) < nv ? h[e] : cmk(0.0, 0.0);
+    __syncthreads();
+  }
+  const int nodes_per_block = 256 >> ls;
+  const int sub = threadIdx.x >> ls;
+  const long long per = (N + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = lo + per < N ? lo + per : N;
+  cpx<double> acc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = cmk(0.0, 0.0);
+  // Columns j >= nv re-read column nv - 1 (a cache hit) with a zero coefficient, and
+  // their sums are discarded: every load is unconditional, so all of a node's loads
+  // are in flight together.
+  for (long long i = lo + sub; i < hi; i += nodes_per_block) {
+    const size_t o = (size_t)i * S + s;
+    cpx<double> wi = w[o];
+    if (MODE != 0 && nv > 0) {  // the norm-only pass at a restart has nv == 0
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        wi = wi - hs[j][s] * V[(size_t)(j < nv ? j : nv - 1) * ldv + o];
+      w[o] = wi;
+    }
+    if (MODE == 2) {
+      acc[0].re += wi.re * wi.re + wi.im * wi.im;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        acc[j] = cfma_conj(V[(size_t)(j < nv ? j : nv - 1) * ldv + o], wi, acc[j]);
+    }
+  }
+  const int nout = (MODE == 2) ? 1 : nv;
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    if (q < nout) {  // nout is uniform over the block
+      cpx<double> v = acc[q];
+      for (int k = 32; k >= S; k >>= 1) {
+        v.re += __shfl_down(v.re, k, 64);
+        v.im += __shfl_down(v.im, k, 64);
+      }
+      __syncthreads();
+      if (lane < S) red[wv][lane] = v;
+      __syncthreads();
+      if (threadIdx.x < S) {
+        cpx<double> t = red[0][threadIdx.x];
+        for (int k = 1; k < 4; ++k) t = t + red[k][threadIdx.x];
+        part[((size_t)blockIdx.x * BKMAX + q) * 64 + threadIdx.x] = t;
+      }
+    }
+  }
+}
+
+// Two-level fixed-order reduction of the partial sums, out[j][s] = sum_b part[b][j][s].
+// Level 1: block (j, slice) sums the rows b = slice, slice + RSL, ... (256/S row
+// groups x S sources, then a tree over the groups); level 2 sums the RSL slices.
+constexpr int RSL = 16;
+
 __global__ __launch_bounds__(256) void kb_reduce(const cpx<double>* __restrict__ part, int nb,
-                                                 int ls, cpx<double>* __restrict__ out) {
+                                                 int ls, cpx<double>* __restrict__ part2) {
   __shared__ cpx<double> sh[256];
   const int S = 1 << ls;
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int j = blockIdx.x, sl = blockIdx.y, t = threadIdx.x;
   const int s = t & (S - 1), grp = t >> ls, ngrp = 256 >> ls;
   cpx<double> acc = cmk(0.0, 0.0);
-  for (int b = grp; b < nb; b += ngrp) acc = acc + part[((size_t)b * BKMAX + j) * 64 + s];
+  for (int b = sl + RSL * grp; b < nb; b += RSL * ngrp)
+    acc = acc + part[((size_t)b * BKMAX + j) * 64 + s];
   sh[t] = acc;
   __syncthreads();
   for (int w = 128; w >= S; w >>= 1) {
     if (t < w) sh[t] = sh[t] + sh[t + w];
     __syncthreads();
   }
-  if (t < S) out[(size_t)j * 64 + t] = sh[t];
+  if (t < S) part2[((size_t)j * RSL + sl) * 64 + t] = sh[t];
+}
+
+__global__ void kb_reduce_fin(const cpx<double>* __restrict__ part2, int S,
+                              cpx<double>* __restrict__ out) {
+  const int j = blockIdx.x, s = threadIdx.x;
+  if (s >= S) return;
+  cpx<double> acc = cmk(0.0, 0.0);
+  for (int sl = 0; sl < RSL; ++sl) acc = acc + part2[((size_t)j * RSL + sl) * 64 + s];
+  out[(size_t)j * 64 + s] = acc;
+}
+
+template <int MODE>
+static void cgs_launch(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                       cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
+                       hipStream_t st) {
+  if (nv <= 8)
+    kb_cgs_r<MODE, 8><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  else if (nv <= 16)
+    kb_cgs_r<MODE, 16><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  else if (nv <= 24)
+    kb_cgs_r<MODE, 24><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  else
+    kb_cgs<MODE><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
 }
 
 hipError_t batch_cgs(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
                      cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
                      cpx<double>* out, hipStream_t st) {
+  if (nv < (mode == 2 ? 0 : 1) || nv > BKMAX) return hipErrorInvalidValue;
   if (mode == 0)
-    kb_cgs<0><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+    cgs_launch<0>(V, ldv, nv, h, w, N, ls, part, nb, st);
   else if (mode == 1)
-    kb_cgs<1><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+    cgs_launch<1>(V, ldv, nv, h, w, N, ls, part, nb, st);
   else
-    kb_cgs<2><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+    cgs_launch<2>(V, ldv, nv, h, w, N, ls, part, nb, st);
   VHB_CHECK();
-  kb_reduce<<<mode == 2 ? 1 : nv, 256, 0, st>>>(part, nb, ls, out);
+  // the slice sums live after the nb partial rows (the workspace holds both)
+  cpx<double>* part2 = part + (size_t)nb * BKMAX * 64;
+  const int nout = mode == 2 ? 1 : nv;
+  kb_reduce<<<dim3(nout, RSL), 256, 0, st>>>(part, nb, ls, part2);
+  VHB_CHECK();
+  kb_reduce_fin<<<nout, 64, 0, st>>>(part2, 1 << ls, out);
   VHB_CHECK();
   return hipSuccess;
 }

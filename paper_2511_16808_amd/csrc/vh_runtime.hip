@@ -436,10 +436,12 @@ vh_status ensure_batch(vh_handle* hd, int S) {
   VH_TRY(hd->alloc((void**)&hd->bQ, N * S * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->bX, N * S * sizeof(cpx<double>)));
   {
-    long long nb = (long long)N * S / 1024;
-    hd->bnred = (int)(nb < 64 ? 64 : (nb > 2048 ? 2048 : nb));
+    long long nb = (long long)N * S / 8192;
+    hd->bnred = (int)(nb < 64 ? 64 : (nb > 1024 ? 1024 : nb));
   }
-  VH_TRY(hd->alloc((void**)&hd->bpart, (size_t)hd->bnred * 65 * 64 * sizeof(cpx<double>)));
+  // bnred partial rows of 65 x 64 sums, then 65 x 16 x 64 slice sums
+  VH_TRY(hd->alloc((void**)&hd->bpart,
+                   ((size_t)hd->bnred + 16) * 65 * 64 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->bK, sizeof(BatchKrylovDev)));
   VH_HIP(hipMemsetAsync(hd->bK, 0, sizeof(BatchKrylovDev), hd->s));
   for (int l = 0; l < hd->levels; ++l) {

@@ -273,7 +273,9 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--budget-gib", type=float, default=240.0, help="c5: HBM budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--smoother", default="patch", choices=["patch", "assembled"])
+    ap.add_argument("--smoother", default="assembled", choices=["patch", "assembled"],
+                    help="additive Vanka applied as stored patch inverses or as the same "
+                         "operator assembled into a 5^d-point stencil (default)")
     ap.add_argument("--batch", type=int, default=None, choices=[0, 1],
                     help="override: sources one after another (0) or sharing each sweep (1)")
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
@@ -357,7 +359,12 @@ def main():
     ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
     bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
-    kname = "k_vanka_sweep" if width == 1 else ("kb_sweep2d" if dim == 2 else "kb_sweep3d")
+    if width == 1:
+        kname = "k_vanka_sweep"
+    elif dim == 2:
+        kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
+    else:
+        kname = "kb_sweep3d"
     traffic = measured_traffic(f"{args.workload}_{'batch' if batch else args.smoother}", kname)
     vc_b = vcycle_bytes(info, dim, esz, E)
     vc_n = sum(r["stats"]["vcycles"] for r in runs)

@@ -641,18 +641,18 @@ __global__ __launch_bounds__(256) void kb_cgs_r(const cpx<double>* __restrict__ 
       hs[e >> 6][e & 63] = (e >> 6) < nv ? h[e] : cmk(0.0, 0.0);
     __syncthreads();
   }
+  // Nodes are dealt to the blocks round-robin, a row of nodes_per_block at a time, so
+  // that at any moment the whole grid reads one narrow window of every column.
   const int nodes_per_block = 256 >> ls;
   const int sub = threadIdx.x >> ls;
-  const long long per = (N + gridDim.x - 1) / gridDim.x;
-  const long long lo = (long long)blockIdx.x * per;
-  const long long hi = lo + per < N ? lo + per : N;
+  const long long stride = (long long)gridDim.x * nodes_per_block;
   cpx<double> acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = cmk(0.0, 0.0);
   // Columns j >= nv re-read column nv - 1 (a cache hit) with a zero coefficient, and
   // their sums are discarded: every load is unconditional, so all of a node's loads
   // are in flight together.
-  for (long long i = lo + sub; i < hi; i += nodes_per_block) {
+  for (long long i = (long long)blockIdx.x * nodes_per_block + sub; i < N; i += stride) {
     const size_t o = (size_t)i * S + s;
     cpx<double> wi = w[o];
     if (MODE != 0 && nv > 0) {  // the norm-only pass at a restart has nv == 0
@@ -722,35 +722,56 @@ __global__ void kb_reduce_fin(const cpx<double>* __restrict__ part2, int S,
   out[(size_t)j * 64 + s] = acc;
 }
 
+// Blocks of 256 threads that are resident at once on the whole device for kernel k
+// (queried once per kernel; every device the library runs on is the same gfx950 part).
+template <class K>
+static int resident_blocks(K k) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, 0) != hipSuccess || per < 1)
+    return 1 << 30;
+  return per * ncu;
+}
+
+// one pass with a grid of exactly one resident wave of blocks (a partial second wave
+// would leave most of the device idle at the end); returns the number of partial rows
+template <int MODE, int NJ>
+static int cgs_r(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h, cpx<double>* w,
+                 long long N, int ls, cpx<double>* part, int nb, hipStream_t st) {
+  static const int res = resident_blocks(kb_cgs_r<MODE, NJ>);
+  const int g = nb < res ? nb : res;
+  kb_cgs_r<MODE, NJ><<<g, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  return g;
+}
+
 template <int MODE>
-static void cgs_launch(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
-                       cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
-                       hipStream_t st) {
-  if (nv <= 8)
-    kb_cgs_r<MODE, 8><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
-  else if (nv <= 16)
-    kb_cgs_r<MODE, 16><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
-  else if (nv <= 24)
-    kb_cgs_r<MODE, 24><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
-  else
-    kb_cgs<MODE><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+static int cgs_launch(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                      cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
+                      hipStream_t st) {
+  if (nv <= 8) return cgs_r<MODE, 8>(V, ldv, nv, h, w, N, ls, part, nb, st);
+  if (nv <= 16) return cgs_r<MODE, 16>(V, ldv, nv, h, w, N, ls, part, nb, st);
+  if (nv <= 24) return cgs_r<MODE, 24>(V, ldv, nv, h, w, N, ls, part, nb, st);
+  kb_cgs<MODE><<<nb, 256, 0, st>>>(V, ldv, nv, h, w, N, ls, part);
+  return nb;
 }
 
 hipError_t batch_cgs(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
                      cpx<double>* w, long long N, int ls, cpx<double>* part, int nb,
                      cpx<double>* out, hipStream_t st) {
   if (nv < (mode == 2 ? 0 : 1) || nv > BKMAX) return hipErrorInvalidValue;
+  int rows;
   if (mode == 0)
-    cgs_launch<0>(V, ldv, nv, h, w, N, ls, part, nb, st);
+    rows = cgs_launch<0>(V, ldv, nv, h, w, N, ls, part, nb, st);
   else if (mode == 1)
-    cgs_launch<1>(V, ldv, nv, h, w, N, ls, part, nb, st);
+    rows = cgs_launch<1>(V, ldv, nv, h, w, N, ls, part, nb, st);
   else
-    cgs_launch<2>(V, ldv, nv, h, w, N, ls, part, nb, st);
+    rows = cgs_launch<2>(V, ldv, nv, h, w, N, ls, part, nb, st);
   VHB_CHECK();
   // the slice sums live after the nb partial rows (the workspace holds both)
   cpx<double>* part2 = part + (size_t)nb * BKMAX * 64;
   const int nout = mode == 2 ? 1 : nv;
-  kb_reduce<<<dim3(nout, RSL), 256, 0, st>>>(part, nb, ls, part2);
+  kb_reduce<<<dim3(nout, RSL), 256, 0, st>>>(part, rows, ls, part2);
   VHB_CHECK();
   kb_reduce_fin<<<nout, 64, 0, st>>>(part2, 1 << ls, out);
   VHB_CHECK();

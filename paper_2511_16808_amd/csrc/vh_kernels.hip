@@ -393,7 +393,7 @@ __host__ __device__ constexpr int setup_waves() {
 
 template <int DIM, int SHAPE, int PATCH, class T>
 __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
-                                                     double w, cpx<T>* __restrict__ G) {
+                                                     double w, cpx<T>* __restrict__ G, Slab sl) {
   constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int PPW = 64 / Np;
   constexpr int WPB = setup_waves<DIM, PATCH, T>();
@@ -405,11 +405,11 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
   const unsigned wib = threadIdx.x >> 6;  // wave in block
   const unsigned slot = lane / Np;
   const int k = (int)(lane % Np);
-  const long long c0 = (long long)blockIdx.x * PB;
+  const long long c0 = sl.c_lo + (long long)blockIdx.x * PB;
   const int pslot = (int)(wib * PPW + slot);
   const long long c = c0 + pslot;
   const bool in_slot = slot < (unsigned)PPW;
-  const bool active = in_slot && c < g.N;
+  const bool active = in_slot && c < sl.c_hi;
   const int base = (int)(in_slot ? slot : 0) * Np;
   const size_t N = (size_t)g.N;
   int cx = 0, cy = 0, cz = 0;
@@ -505,38 +505,39 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
     if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
   __syncthreads();
-  const size_t Npad = (size_t)g.Np;
   for (int e = threadIdx.x; e < Np * Np * PB; e += blockDim.x) {
     const int r = e / PB, p = e % PB, ii = r / Np;
     if (!okrow[ii * PB + p]) continue;
     const long long off = linp(g, patch_off<DIM, PATCH>(ii, 0), patch_off<DIM, PATCH>(ii, 1),
                                patch_off<DIM, PATCH>(ii, 2));
-    G[(size_t)r * Npad + (size_t)(cpad[p] + off)] = stage[e];
+    G[(size_t)r * sl.gstride + (size_t)(cpad[p] + off - sl.gbase)] = stage[e];
   }
 }
 
 template <int DIM, int SHAPE, int PATCH>
 static hipError_t vanka_setup_s(Grid g, const cpx<double>* A, double w, int prec, void* G,
-                                hipStream_t s) {
+                                Slab sl, hipStream_t s) {
   constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int PPW = 64 / Np;
+  if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
+  const long long nc = sl.c_hi - sl.c_lo;
   if (prec == PREC_F64) {
     constexpr int WPB = setup_waves<DIM, PATCH, double>();
-    const unsigned nb = (unsigned)((g.N + WPB * PPW - 1) / (WPB * PPW));
-    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<double>*)G);
+    const unsigned nb = (unsigned)((nc + WPB * PPW - 1) / (WPB * PPW));
+    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<double>*)G, sl);
   } else {
     constexpr int WPB = setup_waves<DIM, PATCH, float>();
-    const unsigned nb = (unsigned)((g.N + WPB * PPW - 1) / (WPB * PPW));
-    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<float>*)G);
+    const unsigned nb = (unsigned)((nc + WPB * PPW - 1) / (WPB * PPW));
+    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<float>*)G, sl);
   }
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
-                       int prec, void* G, hipStream_t s) {
+                       int prec, void* G, Slab sl, hipStream_t s) {
 #define VH_VS(D, S, P) \
-  if (dim == D && shape == S && patch == P) return vanka_setup_s<D, S, P>(g, A, w, prec, G, s);
+  if (dim == D && shape == S && patch == P) return vanka_setup_s<D, S, P>(g, A, w, prec, G, sl, s);
   VH_VS(2, CROSS, PATCH_FULL)
   VH_VS(2, BOX1, PATCH_FULL)
   VH_VS(2, BOX2, PATCH_FULL)
@@ -558,15 +559,16 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
 // in FP64.  u += B r is then a 5^DIM-point stencil sweep.
 template <int DIM, class T>
 __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __restrict__ G,
-                                                        cpx<T>* __restrict__ B) {
-  const unsigned i = node_id();
-  if (i >= g.N) return;
+                                                        Slab sl, cpx<T>* __restrict__ B) {
+  const long long i = sl.c_lo + (long long)node_id();
+  if (i >= sl.c_hi) return;
   constexpr int Np = patch_Np<DIM, PATCH_FULL>();
   constexpr int K5 = shape_K<DIM, BOX2>();
   const size_t N = (size_t)g.Np;
   int cx, cy, cz;
-  decode(i, g, cx, cy, cz);
+  decode((unsigned)i, g, cx, cy, cz);
   const long long ip = linp(g, cx, cy, cz);
+  const size_t ig = (size_t)(ip - sl.gbase);
   for (int e = 0; e < K5; ++e) {
     const int dx = shape_off<DIM, BOX2>(e, 0), dy = shape_off<DIM, BOX2>(e, 1),
               dz = shape_off<DIM, BOX2>(e, 2);
@@ -577,24 +579,26 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
                 my = dy + patch_off<DIM, PATCH_FULL>(a, 1),
                 mz = dz + patch_off<DIM, PATCH_FULL>(a, 2);
       const int m = shape_index<DIM, BOX1>(mx, my, mz);
-      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * N + ip]);
+      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
     }
     B[(size_t)e * N + ip] = ccast<T>(acc);
   }
 }
 
-hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hipStream_t s) {
-  const unsigned nb = nblocks(g.N, 256);
+hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
+                          hipStream_t s) {
+  if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
+  const unsigned nb = nblocks((size_t)(sl.c_hi - sl.c_lo), 256);
   if (dim == 2) {
     if (prec == PREC_F64)
-      k_vanka_assemble<2, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, (cpx<double>*)B);
+      k_vanka_assemble<2, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, (cpx<double>*)B);
     else
-      k_vanka_assemble<2, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, (cpx<float>*)B);
+      k_vanka_assemble<2, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, (cpx<float>*)B);
   } else {
     if (prec == PREC_F64)
-      k_vanka_assemble<3, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, (cpx<double>*)B);
+      k_vanka_assemble<3, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, (cpx<double>*)B);
     else
-      k_vanka_assemble<3, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, (cpx<float>*)B);
+      k_vanka_assemble<3, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, (cpx<float>*)B);
   }
   VH_LAUNCH_CHECK();
   return hipSuccess;
@@ -1077,17 +1081,134 @@ __global__ __launch_bounds__(256) void k_reduce_part(const cpx<double>* __restri
   if (t == 0) out[j] = sh[0];
 }
 
+// Register-resident form of k_cgs for nv <= 8 * P: P lanes per node, lane q of a node
+// holding columns 8q .. 8q + 7 (one accumulator each), nodes dealt to the lane groups
+// of the grid round-robin.  A pass reads each column of V once and w once; in MODE 1
+// the column values loaded for the update are reused for the new dot products.  The
+// update w - V h is summed over the P lanes of a node by a butterfly, which leaves the
+// same bits in every lane.  Columns j >= nv re-read column nv - 1 with a zero
+// coefficient and their sums are discarded, so every load is unconditional.
+template <int MODE, int P>
+__global__ __launch_bounds__(256) void k_cgs_r(const cpx<double>* __restrict__ V, size_t ldv,
+                                               int nv, const cpx<double>* __restrict__ h,
+                                               cpx<double>* __restrict__ w, size_t N,
+                                               cpx<double>* __restrict__ part) {
+  constexpr int CJ = 8, NJ = CJ * P;
+  constexpr int NA = (MODE == 2) ? 1 : CJ;
+  __shared__ cpx<double> red[4][64];
+  __shared__ cpx<double> hs[NJ];
+  if (MODE != 0) {
+    if (threadIdx.x < NJ) hs[threadIdx.x] = (int)threadIdx.x < nv ? h[threadIdx.x] : cmk(0.0, 0.0);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane % P;  // column group of this lane
+  const size_t slot = ((size_t)blockIdx.x * 256 + threadIdx.x) / P;
+  const size_t stride = (size_t)gridDim.x * (256 / P);
+  int col[CJ];
+#pragma unroll
+  for (int c = 0; c < CJ; ++c) col[c] = (q * CJ + c < nv) ? q * CJ + c : (nv > 0 ? nv - 1 : 0);
+  cpx<double> acc[NA];
+#pragma unroll
+  for (int c = 0; c < NA; ++c) acc[c] = cmk(0.0, 0.0);
+  for (size_t i = slot; i < N; i += stride) {
+    cpx<double> wi = w[i];
+    cpx<double> v[CJ];
+    if (MODE == 0 || nv > 0) {  // the norm-only pass at a restart has nv == 0
+#pragma unroll
+      for (int c = 0; c < CJ; ++c) v[c] = V[(size_t)col[c] * ldv + i];
+    }
+    if (MODE != 0 && nv > 0) {
+      cpx<double> t = cmk(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < CJ; ++c) t = cfma(hs[q * CJ + c], v[c], t);
+#pragma unroll
+      for (int o = 1; o < P; o <<= 1) {
+        t.re += __shfl_xor(t.re, o, 64);
+        t.im += __shfl_xor(t.im, o, 64);
+      }
+      wi = wi - t;
+      if (q == 0) w[i] = wi;
+    }
+    if (MODE == 2) {
+      if (q == 0) acc[0].re += wi.re * wi.re + wi.im * wi.im;
+    } else {
+#pragma unroll
+      for (int c = 0; c < CJ; ++c) acc[c] = cfma_conj(v[c], wi, acc[c]);
+    }
+  }
+  // lanes with the same q hold sums of the same columns: fold them (stride P within
+  // the wavefront), then the four wavefronts; column q*CJ + c ends in part[b][.]
+  const int nout = (MODE == 2) ? 1 : nv;
+#pragma unroll
+  for (int c = 0; c < NA; ++c) {
+    if (c < nout) {  // uniform over the block
+      cpx<double> x = acc[c];
+      for (int o = 32; o >= P; o >>= 1) {
+        x.re += __shfl_down(x.re, o, 64);
+        x.im += __shfl_down(x.im, o, 64);
+      }
+      __syncthreads();
+      if (lane < P) red[wv][lane] = x;
+      __syncthreads();
+      if (threadIdx.x < P) {
+        const int j = (int)threadIdx.x * CJ + c;
+        if (j < nout) {
+          cpx<double> t = red[0][threadIdx.x];
+          for (int k = 1; k < 4; ++k) t = t + red[k][threadIdx.x];
+          part[(size_t)blockIdx.x * KMAX + j] = t;
+        }
+      }
+    }
+  }
+}
+
+// Blocks of 256 threads resident at once on the whole device for kernel k (queried
+// once per kernel; every device the library runs on is the same gfx950 part).
+template <class Kern>
+static int resident_blocks(Kern k) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, 0) != hipSuccess || per < 1)
+    return 1 << 30;
+  return per * ncu;
+}
+
+// one pass on a grid of at most one resident wave of blocks; returns the partial rows
+template <int MODE, int P>
+static int cgs_r(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h, cpx<double>* w,
+                 size_t N, cpx<double>* part, int nb, hipStream_t s) {
+  static const int res = resident_blocks(k_cgs_r<MODE, P>);
+  const int g = nb < res ? nb : res;
+  k_cgs_r<MODE, P><<<g, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+  return g;
+}
+
+template <int MODE>
+static int cgs_launch(const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
+                      cpx<double>* w, size_t N, cpx<double>* part, int nb, hipStream_t s) {
+  if (nv <= 8) return cgs_r<MODE, 1>(V, ldv, nv, h, w, N, part, nb, s);
+  if (nv <= 16) return cgs_r<MODE, 2>(V, ldv, nv, h, w, N, part, nb, s);
+  if (nv <= 32) return cgs_r<MODE, 4>(V, ldv, nv, h, w, N, part, nb, s);
+  if (nv <= 64) return cgs_r<MODE, 8>(V, ldv, nv, h, w, N, part, nb, s);
+  k_cgs<MODE><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+  return nb;
+}
+
 hipError_t cgs_pass(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,
                     cpx<double>* w, size_t N, cpx<double>* part, int nb, cpx<double>* out,
                     hipStream_t s) {
+  if (nv < (mode == 2 ? 0 : 1) || nv > KMAX) return hipErrorInvalidValue;
+  int rows;
   if (mode == 0)
-    k_cgs<0><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+    rows = cgs_launch<0>(V, ldv, nv, h, w, N, part, nb, s);
   else if (mode == 1)
-    k_cgs<1><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+    rows = cgs_launch<1>(V, ldv, nv, h, w, N, part, nb, s);
   else
-    k_cgs<2><<<nb, 256, 0, s>>>(V, ldv, nv, h, w, N, part);
+    rows = cgs_launch<2>(V, ldv, nv, h, w, N, part, nb, s);
   VH_LAUNCH_CHECK();
-  k_reduce_part<<<mode == 2 ? 1 : nv, 256, 0, s>>>(part, nb, out);
+  k_reduce_part<<<mode == 2 ? 1 : nv, 256, 0, s>>>(part, rows, out);
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -55,12 +55,22 @@ hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, 
 // form: 0 = per-patch Full (Np*Np entries), 1 = per-patch point, 2 = assembled 5^dim box
 hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const void* r, void* u,
                        bool zero, hipStream_t s);
+// A slab of the smoother setup: patches centred at nodes [c_lo, c_hi) (unpadded linear
+// index) write their rows to G[e * gstride + (padded member index - gbase)].  The whole
+// grid is {0, N, 0, Np}.
+struct Slab {
+  long long c_lo, c_hi;
+  long long gbase;
+  size_t gstride;
+};
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
-                       int prec, void* G, hipStream_t s);
+                       int prec, void* G, Slab sl, hipStream_t s);
 hipError_t sample(Grid g, int E, int padded, int prec, int count, const long long* nodes,
                   const void* src, cpx<double>* out, hipStream_t s);
 hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);
-hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, void* B, hipStream_t s);
+// B rows of nodes [sl.c_lo, sl.c_hi) from the per-patch rows held as in vanka_setup
+hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
+                          hipStream_t s);
 hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,
                     const cpx<double>* Af, cpx<double>* Ac, hipStream_t s);
 hipError_t restrict_(int dim, int rf, Grid gf, Grid gc, int prec, const void* r, void* rc,

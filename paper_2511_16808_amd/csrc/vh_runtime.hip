@@ -631,6 +631,68 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
 }
 
 // ---------------------------------------------------------------- setup
+// Geometry of the slabs in which the assembled smoother of a level is built: slabs are
+// runs of whole planes of the outermost axis (z in 3D, y in 2D).  The per-patch rows
+// of a slab of SZ output planes need the patches centred on SZ + 2 planes, whose
+// members span SZ + 4 planes.
+struct SlabPlan {
+  long long n_out, plane, plane_pad, SZ, cnt_max;
+  size_t per_plane;  // bytes of per-patch rows per plane
+  bool own;          // true: a temporary buffer, false: the caller's scratch area
+};
+
+SlabPlan slab_plan(int dim, const Grid& g, int Np, size_t esz, size_t scratch_bytes) {
+  SlabPlan p;
+  p.n_out = dim == 3 ? g.nz : g.ny;
+  p.plane = dim == 3 ? (long long)g.nx * g.ny : g.nx;
+  p.plane_pad = dim == 3 ? (long long)g.nxp * g.ny : g.nxp;
+  p.per_plane = (size_t)Np * Np * (size_t)p.plane_pad * esz;
+  p.SZ = (long long)(scratch_bytes / p.per_plane) - 4;
+  p.own = false;
+  if (p.SZ < 8 && p.SZ < p.n_out) {  // scratch too small: up to 16 planes at a time
+    p.SZ = p.n_out < 16 ? p.n_out : 16;
+    p.own = true;
+  }
+  if (p.SZ > p.n_out) p.SZ = p.n_out;
+  p.cnt_max = p.SZ + 4 < p.n_out ? p.SZ + 4 : p.n_out;
+  return p;
+}
+
+// Assembled smoother of level Lv built without holding the level's whole per-patch
+// array: each slab of output planes gets its patch inverses in the scratch area (the
+// patches centred within one plane of the slab), then its assembled rows.
+vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
+                         void* scratch, size_t scratch_bytes) {
+  const int dim = hd->dim;
+  const Grid& g = Lv.g;
+  hipStream_t s = hd->s;
+  const SlabPlan p = slab_plan(dim, g, Np, hd->esz, scratch_bytes);
+  void* buf = scratch;
+  if (p.own) VH_TRY(hd->alloc(&buf, (size_t)p.cnt_max * p.per_plane));
+  const size_t gstride = (size_t)p.cnt_max * p.plane_pad;
+  const int K5 = dim == 2 ? 25 : 125;
+  const size_t Npad = (size_t)g.Np;
+  VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * Npad * hd->esz));
+  VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));
+  for (long long p0 = 0; p0 < p.n_out; p0 += p.SZ) {
+    const long long p1 = p0 + p.SZ < p.n_out ? p0 + p.SZ : p.n_out;
+    const long long b0 = p0 - 2 > 0 ? p0 - 2 : 0;
+    const long long c0 = p0 - 1 > 0 ? p0 - 1 : 0, c1 = p1 + 1 < p.n_out ? p1 + 1 : p.n_out;
+    VH_HIP(fill(buf, (size_t)Np * Np * gstride, hd->prec, 0, 0, s));
+    VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, g, A, Lv.w, hd->prec, buf,
+                       Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
+    VH_HIP(vanka_assemble(dim, g, hd->prec, buf,
+                          Slab{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride}, Lv.B, s));
+  }
+  if (p.own) {
+    VH_HIP(hipStreamSynchronize(s));
+    hd->release(buf);
+    hd->bytes -= (size_t)p.cnt_max * p.per_plane;
+  }
+  Lv.E = K5;
+  return VH_OK;
+}
+
 vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   const int dim = hd->dim;
   const vh_options& o = hd->opt;
@@ -680,6 +742,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     VH_TRY(hd->alloc((void**)&A64[l + 1], (size_t)Lc.K * Lc.g.N * sizeof(cpx<double>)));
     VH_HIP(galerkin(dim, Lf.shape, Lc.shape, Lf.rf, Lf.pf, Lf.g, Lc.g, A64[l], A64[l + 1], s));
   }
+  // the FGMRES basis is allocated first: until the first solve it is the scratch
+  // area in which the assembled smoother is built slab by slab
+  hd->m = o.restart;
+  VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
   // per level: operator at the preconditioner precision, patch inverses, vectors
   const int Np = patch_size(dim, hd->patch);
   for (int l = 0; l < hd->levels; ++l) {
@@ -699,22 +765,14 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     VH_HIP(fill(Lv.r, N, hd->prec, 0, 0, s));
     Lv.bytes = ((size_t)Lv.K + 3) * N * hd->esz;
     if (l + 1 == hd->levels) break;
-    void* G = nullptr;
     const size_t Npad = (size_t)Lv.g.Np;  // smoother arrays use the padded row layout
-    VH_TRY(hd->alloc(&G, (size_t)Np * Np * Npad * hd->esz));
-    VH_HIP(fill(G, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
-    VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, Lv.g, A64[l], Lv.w, hd->prec, G, s));
     if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch == VH_PATCH_FULL) {
-      const int K5 = dim == 2 ? 25 : 125;
-      VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * Npad * hd->esz));
-      VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));
-      VH_HIP(vanka_assemble(dim, Lv.g, hd->prec, G, Lv.B, s));
-      VH_HIP(hipStreamSynchronize(s));
-      hd->release(G);
-      hd->bytes -= (size_t)Np * Np * Npad * hd->esz;
-      Lv.E = K5;
+      VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
     } else {
-      Lv.B = G;
+      VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
+      VH_HIP(fill(Lv.B, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
+      VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, Lv.g, A64[l], Lv.w, hd->prec, Lv.B,
+                         Slab{0, (long long)N, 0, Npad}, s));
       Lv.E = Np * Np;
     }
     Lv.bytes += (size_t)Lv.E * Npad * hd->esz;
@@ -745,13 +803,11 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
       hd->bytes -= (size_t)hd->L[l].K * hd->L[l].g.N * sizeof(cpx<double>);
       hd->release(A64[l]);
     }
-  // FGMRES workspace
-  hd->m = o.restart;
+  // FGMRES workspace (the basis V is already allocated)
   {
     long long nb = (long long)N0 / 512;
     hd->nred = (int)(nb < 64 ? 64 : (nb > 2048 ? 2048 : nb));
   }
-  VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc(&hd->Z, (size_t)hd->m * N0 * hd->esz));
   VH_TRY(hd->alloc((void**)&hd->part, (size_t)hd->nred * 65 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->K, sizeof(KrylovDev)));
@@ -1082,7 +1138,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   const int ig = resolve_intergrid(dim, o.intergrid);
   const int Np = patch_size(dim, patch);
   size_t nn[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
-  size_t total = 0, N0 = nn[0] * nn[1] * nn[2];
+  size_t total = 0, N0 = nn[0] * nn[1] * nn[2], slab_tmp = 0;
   int shape = CROSS;
   total += (size_t)(2 * dim + 1) * N0 * 16;  // unshifted H
   for (int l = 0; l < levels; ++l) {
@@ -1093,15 +1149,19 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
       total += N * N * 16;
       break;
     }
-    const int E = (o.smoother == VH_SMOOTHER_ASSEMBLED && patch == VH_PATCH_FULL)
-                      ? (dim == 2 ? 25 : 125)
-                      : Np * Np;
+    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && patch == VH_PATCH_FULL;
+    const int E = assembled ? (dim == 2 ? 25 : 125) : Np * Np;
     const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
     total += (size_t)E * Npad * esz;
+    if (assembled) {  // a temporary slab buffer when the basis is too small to hold one
+      const Grid g = make_grid(dim, (int)nn[0], (int)nn[1], (int)nn[2]);
+      const SlabPlan p = slab_plan(dim, g, Np, esz, (size_t)(o.restart + 1) * N0 * 16);
+      if (p.own && (size_t)p.cnt_max * p.per_plane > slab_tmp) slab_tmp = (size_t)p.cnt_max * p.per_plane;
+    }
     shape = (ig == VH_IG_LINEAR) ? BOX1 : BOX2;
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }
-  total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz;
+  total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz + slab_tmp;
   total += (size_t)2048 * 65 * 16 + sizeof(KrylovDev);
   if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
     size_t S = 1;

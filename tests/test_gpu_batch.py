@@ -80,11 +80,15 @@ def test_batch_zero_and_nonconverging_sources():
     assert st == B.VH_ENOCONV and stats[0]["iterations"] == 2 and not stats[0]["converged"]
 
 
-def test_batch_of_64_sources_2d_ragged_tile():
+@pytest.mark.parametrize("smoother", ["patch", "assembled"])
+def test_batch_of_64_sources_2d_ragged_tile(smoother):
     """64 sources on an 81^2 grid (81 nodes per row: five full 16-node row segments and a
-    one-node tail): every sampled source reaches the FP64 tolerance, and source 5 equals
-    the same source solved alone (1e-10, rounding of the batched dot products only)."""
-    c = Case(n=(81, 81), levels=3, alpha=0.3, medium="layered", seed=6, sponge_width=8)
+    one-node tail), per-patch and assembled smoother: every sampled source reaches the
+    FP64 tolerance, and source 5 equals the same source solved alone (1e-10, rounding of
+    the batched dot products only)."""
+    sm = B.VH_SMOOTHER_ASSEMBLED if smoother == "assembled" else B.VH_SMOOTHER_PATCH
+    c = Case(n=(81, 81), levels=3, alpha=0.3, medium="layered", seed=6, sponge_width=8,
+             smoother=sm)
     q = synth.random_sources(c.n, 64, seed=5, margin=9)
     st, stats, u = solve(c, q.ravel(), batch=1)
     assert st == B.VH_OK and len(stats) == 64

@@ -172,7 +172,8 @@ def kernel_sha(kernel):
     """Hash of the source text of one kernel template (from its declaration to the end
     of its body); counter-measured traffic is only reported for an unchanged kernel."""
     import hashlib
-    fname = "vh_batch.hip" if kernel.startswith("kb_") else "vh_kernels.hip"
+    fname = ("vh_mfma.hip" if kernel == "kb_sweep_mfma" else
+             "vh_batch.hip" if kernel.startswith("kb_") else "vh_kernels.hip")
     src = open(os.path.join(ROOT, "paper_2511_16808_amd", "csrc", fname)).read()
     a = src.find(f"void {kernel}(")
     if a < 0:
@@ -276,6 +277,9 @@ def main():
     ap.add_argument("--smoother", default="assembled", choices=["patch", "assembled"],
                     help="additive Vanka applied as stored patch inverses or as the same "
                          "operator assembled into a 5^d-point stencil (default)")
+    ap.add_argument("--contraction", default="valu", choices=["valu", "mfma_f32", "mfma_bf16x3"],
+                    help="batched per-patch smoother on the vector ALUs or the matrix cores "
+                         "(implies --smoother patch)")
     ap.add_argument("--batch", type=int, default=None, choices=[0, 1],
                     help="override: sources one after another (0) or sharing each sweep (1)")
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
@@ -316,13 +320,18 @@ def main():
     gt = torch.tensor(gamma.ravel(), dtype=torch.float64, device=dev)
     qt = torch.tensor(q, dtype=torch.complex128, device=dev)
     ut = torch.empty_like(qt)
+    contraction = {"valu": B.VH_CONTRACT_VALU, "mfma_f32": B.VH_CONTRACT_MFMA_F32,
+                   "mfma_bf16x3": B.VH_CONTRACT_MFMA_BF16X3}[args.contraction]
+    if contraction != B.VH_CONTRACT_VALU:
+        args.smoother = "patch"  # the matrix-core sweep applies the stored patch inverses
     smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
     nsrc = w.get("nsrc", 1)
     batch = w.get("batch", 0) if args.batch is None else args.batch
     precision = w["precision"] if args.precision is None else {"c128": 0, "c64": 1}[args.precision]
     opt = B.make_options(precision=precision, restart=w["restart"], damping=w["damping"],
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR,
-                         smoother=smoother, stream=stream, timing=1, batch=batch)
+                         smoother=smoother, stream=stream, timing=1, batch=batch,
+                         contraction=contraction)
     torch.cuda.synchronize()
 
     def step():
@@ -361,11 +370,14 @@ def main():
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
     if width == 1:
         kname = "k_vanka_sweep"
+    elif contraction != B.VH_CONTRACT_VALU and width >= 16:
+        kname = "kb_sweep_mfma"
     elif dim == 2:
         kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
     else:
         kname = "kb_sweep3d"
-    traffic = measured_traffic(f"{args.workload}_{'batch' if batch else args.smoother}", kname)
+    tkey = f"{args.workload}_{'batch_' + args.contraction if batch else args.smoother}"
+    traffic = measured_traffic(tkey, kname)
     vc_b = vcycle_bytes(info, dim, esz, E)
     vc_n = sum(r["stats"]["vcycles"] for r in runs)
     vc_ms = sum(r["stats"]["vcycle_ms"] for r in runs)
@@ -384,7 +396,8 @@ def main():
         "dtype": "c128" if precision == 0 else "c64+c128",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "nodes": N, "levels": w["levels"],
-                   "smoother": args.smoother, "sources": nsrc, "batched": bool(batch)},
+                   "smoother": args.smoother, "sources": nsrc, "batched": bool(batch),
+                   "contraction": args.contraction},
         "iterations": st["iterations"] if nsrc == 1 else
         {"mean": float(np.mean(its_all)), "min": int(min(its_all)), "max": int(max(its_all))},
         "converged": all(x["converged"] for x in last["all_stats"]) and

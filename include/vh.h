@@ -70,6 +70,16 @@ typedef int vh_status;
 #define VH_SMOOTHER_PATCH 0     /* per-patch inverses, [Np*Np][node]; block multiply + weighted overlap-add */
 #define VH_SMOOTHER_ASSEMBLED 1 /* the same operator summed into a 5^d-point stencil at setup */
 
+/* Batched smoother contraction (vh_options.contraction).  The per-patch product
+ * E_c = A_c^{-1} [r_c^(1..S)] of eq. (smoother) for S >= 16 sources sharing a sweep:
+ *   VALU        complex64 FMAs on the vector ALUs (every configuration)
+ *   MFMA_F32    real-embedded [S x 18] . [18 x 18] products on the matrix cores, FP32
+ *   MFMA_BF16X3 the same in split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation;
+ *               about 2^-16 relative error per product on top of complex64 rounding. */
+#define VH_CONTRACT_VALU 0
+#define VH_CONTRACT_MFMA_F32 1
+#define VH_CONTRACT_MFMA_BF16X3 2
+
 typedef struct vh_options {
     int precision;          /* VH_PREC_*; default VH_PREC_FP64                         */
     int restart;            /* FGMRES restart length m; default 20                     */
@@ -90,6 +100,9 @@ typedef struct vh_options {
                                1: in groups of up to 64 sources that share every V-cycle
                                sweep (each coefficient and patch-inverse entry is read once
                                per group), each source with its own FP64 FGMRES state    */
+    int contraction;        /* VH_CONTRACT_*: how a batch of >= 16 sources applies the
+                               per-patch smoother (2D, Full patch, VH_SMOOTHER_PATCH,
+                               VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -114,6 +127,9 @@ typedef struct vh_level_info {
     int smoother_entries;   /* Np*Np (patch form) or 5^d (assembled) per node          */
     int offsets[125][3];    /* stencil offsets, K used entries                          */
     size_t bytes;           /* device bytes owned by this level                        */
+    int mfma_sources;       /* batch width the matrix-core sweep was tuned for (0: none) */
+    int mfma_tile;          /* patches per strip row chosen by the tuner (16 or 32)      */
+    int mfma_rows;          /* rows per block chosen by the tuner                        */
 } vh_level_info;
 
 typedef struct vh_handle vh_handle;
@@ -175,6 +191,14 @@ vh_status vh_apply_vcycle(vh_handle *hd, const void *v, void *z);
 /* u <- u + B_l (q - A_l u) on level l (one damped smoothing step, eq. (smoother));
  * q, u device c128[N_l]. */
 vh_status vh_apply_smoother(vh_handle *hd, int level, const void *q, void *u);
+
+/* The multi-source forms of the two hooks above, through the batched kernels that
+ * vh_solve uses with vh_options.batch = 1 (and vh_options.contraction):
+ *   q, u, v, z : device c128[nsrc][N_l] (source-major, as in vh_solve), 1 <= nsrc <= 64.
+ * vh_apply_smoother_batch: u_s <- u_s + B_l (q_s - A_l u_s) for every source s;
+ * vh_apply_vcycle_batch:   z_s = M^{-1} v_s (one V-cycle from zero) for every source. */
+vh_status vh_apply_smoother_batch(vh_handle *hd, int level, int nsrc, const void *q, void *u);
+vh_status vh_apply_vcycle_batch(vh_handle *hd, int nsrc, const void *v, void *z);
 
 /* Copies level data to HOST buffers (each may be NULL):
  *   coef : c128[K][N]  operator coefficients (H_s^level)

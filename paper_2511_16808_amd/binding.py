@@ -30,6 +30,9 @@ VH_BC_ABC = 0
 VH_BC_DIRICHLET = 1
 VH_SMOOTHER_PATCH = 0
 VH_SMOOTHER_ASSEMBLED = 1
+VH_CONTRACT_VALU = 0
+VH_CONTRACT_MFMA_F32 = 1
+VH_CONTRACT_MFMA_BF16X3 = 2
 
 
 class vh_options(ctypes.Structure):
@@ -39,7 +42,7 @@ class vh_options(ctypes.Structure):
         ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
         ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
         ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
-        ("batch", ctypes.c_int),
+        ("batch", ctypes.c_int), ("contraction", ctypes.c_int),
     ]
 
 
@@ -60,7 +63,8 @@ class vh_level_info(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int * 3), ("stencil_points", ctypes.c_int),
         ("smoother_entries", ctypes.c_int), ("offsets", (ctypes.c_int * 3) * 125),
-        ("bytes", ctypes.c_size_t),
+        ("bytes", ctypes.c_size_t), ("mfma_sources", ctypes.c_int), ("mfma_tile", ctypes.c_int),
+        ("mfma_rows", ctypes.c_int),
     ]
 
 
@@ -106,6 +110,8 @@ _SIGNATURES = {
     "vh_apply_operator": (_I, [_P, _I, _I, _P, _P]),
     "vh_apply_vcycle": (_I, [_P, _P, _P]),
     "vh_apply_smoother": (_I, [_P, _I, _P, _P]),
+    "vh_apply_smoother_batch": (_I, [_P, _I, _I, _P, _P]),
+    "vh_apply_vcycle_batch": (_I, [_P, _I, _P, _P]),
     "vh_export_level": (_I, [_P, _I, _P, _P, _P]),
     "vh_sample_level": (_I, [_P, _I, _I, _I, _P, _P]),
     "vh_footprint_bytes": (ctypes.c_size_t, [_I, ctypes.POINTER(_I), _I, _I, _I,
@@ -211,6 +217,8 @@ def vh_get_level_info(hd, level):
     return {
         "n": tuple(info.n), "stencil_points": K, "smoother_entries": info.smoother_entries,
         "offsets": [tuple(info.offsets[k]) for k in range(K)], "bytes": info.bytes,
+        "mfma_sources": info.mfma_sources, "mfma_tile": info.mfma_tile,
+        "mfma_rows": info.mfma_rows,
     }
 
 
@@ -224,6 +232,15 @@ def vh_apply_vcycle(hd, v, z):
 
 def vh_apply_smoother(hd, level, q, u):
     check(lib().vh_apply_smoother(hd, level, _ptr(q, "complex128"), _ptr(u, "complex128")))
+
+
+def vh_apply_smoother_batch(hd, level, nsrc, q, u):
+    check(lib().vh_apply_smoother_batch(hd, level, nsrc, _ptr(q, "complex128"),
+                                        _ptr(u, "complex128")))
+
+
+def vh_apply_vcycle_batch(hd, nsrc, v, z):
+    check(lib().vh_apply_vcycle_batch(hd, nsrc, _ptr(v, "complex128"), _ptr(z, "complex128")))
 
 
 def vh_export_level(hd, level, coef=None, smoother=None, coarse_inv=None):

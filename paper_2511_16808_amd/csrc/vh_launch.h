@@ -100,6 +100,10 @@ hipError_t batch_scatter(long long N, int S, int nsrc, const cpx<double>* X, cpx
                          hipStream_t st);
 hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,
                          int px, const void* x, int py, const void* b, void* y, hipStream_t st);
+// batched 2D Full-patch sweep on MFMA (1 << ls sources, ls in 4..6, complex64):
+// split = 0 FP32, 1 split BF16; txp = 16 or 32 patches per strip row; rows per block
+hipError_t batch_sweep_mfma(Grid g, int ls, int split, int txp, int rows, const void* G,
+                            const void* r, void* u, bool zero, hipStream_t st);
 hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* G, const void* r,
                        void* u, bool zero, hipStream_t st);
 hipError_t batch_restrict(int dim, int rf, Grid gf, Grid gc, int ls, int prec, const void* r,

@@ -60,6 +60,8 @@ struct Level {
   int rf = FAM_LINEAR, pf = FAM_LINEAR;  // transfers to level l+1
   double w = 1.0;                         // damping
   size_t bytes = 0;
+  int mfma_txp[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned matrix-core sweep tile per log2(S)
+  int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 }  // namespace
@@ -225,6 +227,14 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
     return fail(VH_EINVAL, "unknown smoother");
   if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
+  if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
+    return fail(VH_EINVAL, "unknown contraction");
+  if (o.contraction != VH_CONTRACT_VALU &&
+      (dim != 2 || patch != VH_PATCH_FULL || o.smoother != VH_SMOOTHER_PATCH ||
+       o.precision != VH_PREC_C64))
+    return fail(VH_EUNSUPPORTED,
+                "the matrix-core contraction needs dim 2, the Full patch, the per-patch "
+                "smoother and the complex64 preconditioner");
   // the coarsest level is solved by a dense inverse
   long long nc = 1;
   for (int d = 0; d < dim; ++d) nc *= (n[d] - 1) / (1LL << (levels - 1)) + 1;
@@ -460,9 +470,75 @@ vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zer
   const int tk = (l == 0) ? hd->tbegin(zero ? 0 : 1) : -1;
   const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2
                    : (hd->patch == VH_PATCH_FULL ? 0 : 1);
-  VH_HIP(batch_sweep(hd->dim, form, Lv.g, ls, hd->prec, Lv.B, r, u, zero, hd->s));
+  if (Lv.mfma_txp[ls])
+    VH_HIP(batch_sweep_mfma(Lv.g, ls, hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3,
+                            Lv.mfma_txp[ls], Lv.mfma_rows[ls], Lv.B, r, u, zero, hd->s));
+  else
+    VH_HIP(batch_sweep(hd->dim, form, Lv.g, ls, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
   return VH_OK;
+}
+
+// Tile choice of the matrix-core sweep for every smoothed level and batch width S:
+// each candidate (patches per strip row, about 1, 2 or 4 blocks per CU) is timed on the
+// level's own grid with HIP events, the fastest kept.  Runs once per handle and S, so
+// repeated solves with one handle take the same tiles (and give the same bits).
+vh_status tune_mfma(vh_handle* hd, int ls) {
+  const int S = 1 << ls;
+  if (hd->opt.contraction == VH_CONTRACT_VALU || ls < 4) return VH_OK;
+  int dev = 0, ncu = 256;
+  VH_HIP(hipGetDevice(&dev));
+  VH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int split = hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3;
+  hipEvent_t e0, e1;
+  VH_HIP(hipEventCreate(&e0));
+  VH_HIP(hipEventCreate(&e1));
+  vh_status st = VH_OK;
+  for (int l = 0; l + 1 < hd->levels && st == VH_OK; ++l) {
+    Level& Lv = hd->L[l];
+    if (Lv.mfma_txp[ls]) continue;
+    const size_t NS = (size_t)Lv.g.N * S;
+    if (fill(hd->br[l], NS, hd->prec, 0, 0, hd->s) != hipSuccess) { st = VH_EDEVICE; break; }
+    float best = 1e30f;
+    int btxp = 16, brows = Lv.g.ny;
+    for (int txp : {16, 32}) {
+      const long long nstrip = (Lv.g.nx + txp - 3) / (txp - 2);
+      for (int per_cu : {1, 2, 4}) {
+        long long nchunk = (long long)per_cu * ncu / nstrip;
+        if (nchunk < 1) nchunk = 1;
+        if (nchunk > Lv.g.ny) nchunk = Lv.g.ny;
+        const int rows = (int)((Lv.g.ny + nchunk - 1) / nchunk);
+        float ms = 0.f;
+        hipError_t e = batch_sweep_mfma(Lv.g, ls, split, txp, rows, Lv.B, hd->br[l], hd->bu[l],
+                                        true, hd->s);
+        if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k)
+          e = batch_sweep_mfma(Lv.g, ls, split, txp, rows, Lv.B, hd->br[l], hd->bu[l], true,
+                               hd->s);
+        if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          continue;  // a tile that does not launch here is not a candidate
+        }
+        if (ms < best) {
+          best = ms;
+          btxp = txp;
+          brows = rows;
+        }
+      }
+    }
+    if (best >= 1e30f) {
+      st = fail(VH_EDEVICE, "no matrix-core sweep tile launches on this device");
+      break;
+    }
+    Lv.mfma_txp[ls] = btxp;
+    Lv.mfma_rows[ls] = brows;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, void* r) {
@@ -519,6 +595,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
   while ((1 << ls) < nsrc) ++ls;
   const int S = 1 << ls;
   VH_TRY(ensure_batch(hd, S));
+  VH_TRY(tune_mfma(hd, ls));
   const long long N = hd->L[0].g.N;
   const int m = hd->m;
   const size_t ldv = (size_t)N * S;
@@ -997,6 +1074,13 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->smoother_entries = Lv.E;
   shape_offsets(hd->dim, Lv.shape, Lv.K, info->offsets);
   info->bytes = Lv.bytes;
+  for (int ls = 6; ls >= 0; --ls)
+    if (Lv.mfma_txp[ls]) {
+      info->mfma_sources = 1 << ls;
+      info->mfma_tile = Lv.mfma_txp[ls];
+      info->mfma_rows = Lv.mfma_rows[ls];
+      break;
+    }
   return VH_OK;
 }
 
@@ -1050,6 +1134,54 @@ vh_status vh_apply_smoother(vh_handle* hd, int level, const void* q, void* u) {
     VH_TRY(smooth(hd, Lv, Lv.r, Lv.u, false));
     VH_HIP(convert(Lv.u, hd->prec, u, PREC_F64, N, hd->s));
   }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+namespace {
+int batch_log2(int nsrc) {
+  int ls = 0;
+  while ((1 << ls) < nsrc) ++ls;
+  return ls;
+}
+// source-major c128 [nsrc][n] -> node-major [n][S] at the preconditioner precision in dst
+vh_status to_batch(vh_handle* hd, long long n, int S, int nsrc, const void* src, void* dst) {
+  VH_HIP(batch_gather(n, S, nsrc, (const cpx<double>*)src, hd->bQ, hd->s));
+  VH_HIP(convert(hd->bQ, PREC_F64, dst, hd->prec, (size_t)n * S, hd->s));
+  return VH_OK;
+}
+vh_status from_batch(vh_handle* hd, long long n, int S, int nsrc, const void* src, void* dst) {
+  VH_HIP(convert(src, hd->prec, hd->bX, PREC_F64, (size_t)n * S, hd->s));
+  VH_HIP(batch_scatter(n, S, nsrc, hd->bX, (cpx<double>*)dst, hd->s));
+  return VH_OK;
+}
+}  // namespace
+
+vh_status vh_apply_smoother_batch(vh_handle* hd, int level, int nsrc, const void* q, void* u) {
+  if (!hd || !q || !u || level < 0 || level + 1 >= hd->levels || nsrc < 1 || nsrc > 64)
+    return fail(VH_EINVAL, "bad argument (1 <= nsrc <= 64; the coarsest level has no smoother)");
+  const int ls = batch_log2(nsrc), S = 1 << ls;
+  VH_TRY(ensure_batch(hd, S));
+  VH_TRY(tune_mfma(hd, ls));
+  const long long n = hd->L[level].g.N;
+  VH_TRY(to_batch(hd, n, S, nsrc, q, hd->bq[level]));
+  VH_TRY(to_batch(hd, n, S, nsrc, u, hd->bu[level]));
+  VH_TRY(bresidual(hd, level, ls, hd->bq[level], hd->bu[level], hd->br[level]));
+  VH_TRY(bsmooth(hd, level, ls, hd->br[level], hd->bu[level], false));
+  VH_TRY(from_batch(hd, n, S, nsrc, hd->bu[level], u));
+  VH_HIP(hipStreamSynchronize(hd->s));
+  return VH_OK;
+}
+
+vh_status vh_apply_vcycle_batch(vh_handle* hd, int nsrc, const void* v, void* z) {
+  if (!hd || !v || !z || nsrc < 1 || nsrc > 64) return fail(VH_EINVAL, "bad argument (1 <= nsrc <= 64)");
+  const int ls = batch_log2(nsrc), S = 1 << ls;
+  VH_TRY(ensure_batch(hd, S));
+  VH_TRY(tune_mfma(hd, ls));
+  const long long n = hd->L[0].g.N;
+  VH_TRY(to_batch(hd, n, S, nsrc, v, hd->bq[0]));
+  VH_TRY(vcycle_b(hd, 0, ls, hd->bq[0], hd->bZ));
+  VH_TRY(from_batch(hd, n, S, nsrc, hd->bZ, z));
   VH_HIP(hipStreamSynchronize(hd->s));
   return VH_OK;
 }

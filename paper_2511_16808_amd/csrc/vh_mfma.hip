@@ -37,7 +37,6 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MW = 4;    // wavefronts per block
 constexpr int NPM = 9;   // members of a Full 3x3 patch
-constexpr int MPAD = 12; // member slots per staged inverse row (16-byte aligned runs of 4)
 
 // (re, im) -> bf16 pair, re in the low half (round to nearest even)
 __device__ __forceinline__ unsigned bf16_pair(float a, float b) {
@@ -54,6 +53,14 @@ __device__ __forceinline__ uint2 float_pair(float a, float b) {
   return make_uint2(__float_as_uint(a), __float_as_uint(b));
 }
 
+// Workgroup barrier that orders LDS only: global loads issued before it (the next
+// row's prefetch) stay in flight across it, where __syncthreads would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ bool inside2(const Grid& g, int x, int y) {
   return (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
 }
@@ -65,69 +72,143 @@ __global__ __launch_bounds__(256) void kb_sweep_mfma(Grid g, int rows,
                                                      const cpx<float>* __restrict__ G,
                                                      const cpx<float>* __restrict__ r,
                                                      cpx<float>* __restrict__ u) {
-  constexpr int S = 1 << LS, MT = S / 16;  // M tiles of 16 sources
+  constexpr int S = 1 << LS, MT = S / 16;  // source tiles of 16
   constexpr int TX = TXP - 2, RC = TXP + 2, SUB = TXP / MW;
   static_assert(SUB >= 3, "patches added together must be >= 3 columns apart");
+  constexpr int SP = S + 2;            // LDS stride of one node (16 B of padding)
+  constexpr int RS = RC * SP;          // residual ring: stride of one row
+  constexpr int US = TX * SP;          // accumulator ring: stride of one row
+  constexpr int NROW = 2 * NPM;        // rows (a, ro) of the embedded inverse
+  constexpr int GPS = 3 * NROW * 4 + 2;  // staged inverse of one patch: [grp][row][4]
   constexpr int NR = (RC * S + 255) / 256;           // residual row elements per thread
   constexpr int NG = (TXP * NPM * NPM + 255) / 256;  // inverse entries per thread
-  __shared__ uint2 rr[3][RC][S];              // residual ring (split or FP32 bits)
-  __shared__ __align__(16) uint2 gb[TXP][2][NPM][MPAD];  // B entries: patch, version ro, row a
-  __shared__ float2 ua[3][TX][S];             // overlap-add accumulator ring
+  constexpr int ZR = 3 * RS;           // S zero residuals (members outside the patch)
+  constexpr int ZA = TXP * GPS;        // 4 zero inverse entries (rows past the 18)
+  constexpr int NU = (TX * S + 255) / 256;  // output row elements per thread
+  __shared__ uint2 rr[3 * RS + S];                 // residual ring (split or FP32 bits)
+  __shared__ __align__(16) uint2 gb[TXP * GPS + 4];  // A operands per patch
+  __shared__ float2 ua[3 * US];                    // overlap-add ring
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int grp = lane >> 4, l16 = lane & 15;
   const int nstrip = (g.nx + TX - 1) / TX;
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   const int x0 = (int)(b % (unsigned)nstrip) * TX;
   const int yb = (int)(b / (unsigned)nstrip) * rows;
   if (yb >= g.ny) return;  // whole block
   const int ye = yb + rows < g.ny ? yb + rows : g.ny;
+  const int xe = x0 + TX < g.nx ? x0 + TX : g.nx;
   const int py_lo = yb > 0 ? yb - 1 : 0, py_hi = ye < g.ny - 1 ? ye : g.ny - 1;
-  const size_t Np = (size_t)g.Np;
+  const size_t rowS = (size_t)g.nx * S;  // elements of one grid row of a batch vector
 
-  for (int e = tid; e < 3 * TX * S; e += 256) (&ua[0][0][0])[e] = make_float2(0.f, 0.f);
-  for (int e = tid; e < TXP * 2 * NPM * MPAD; e += 256) (&gb[0][0][0][0])[e] = make_uint2(0, 0);
+  for (int e = tid; e < 3 * US; e += 256) ua[e] = make_float2(0.f, 0.f);
+  for (int e = tid; e < TXP * GPS + 4; e += 256) gb[e] = make_uint2(0, 0);
+  for (int e = tid; e < S; e += 256) rr[ZR + e] = make_uint2(0, 0);
 
-  cpx<float> rv[NR], gv[NG];
-  auto load_row = [&](int y) {
+  // ---- per-lane operand constants
+  // A operand (inverse rows): row 16 tm + l16 of the 18 rows; the split form reads members
+  // 4 grp .. 4 grp + 3 (grp 3 only padding), the FP32 form one (m, ri) per step.  Lanes
+  // without a row read the zero block.
+  int arow[2];
+  bool aok[2];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int e = tid + 256 * i, col = e >> LS, s = e & (S - 1);
-      const int x = x0 - 2 + col;
-      rv[i] = (e < RC * S && inside2(g, x, y)) ? r[((size_t)y * g.nx + x) * S + s]
-                                                : cmk(0.f, 0.f);
+  for (int tm = 0; tm < 2; ++tm) {
+    const int row = 16 * tm + l16;
+    aok[tm] = row < NROW && (!SPLIT || grp < 3);
+    arow[tm] = ((SPLIT ? grp : 0) * NROW + row) * 4;
+  }
+  // B operand (member residuals): member m = 4 grp + jj (split) or (4 st + grp) / 2;
+  // members past the ninth read the zero residuals
+  constexpr int NB = SPLIT ? 4 : 5;
+  int bdx[NB], bdy[NB];
+  bool bok[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int m = SPLIT ? 4 * grp + k : (4 * k + grp) >> 1;
+    const int mc = m < NPM ? m : NPM - 1;
+    bdx[k] = mc % 3 - 1;
+    bdy[k] = mc / 3 - 1;
+    bok[k] = m < NPM;
+  }
+  // outputs a = 8 tm + 2 grp + h2 held by this lane
+  int odx[2][2], ody[2][2];
+  bool ook[2][2];
+#pragma unroll
+  for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int a = 8 * tm + 2 * grp + h2, ac = a < NPM ? a : NPM - 1;
+      odx[tm][h2] = ac % 3 - 1;
+      ody[tm][h2] = ac / 3 - 1;
+      ook[tm][h2] = a < NPM;
     }
+
+  // ---- per-thread staging constants (the rows change, the columns do not)
+  int r_goff[NR], r_ldst[NR];
+  bool r_ok[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int e = tid + 256 * i, col = e >> LS, sl = e & (S - 1), x = x0 - 2 + col;
+    r_ok[i] = e < RC * S && (unsigned)x < (unsigned)g.nx;
+    r_goff[i] = x * S + sl;
+    r_ldst[i] = col * SP + sl;
+  }
+  size_t g_goff[NG];
+  int g_dy[NG], g_ldst[NG];
+  bool g_ok[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int e = tid + 256 * i, p = e % TXP, q = e / TXP, a = q / NPM, m = q % NPM;
+    const int px = x0 - 1 + p, x = px + a % 3 - 1;
+    g_ok[i] = e < TXP * NPM * NPM && (unsigned)px < (unsigned)g.nx && (unsigned)x < (unsigned)g.nx;
+    g_goff[i] = (size_t)q * g.Np + (size_t)(g_ok[i] ? x : 0);
+    g_dy[i] = a / 3 - 1;
+    g_ldst[i] = p * GPS + ((m >> 2) * NROW + 2 * a) * 4 + (m & 3);
+  }
+  int u_goff[NU], u_lsrc[NU];
+  bool u_ok[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    const int e = tid + 256 * i, col = e >> LS, sl = e & (S - 1), x = x0 + col;
+    u_ok[i] = e < TX * S && x < g.nx;
+    u_goff[i] = x * S + sl;
+    u_lsrc[i] = col * SP + sl;
+  }
+
+  cpx<float> rv[NR], gv[NG], uv[NU];
+  auto load_row = [&](int y) {
+    const bool yok = (unsigned)y < (unsigned)g.ny;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+      rv[i] = (yok && r_ok[i]) ? r[(size_t)y * rowS + r_goff[i]] : cmk(0.f, 0.f);
   };
   auto store_row = [&](int y) {
-    uint2* dst = &rr[(y + 3) % 3][0][0];
+    uint2* dst = rr + ((y + 3) % 3) * RS;
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int e = tid + 256 * i;
-      if (e < RC * S)
-        dst[e] = SPLIT ? split_pair(rv[i].re, rv[i].im) : float_pair(rv[i].re, rv[i].im);
-    }
+    for (int i = 0; i < NR; ++i)
+      if (tid + 256 * i < RC * S)
+        dst[r_ldst[i]] = SPLIT ? split_pair(rv[i].re, rv[i].im) : float_pair(rv[i].re, rv[i].im);
   };
   auto load_g = [&](int py) {
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-      const int e = tid + 256 * i, p = e % TXP, q = e / TXP;
-      const int a = q / NPM;
-      const int px = x0 - 1 + p, x = px + a % 3 - 1, y = py + a / 3 - 1;
-      gv[i] = (e < TXP * NPM * NPM && (unsigned)px < (unsigned)g.nx && inside2(g, x, y))
-                  ? G[(size_t)q * Np + (size_t)x + (size_t)g.nxp * y]
+      const int y = py + g_dy[i];
+      gv[i] = (g_ok[i] && (unsigned)y < (unsigned)g.ny)
+                  ? G[g_goff[i] + (size_t)g.nxp * (size_t)y]
                   : cmk(0.f, 0.f);
     }
   };
+  // entry (a, m) -> rows (a, 0) = (Ar, -Ai) and (a, 1) = (Ai, Ar) at member slot m
   auto store_g = [&]() {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) {
-      const int e = tid + 256 * i, p = e % TXP, q = e / TXP;
-      if (e < TXP * NPM * NPM) {
-        const int a = q / NPM, m = q % NPM;
+    for (int i = 0; i < NG; ++i)
+      if (tid + 256 * i < TXP * NPM * NPM) {
         const float ar = gv[i].re, ai = gv[i].im;
-        gb[p][0][a][m] = SPLIT ? split_pair(ar, -ai) : float_pair(ar, -ai);
-        gb[p][1][a][m] = SPLIT ? split_pair(ai, ar) : float_pair(ai, ar);
+        gb[g_ldst[i]] = SPLIT ? split_pair(ar, -ai) : float_pair(ar, -ai);
+        gb[g_ldst[i] + 4] = SPLIT ? split_pair(ai, ar) : float_pair(ai, ar);
       }
-    }
   };
+  const unsigned* rr32 = reinterpret_cast<const unsigned*>(rr);
+  const unsigned* gb32 = reinterpret_cast<const unsigned*>(gb);
 
   load_row(py_lo - 1);
   store_row(py_lo - 1);
@@ -136,53 +217,65 @@ __global__ __launch_bounds__(256) void kb_sweep_mfma(Grid g, int rows,
   load_row(py_lo + 1);
   load_g(py_lo);
 
-  const int grp = lane >> 4, l16 = lane & 15;
   for (int py = py_lo; py <= py_hi; ++py) {
-    __syncthreads();  // the previous row is done with ring slot (py + 1) % 3 and gb
+    lds_barrier();  // the previous row is done with ring slot (py + 1) % 3 and gb
     store_row(py + 1);
     store_g();
-    __syncthreads();
+    lds_barrier();
     if (py < py_hi) {
       load_row(py + 2);
       load_g(py + 1);
     }
+    const int yo = py - 1;  // output row completed by this patch row
+    const bool fin = yo >= yb && yo < ye;
+    if (!ZERO && fin) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i)
+        uv[i] = u_ok[i] ? u[(size_t)yo * rowS + u_goff[i]] : cmk(0.f, 0.f);
+    }
+    // ring offsets of this row: residual members, and kept outputs
+    int rb[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      rb[k] = ((py + bdy[k] + 3) % 3) * RS + (1 + bdx[k]) * SP + l16;
+    int ob[2][2];
+    bool orow[2][2];
+#pragma unroll
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int y = py + ody[tm][h2];
+        orow[tm][h2] = ook[tm][h2] && y >= yb && y < ye;
+        ob[tm][h2] = ((y + 3) % 3) * US + (odx[tm][h2] - x0) * SP + l16;
+      }
     for (int j = 0; j < SUB; ++j) {
       const int p = j + SUB * wv, px = x0 - 1 + p;
       if ((unsigned)px < (unsigned)g.nx) {  // uniform over the wavefront
-        // MFMA operands: A = patch matrix, rows (a, ro) = 16 tm + l16 (tm = 1 holds only
-        // a = 8), columns k = (m, ri); B = residuals, rows k, columns = sources 16 tn + l16.
-        // Lane group grp holds k = 8 grp .. 8 grp + 7, i.e. members 4 grp .. 4 grp + 3.
         f32x4 acc[2][MT];
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[0][t] = acc[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        int ab[2], bb[NB];
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) ab[tm] = aok[tm] ? p * GPS + arow[tm] : ZA;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) bb[k] = bok[k] ? rb[k] + p * SP : ZR + l16;
         if constexpr (SPLIT) {
           bf16x8 ah[2], al[2];
 #pragma unroll
           for (int tm = 0; tm < 2; ++tm) {
-            const int row = 16 * tm + l16, a = row >> 1, ro = row & 1;
-            u32x4 h = {0, 0, 0, 0}, lo = {0, 0, 0, 0};
-            if (a < NPM && grp < 3) {
-              const uint4* src = reinterpret_cast<const uint4*>(&gb[p][ro][a][4 * grp]);
-              const uint4 v0 = src[0], v1 = src[1];
-              h = u32x4{v0.x, v0.z, v1.x, v1.z};
-              lo = u32x4{v0.y, v0.w, v1.y, v1.w};
-            }
-            ah[tm] = __builtin_bit_cast(bf16x8, h);
-            al[tm] = __builtin_bit_cast(bf16x8, lo);
+            const uint4* src = reinterpret_cast<const uint4*>(gb + ab[tm]);
+            const uint4 v0 = src[0], v1 = src[1];
+            ah[tm] = __builtin_bit_cast(bf16x8, u32x4{v0.x, v0.z, v1.x, v1.z});
+            al[tm] = __builtin_bit_cast(bf16x8, u32x4{v0.y, v0.w, v1.y, v1.w});
           }
 #pragma unroll
           for (int t = 0; t < MT; ++t) {
-            const int s = 16 * t + l16;
-            u32x4 h = {0, 0, 0, 0}, lo = {0, 0, 0, 0};
+            u32x4 h, lo;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              const int m = 4 * grp + jj;
-              if (m < NPM) {
-                const int dx = m % 3 - 1, dy = m / 3 - 1;
-                const uint2 v = rr[(py + dy + 3) % 3][p + 1 + dx][s];
-                h[jj] = v.x;
-                lo[jj] = v.y;
-              }
+            for (int k = 0; k < 4; ++k) {
+              const uint2 v = rr[bb[k] + 16 * t];
+              h[k] = v.x;
+              lo[k] = v.y;
             }
             const bf16x8 bh = __builtin_bit_cast(bf16x8, h), bl = __builtin_bit_cast(bf16x8, lo);
 #pragma unroll
@@ -193,68 +286,59 @@ __global__ __launch_bounds__(256) void kb_sweep_mfma(Grid g, int rows,
             }
           }
         } else {
-          // FP32: K = 18 in 5 steps of 4; lane holds k = 4 st + grp
+          // K = 18 in 5 steps of 4: lane holds k = 4 st + grp, member k / 2, part k % 2
+          // (k = 18, 19 fall on the zero padding of member slot 9)
+          const int ri = grp & 1;
 #pragma unroll
           for (int st = 0; st < 5; ++st) {
-            const int k = 4 * st + grp, m = k >> 1, ri = k & 1;
+            const int m = (4 * st + grp) >> 1;
             float ak[2];
 #pragma unroll
             for (int tm = 0; tm < 2; ++tm) {
-              const int row = 16 * tm + l16, a = row >> 1, ro = row & 1;
-              ak[tm] = 0.f;
-              if (a < NPM && m < NPM) {
-                const uint2 v = gb[p][ro][a][m];
-                ak[tm] = __uint_as_float(ri ? v.y : v.x);
-              }
+              const int w = aok[tm] ? 2 * (ab[tm] + (m >> 2) * NROW * 4 + (m & 3)) + ri : 2 * ZA;
+              ak[tm] = __uint_as_float(gb32[w]);
             }
-            const int dx = m % 3 - 1, dy = m / 3 - 1;
 #pragma unroll
             for (int t = 0; t < MT; ++t) {
-              float bk = 0.f;
-              if (m < NPM) {
-                const uint2 v = rr[(py + dy + 3) % 3][p + 1 + dx][16 * t + l16];
-                bk = __uint_as_float(ri ? v.y : v.x);
-              }
+              const float bk = __uint_as_float(rr32[2 * (bb[st] + 16 * t) + ri]);
 #pragma unroll
               for (int tm = 0; tm < 2; ++tm)
                 acc[tm][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[tm], bk, acc[tm][t], 0, 0, 0);
             }
           }
         }
-        // overlap-add: lane holds rows 16 tm + 4 grp + i of E, i.e. (re, im) of outputs
-        // a = 8 tm + 2 grp and a + 1, for source 16 t + l16: contiguous float2 runs
+        // overlap-add: lane holds (re, im) of outputs a = 8 tm + 2 grp + h2 for sources
+        // 16 t + l16 (contiguous float2 runs); only lanes whose output node is kept touch
+        // LDS (a = 9 .. 15 never exist, a = 8 lives in lane group 0)
 #pragma unroll
-        for (int tm = 0; tm < 2; ++tm) {
+        for (int tm = 0; tm < 2; ++tm)
 #pragma unroll
-          for (int h2 = 0; h2 < 2; ++h2) {
-            const int a = 8 * tm + 2 * grp + h2;
-            if (a < NPM) {
-              const int x = px + a % 3 - 1, y = py + a / 3 - 1;
-              if (x >= x0 && x < x0 + TX && x < g.nx && y >= yb && y < ye) {
-                float2* dst = &ua[y % 3][x - x0][0];
+          for (int h2 = 0; h2 < (tm == 0 ? 2 : 1); ++h2) {
+            const int x = px + odx[tm][h2];
+            if (orow[tm][h2] && x >= x0 && x < xe) {
+              float2* dst = ua + ob[tm][h2] + px * SP;
 #pragma unroll
-                for (int t = 0; t < MT; ++t) {
-                  float2& d = dst[16 * t + l16];
-                  d = make_float2(d.x + acc[tm][t][2 * h2], d.y + acc[tm][t][2 * h2 + 1]);
-                }
+              for (int t = 0; t < MT; ++t) {
+                float2& d = dst[16 * t];
+                d = make_float2(d.x + acc[tm][t][2 * h2], d.y + acc[tm][t][2 * h2 + 1]);
               }
             }
           }
-        }
       }
-      __syncthreads();
+      lds_barrier();
     }
     // output row py - 1 has all its contributions
-    const int yo = py - 1;
-    if (yo >= yb && yo < ye) {
-      for (int e = tid; e < TX * S; e += 256) {
-        const int col = e >> LS, s = e & (S - 1), x = x0 + col;
-        float2& a = ua[yo % 3][col][s];
-        if (x < g.nx) {
-          cpx<float>& o = u[((size_t)yo * g.nx + x) * S + s];
-          o = ZERO ? cmk(a.x, a.y) : cmk(o.re + a.x, o.im + a.y);
+    if (fin) {
+      float2* row = ua + (yo % 3) * US;
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        if (tid + 256 * i < TX * S) {
+          float2& a = row[u_lsrc[i]];
+          if (u_ok[i])
+            u[(size_t)yo * rowS + u_goff[i]] =
+                ZERO ? cmk(a.x, a.y) : cmk(uv[i].re + a.x, uv[i].im + a.y);
+          a = make_float2(0.f, 0.f);
         }
-        a = make_float2(0.f, 0.f);
       }
     }
   }
@@ -262,10 +346,11 @@ __global__ __launch_bounds__(256) void kb_sweep_mfma(Grid g, int rows,
   if (ye == g.ny && py_hi == g.ny - 1) {
     const int yo = g.ny - 1;
     if (yo >= yb) {
+      const float2* row = ua + (yo % 3) * US;
       for (int e = tid; e < TX * S; e += 256) {
         const int col = e >> LS, s = e & (S - 1), x = x0 + col;
         if (x < g.nx) {
-          const float2 a = ua[yo % 3][col][s];
+          const float2 a = row[col * SP + s];
           cpx<float>& o = u[((size_t)yo * g.nx + x) * S + s];
           o = ZERO ? cmk(a.x, a.y) : cmk(o.re + a.x, o.im + a.y);
         }

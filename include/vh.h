@@ -61,6 +61,13 @@ typedef int vh_status;
 /* Vanka patches, Sec. 3.2 list of patches. */
 #define VH_PATCH_FULL 0     /* 3x3 (2D) / 3x3x3 (3D) box around every node, truncated at the boundary */
 #define VH_PATCH_POINT 1    /* 1x1 patch = damped point Jacobi (Sec. 4.1)              */
+/* Sec. 3.2 patches; member order as the Fourier matrices of Sec. 4.1 (3^d box order,
+ * x fastest, restricted to the members); truncated at the boundary (Sec. 3.3) except
+ * ELEMENT, which is anchored at the lowest corner of every cell and has no boundary
+ * patches.  Value 2 is not a patch. */
+#define VH_PATCH_PLUS 3     /* node and its 2d axis neighbours (5 / 7 members)          */
+#define VH_PATCH_RB 4       /* 3^d box members of the centre's red-black colour (5 / 13) */
+#define VH_PATCH_ELEMENT 5  /* the 2^d corners of a cell (4 / 8)                        */
 
 /* Boundary treatment of the finest operator. */
 #define VH_BC_ABC 0         /* absorbing layer + first-order absorbing closure (default) */
@@ -69,6 +76,16 @@ typedef int vh_status;
 /* Smoother storage. */
 #define VH_SMOOTHER_PATCH 0     /* per-patch inverses, [Np*Np][node]; block multiply + weighted overlap-add */
 #define VH_SMOOTHER_ASSEMBLED 1 /* the same operator summed into a 5^d-point stencil at setup */
+
+/* Fine-grid stencil (vh_options.stencil).
+ *   FD2      : 2nd-order 5-point (2D) / 7-point (3D) stencil (Sec. 2.1); with VH_BC_ABC the
+ *              absorbing layer plus a first-order absorbing closure of the boundary rows.
+ *   COMPACT4 : compact 4th-order 9-point (2D) / 19-point (3D) stencil, eq. (disc4thCompact)
+ *              and (disc4thCompact3D), H = L - M diag(beta) (the mass stencil acting on
+ *              beta u), shift i alpha omega^2 M; stencil truncated at the boundary, with
+ *              VH_BC_ABC the absorbing layer only. */
+#define VH_STENCIL_FD2 0
+#define VH_STENCIL_COMPACT4 1
 
 /* Batched smoother contraction (vh_options.contraction).  The per-patch product
  * E_c = A_c^{-1} [r_c^(1..S)] of eq. (smoother) for S >= 16 sources sharing a sweep:
@@ -100,6 +117,7 @@ typedef struct vh_options {
                                1: in groups of up to 64 sources that share every V-cycle
                                sweep (each coefficient and patch-inverse entry is read once
                                per group), each source with its own FP64 FGMRES state    */
+    int stencil;            /* VH_STENCIL_*; default VH_STENCIL_FD2                     */
     int contraction;        /* VH_CONTRACT_*: how a batch of >= 16 sources applies the
                                per-patch smoother (2D, Full patch, VH_SMOOTHER_PATCH,
                                VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */

@@ -26,10 +26,15 @@ VH_IG_MIXED = 1
 VH_IG_LINEAR = 2
 VH_PATCH_FULL = 0
 VH_PATCH_POINT = 1
+VH_PATCH_PLUS = 3
+VH_PATCH_RB = 4
+VH_PATCH_ELEMENT = 5
 VH_BC_ABC = 0
 VH_BC_DIRICHLET = 1
 VH_SMOOTHER_PATCH = 0
 VH_SMOOTHER_ASSEMBLED = 1
+VH_STENCIL_FD2 = 0
+VH_STENCIL_COMPACT4 = 1
 VH_CONTRACT_VALU = 0
 VH_CONTRACT_MFMA_F32 = 1
 VH_CONTRACT_MFMA_BF16X3 = 2
@@ -42,7 +47,7 @@ class vh_options(ctypes.Structure):
         ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
         ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
         ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
-        ("batch", ctypes.c_int), ("contraction", ctypes.c_int),
+        ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("contraction", ctypes.c_int),
     ]
 
 

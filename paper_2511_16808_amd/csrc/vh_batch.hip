@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void kb_sweep(Grid g, int ls, const cpx<T>* __
   const size_t Np = (size_t)g.Np;
   const int S = 1 << ls;
   constexpr int E = bsm_entries<DIM, FORM>();
-  constexpr int UNR = (DIM == 3 && FORM == 0) ? 27 : E;
+  constexpr int UNR = (DIM == 3 && FORM == 0) ? 27 : (E > 128 ? patch_Np<DIM, FORM>() : E);
   cpx<T> acc = cmk<T>(0, 0);
 #pragma unroll 1
   for (int e0 = 0; e0 < E; e0 += UNR) {
@@ -426,6 +426,7 @@ hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* 
     return prec == PREC_F64 ? bsweep_t<D, F, double>(g, ls, G, r, u, zero, st) \
                             : bsweep_t<D, F, float>(g, ls, G, r, u, zero, st);
   VHB_SW(2, 0) VHB_SW(3, 0) VHB_SW(2, 1) VHB_SW(3, 1) VHB_SW(2, 2) VHB_SW(3, 2)
+  VHB_SW(2, 3) VHB_SW(3, 3) VHB_SW(2, 4) VHB_SW(3, 4) VHB_SW(2, 5) VHB_SW(3, 5)
 #undef VHB_SW
   return hipErrorInvalidValue;
 }

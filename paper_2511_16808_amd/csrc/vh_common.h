@@ -145,16 +145,55 @@ __host__ __device__ constexpr int shape_index(int dx, int dy, int dz) {
   return (dx + r) + W * (dy + r) + (DIM == 3 ? W * W * (dz + r) : 0);
 }
 
-// Vanka patches: FULL = the 3^DIM box (BOX1 ordering), POINT = the node itself.
-enum Patch : int { PATCH_FULL = 0, PATCH_POINT = 1 };
+// Vanka patches (Sec. 3.2): FULL = the 3^DIM box; POINT = the node itself; PLUS = the
+// node and its 2*DIM axis neighbours; RB = the members of the 3^DIM box with the same
+// red-black colour as the centre (|dx| + |dy| + |dz| even); ELEMENT = the 2^DIM corners
+// of the cell whose lowest corner is the anchor.  Members of FULL, PLUS and RB are in
+// 3^DIM-box order (x fastest), ELEMENT in 2^DIM-box order (x fastest).  Every node
+// anchors a (truncated) patch, except for ELEMENT, anchored at every cell only.
+// Value 2 is the assembled-stencil form of the sweep, not a patch.
+enum Patch : int { PATCH_FULL = 0, PATCH_POINT = 1, PATCH_PLUS = 3, PATCH_RB = 4, PATCH_ELEMENT = 5 };
+
+// does member t of the 3^DIM box (x fastest) belong to the patch?
+template <int DIM, int PATCH>
+__host__ __device__ constexpr bool box_member(int t) {
+  const int ax = t % 3 - 1, ay = (t / 3) % 3 - 1, az = DIM == 3 ? t / 9 - 1 : 0;
+  const int l1 = (ax < 0 ? -ax : ax) + (ay < 0 ? -ay : ay) + (az < 0 ? -az : az);
+  return PATCH == PATCH_FULL ? true
+         : PATCH == PATCH_PLUS ? l1 <= 1
+         : PATCH == PATCH_RB   ? (l1 % 2 == 0)
+                               : l1 == 0;
+}
 
 template <int DIM, int PATCH>
 __host__ __device__ constexpr int patch_Np() {
-  return PATCH == PATCH_FULL ? ipow(3, DIM) : 1;
+  if (PATCH == PATCH_ELEMENT) return ipow(2, DIM);
+  int n = 0;
+  for (int t = 0; t < ipow(3, DIM); ++t) n += box_member<DIM, PATCH>(t) ? 1 : 0;
+  return n;
 }
+
 template <int DIM, int PATCH>
 __host__ __device__ constexpr int patch_off(int k, int c) {
-  return PATCH == PATCH_FULL ? shape_off<DIM, BOX1>(k, c) : 0;
+  if (c >= DIM) return 0;
+  if (PATCH == PATCH_ELEMENT) return (k >> c) & 1;
+  int seen = 0;
+  for (int t = 0; t < ipow(3, DIM); ++t)
+    if (box_member<DIM, PATCH>(t)) {
+      if (seen == k) return (t / ipow(3, c)) % 3 - 1;
+      ++seen;
+    }
+  return 0;
+}
+
+// index of the member at offset (dx, dy, dz) from the anchor, or -1
+template <int DIM, int PATCH>
+__host__ __device__ constexpr int patch_member(int dx, int dy, int dz) {
+  for (int k = 0; k < patch_Np<DIM, PATCH>(); ++k)
+    if (patch_off<DIM, PATCH>(k, 0) == dx && patch_off<DIM, PATCH>(k, 1) == dy &&
+        patch_off<DIM, PATCH>(k, 2) == dz)
+      return k;
+  return -1;
 }
 
 // Intergrid families (1D weights, Sec. 3.1): restriction r(t), prolongation p(t) = 2 r(t).

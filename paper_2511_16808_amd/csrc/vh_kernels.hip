@@ -139,6 +139,82 @@ __global__ __launch_bounds__(256) void k_fine_operator(Grid g, const double* __r
   }
 }
 
+// Compact 4th-order stencil, eq. (disc4thCompact) / (disc4thCompact3D): H = L - M diag(beta)
+// with the mass stencil M acting on beta u (beta of the neighbour node; the stencil is
+// printed for constant kappa), H_s = H + i alpha omega^2 M.  Both as 3^DIM-box arrays
+// (x fastest); weights pointing outside the grid are dropped; with bc = BC_ABC the
+// absorbing layer is added to gamma (no Sommerfeld rows for this stencil).
+template <int DIM>
+__host__ __device__ constexpr double compact_L(int l1, double ih2) {
+  // 2D: centre 10/3, axis -2/3, diagonal -1/6;  3D: centre 4, face -1/3, edge -1/6, corner 0
+  return DIM == 2 ? (l1 == 0 ? 10.0 / 3 : l1 == 1 ? -2.0 / 3 : -1.0 / 6) * ih2
+                  : (l1 == 0 ? 4.0 : l1 == 1 ? -1.0 / 3 : l1 == 2 ? -1.0 / 6 : 0.0) * ih2;
+}
+template <int DIM>
+__host__ __device__ constexpr double compact_M(int l1) {
+  // 2D: centre 2/3, axis 1/12;  3D: centre 1/2, axis 1/12
+  return l1 == 0 ? (DIM == 2 ? 2.0 / 3 : 0.5) : (l1 == 1 ? 1.0 / 12 : 0.0);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fine_compact4(Grid g, const double* __restrict__ kappa,
+                                                       const double* __restrict__ gamma0, double h,
+                                                       double omega, double alpha, int bc, int sw,
+                                                       double samp, cpx<double>* __restrict__ H,
+                                                       cpx<double>* __restrict__ Hs) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int c[3];
+  decode(i, g, c[0], c[1], c[2]);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const double ih2 = 1.0 / (h * h);
+  const size_t N = (size_t)g.N;
+  constexpr int K = shape_K<DIM, BOX1>();
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    const int dx = shape_off<DIM, BOX1>(e, 0), dy = shape_off<DIM, BOX1>(e, 1),
+              dz = shape_off<DIM, BOX1>(e, 2);
+    const int x = c[0] + dx, y = c[1] + dy, z = c[2] + dz;
+    cpx<double> hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
+    if (inside(g, x, y, z)) {
+      const int l1 = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+      const double Lw = compact_L<DIM>(l1, ih2), Mw = compact_M<DIM>(l1);
+      const unsigned j = (unsigned)lin(g, x, y, z);
+      const double k = kappa[j];
+      double gam = gamma0 ? gamma0[j] : 0.0;
+      if (bc == BC_ABC && sw > 0) {
+        const int cj[3] = {x, y, z};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int s = min(cj[d], n[d] - 1 - cj[d]);
+          if (s < sw) {
+            const double f = (double)(sw - s) / (double)sw;
+            gam += samp * omega * f * f;
+          }
+        }
+      }
+      // beta = omega^2 kappa^2 - i omega kappa^2 gamma
+      const double bre = omega * omega * k * k, bim = -omega * k * k * gam;
+      hv = cmk(Lw - Mw * bre, -Mw * bim);
+      sv = cmk(hv.re, hv.im + alpha * omega * omega * Mw);
+    }
+    H[(size_t)e * N + i] = hv;
+    Hs[(size_t)e * N + i] = sv;
+  }
+}
+
+hipError_t fine_compact4(int dim, Grid g, const double* kappa, const double* gamma, double h,
+                         double omega, double alpha, int bc, int sw, double samp, cpx<double>* H,
+                         cpx<double>* Hs, hipStream_t s) {
+  const unsigned nb = nblocks(g.N, 256);
+  if (dim == 2)
+    k_fine_compact4<2><<<nb, 256, 0, s>>>(g, kappa, gamma, h, omega, alpha, bc, sw, samp, H, Hs);
+  else
+    k_fine_compact4<3><<<nb, 256, 0, s>>>(g, kappa, gamma, h, omega, alpha, bc, sw, samp, H, Hs);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 hipError_t fine_operator(int dim, Grid g, const double* kappa, const double* gamma, double h,
                          double omega, double alpha, int bc, int sw, double samp, cpx<double>* H,
                          cpx<double>* Hs, hipStream_t s) {
@@ -274,7 +350,7 @@ constexpr int VT_X = 64, VT_Y = 4, VT_H = 2;
 
 // Smoother entry sets: the per-patch form (entry a*Np + m reads r at off_m - off_a)
 // and the assembled form (the 5^DIM box).
-enum SmForm : int { SM_FULL = 0, SM_POINT = 1, SM_BOX2 = 2 };
+enum SmForm : int { SM_FULL = 0, SM_POINT = 1, SM_BOX2 = 2, SM_PLUS = 3, SM_RB = 4, SM_ELEMENT = 5 };
 
 template <int DIM, int FORM>
 __host__ __device__ constexpr int sm_entries() {
@@ -313,7 +389,8 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   constexpr int E = sm_entries<DIM, FORM>();
   // 3D per-patch form: three patches (81 entries) per iteration, to bound register use;
   // there plain loads keep more of them in flight than non-temporal ones
-  constexpr int UNR = (DIM == 3 && FORM == SM_FULL) ? 81 : E;
+  constexpr int UNR = (DIM == 3 && FORM == SM_FULL) ? 81
+                      : (E > 128 ? patch_Np<DIM, FORM>() : E);
   constexpr bool NT = (UNR == E);
   const size_t Np = (size_t)g.Np;
   const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
@@ -358,6 +435,12 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
   VH_VP(3, SM_POINT)
   VH_VP(2, SM_BOX2)
   VH_VP(3, SM_BOX2)
+  VH_VP(2, SM_PLUS)
+  VH_VP(3, SM_PLUS)
+  VH_VP(2, SM_RB)
+  VH_VP(3, SM_RB)
+  VH_VP(2, SM_ELEMENT)
+  VH_VP(3, SM_ELEMENT)
 #undef VH_VP
   return hipErrorInvalidValue;
 }
@@ -373,11 +456,31 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
 // G[(i*Np + m)][c + off_i].
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
+// is (x, y, z) the anchor of a patch?  Every node is, except for ELEMENT patches, which
+// are anchored at the lowest corner of every cell
+template <int DIM, int PATCH>
+__device__ __forceinline__ bool anchor_ok(const Grid& g, int x, int y, int z) {
+  if (PATCH != PATCH_ELEMENT) return inside(g, x, y, z);
+  return (unsigned)x < (unsigned)(g.nx - 1) && (unsigned)y < (unsigned)(g.ny - 1) &&
+         (DIM == 2 || (unsigned)z < (unsigned)(g.nz - 1));
+}
+
+// number of patches containing node (x, y, z) (Sec. 3.3 weights)
 template <int DIM, int PATCH>
 __device__ __forceinline__ int patch_count(const Grid& g, int x, int y, int z) {
   if (PATCH == PATCH_POINT) return 1;
-  int c = (3 - (x == 0) - (x == g.nx - 1)) * (3 - (y == 0) - (y == g.ny - 1));
-  if (DIM == 3) c *= (3 - (z == 0) - (z == g.nz - 1));
+  if (PATCH == PATCH_FULL) {
+    int c = (3 - (x == 0) - (x == g.nx - 1)) * (3 - (y == 0) - (y == g.ny - 1));
+    if (DIM == 3) c *= (3 - (z == 0) - (z == g.nz - 1));
+    return c;
+  }
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < patch_Np<DIM, PATCH>(); ++k)
+    c += anchor_ok<DIM, PATCH>(g, x - patch_off<DIM, PATCH>(k, 0), y - patch_off<DIM, PATCH>(k, 1),
+                               z - patch_off<DIM, PATCH>(k, 2))
+             ? 1
+             : 0;
   return c;
 }
 
@@ -409,11 +512,13 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
   const int pslot = (int)(wib * PPW + slot);
   const long long c = c0 + pslot;
   const bool in_slot = slot < (unsigned)PPW;
-  const bool active = in_slot && c < sl.c_hi;
+  const bool in_range = in_slot && c < sl.c_hi;
   const int base = (int)(in_slot ? slot : 0) * Np;
   const size_t N = (size_t)g.N;
   int cx = 0, cy = 0, cz = 0;
-  if (active) decode((unsigned)c, g, cx, cy, cz);
+  if (in_range) decode((unsigned)c, g, cx, cy, cz);
+  // a node that anchors no patch keeps identity rows and writes nothing
+  const bool active = in_range && anchor_ok<DIM, PATCH>(g, cx, cy, cz);
   const int kx = cx + patch_off<DIM, PATCH>(k, 0), ky = cy + patch_off<DIM, PATCH>(k, 1),
             kz = cz + patch_off<DIM, PATCH>(k, 2);
   const bool mem_in = active && inside(g, kx, ky, kz);
@@ -550,6 +655,21 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
   VH_VS(3, CROSS, PATCH_POINT)
   VH_VS(3, BOX1, PATCH_POINT)
   VH_VS(3, BOX2, PATCH_POINT)
+  VH_VS(2, CROSS, PATCH_PLUS)
+  VH_VS(2, BOX1, PATCH_PLUS)
+  VH_VS(2, BOX2, PATCH_PLUS)
+  VH_VS(3, CROSS, PATCH_PLUS)
+  VH_VS(3, BOX1, PATCH_PLUS)
+  VH_VS(2, CROSS, PATCH_RB)
+  VH_VS(2, BOX1, PATCH_RB)
+  VH_VS(2, BOX2, PATCH_RB)
+  VH_VS(3, CROSS, PATCH_RB)
+  VH_VS(3, BOX1, PATCH_RB)
+  VH_VS(2, CROSS, PATCH_ELEMENT)
+  VH_VS(2, BOX1, PATCH_ELEMENT)
+  VH_VS(2, BOX2, PATCH_ELEMENT)
+  VH_VS(3, CROSS, PATCH_ELEMENT)
+  VH_VS(3, BOX1, PATCH_ELEMENT)
 #undef VH_VS
   return hipErrorInvalidValue;
 }
@@ -557,12 +677,12 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
 // Assembled form of the same operator: B[d][i] = sum over (a, m) with
 // off_m - off_a = d of G[(a*Np+m)][i]  (d in the 5^DIM box, FULL patch), summed
 // in FP64.  u += B r is then a 5^DIM-point stencil sweep.
-template <int DIM, class T>
+template <int DIM, int PATCH, class T>
 __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __restrict__ G,
                                                         Slab sl, cpx<T>* __restrict__ B) {
   const long long i = sl.c_lo + (long long)node_id();
   if (i >= sl.c_hi) return;
-  constexpr int Np = patch_Np<DIM, PATCH_FULL>();
+  constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int K5 = shape_K<DIM, BOX2>();
   const size_t N = (size_t)g.Np;
   int cx, cy, cz;
@@ -575,33 +695,49 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
     cpx<double> acc = cmk(0.0, 0.0);
 #pragma unroll
     for (int a = 0; a < Np; ++a) {
-      const int mx = dx + patch_off<DIM, PATCH_FULL>(a, 0),
-                my = dy + patch_off<DIM, PATCH_FULL>(a, 1),
-                mz = dz + patch_off<DIM, PATCH_FULL>(a, 2);
-      const int m = shape_index<DIM, BOX1>(mx, my, mz);
+      const int mx = dx + patch_off<DIM, PATCH>(a, 0),
+                my = dy + patch_off<DIM, PATCH>(a, 1),
+                mz = dz + patch_off<DIM, PATCH>(a, 2);
+      const int m = patch_member<DIM, PATCH>(mx, my, mz);
       if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
     }
     B[(size_t)e * N + ip] = ccast<T>(acc);
   }
 }
 
-hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
-                          hipStream_t s) {
-  if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
+template <int PATCH>
+static hipError_t assemble_p(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
+                             hipStream_t s) {
   const unsigned nb = nblocks((size_t)(sl.c_hi - sl.c_lo), 256);
   if (dim == 2) {
     if (prec == PREC_F64)
-      k_vanka_assemble<2, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, (cpx<double>*)B);
+      k_vanka_assemble<2, PATCH, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl,
+                                                            (cpx<double>*)B);
     else
-      k_vanka_assemble<2, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, (cpx<float>*)B);
+      k_vanka_assemble<2, PATCH, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl,
+                                                           (cpx<float>*)B);
   } else {
     if (prec == PREC_F64)
-      k_vanka_assemble<3, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, (cpx<double>*)B);
+      k_vanka_assemble<3, PATCH, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl,
+                                                            (cpx<double>*)B);
     else
-      k_vanka_assemble<3, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, (cpx<float>*)B);
+      k_vanka_assemble<3, PATCH, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl,
+                                                           (cpx<float>*)B);
   }
   VH_LAUNCH_CHECK();
   return hipSuccess;
+}
+
+hipError_t vanka_assemble(int dim, int patch, Grid g, int prec, const void* G, Slab sl, void* B,
+                          hipStream_t s) {
+  if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
+  switch (patch) {
+    case PATCH_FULL: return assemble_p<PATCH_FULL>(dim, g, prec, G, sl, B, s);
+    case PATCH_PLUS: return assemble_p<PATCH_PLUS>(dim, g, prec, G, sl, B, s);
+    case PATCH_RB: return assemble_p<PATCH_RB>(dim, g, prec, G, sl, B, s);
+    case PATCH_ELEMENT: return assemble_p<PATCH_ELEMENT>(dim, g, prec, G, sl, B, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // dst[e][i] (FP64, N-node rows) = src[e][padded i] (smoother arrays, for inspection)
@@ -725,6 +861,8 @@ hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc
   VH_GK(2, CROSS, BOX2, FAM_CUBIC, FAM_CUBIC)   // level-dependent, finest -> 2nd
   VH_GK(2, CROSS, BOX2, FAM_LINEAR, FAM_CUBIC)  // mixed from the finest level
   VH_GK(2, BOX2, BOX2, FAM_LINEAR, FAM_CUBIC)   // level-dependent / mixed below
+  VH_GK(2, BOX1, BOX2, FAM_CUBIC, FAM_CUBIC)    // compact fine level: level-dependent
+  VH_GK(2, BOX1, BOX2, FAM_LINEAR, FAM_CUBIC)   // compact fine level: mixed
   VH_GK(2, CROSS, BOX1, FAM_LINEAR, FAM_LINEAR) // bilinear
   VH_GK(2, BOX1, BOX1, FAM_LINEAR, FAM_LINEAR)
   VH_GK(3, CROSS, BOX1, FAM_LINEAR, FAM_LINEAR) // trilinear

@@ -48,6 +48,10 @@ hipError_t convert(const void* a, int pa, void* b, int pb, size_t n, hipStream_t
 hipError_t fine_operator(int dim, Grid g, const double* kappa, const double* gamma, double h,
                          double omega, double alpha, int bc, int sw, double samp, cpx<double>* H,
                          cpx<double>* Hs, hipStream_t s);
+// compact 4th-order fine operator (3^dim-box arrays), same arguments as fine_operator
+hipError_t fine_compact4(int dim, Grid g, const double* kappa, const double* gamma, double h,
+                         double omega, double alpha, int bc, int sw, double samp, cpx<double>* H,
+                         cpx<double>* Hs, hipStream_t s);
 hipError_t check_media(long long N, const double* kappa, const double* gamma, int* flag,
                        hipStream_t s);
 hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, int px,
@@ -69,7 +73,7 @@ hipError_t sample(Grid g, int E, int padded, int prec, int count, const long lon
                   const void* src, cpx<double>* out, hipStream_t s);
 hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);
 // B rows of nodes [sl.c_lo, sl.c_hi) from the per-patch rows held as in vanka_setup
-hipError_t vanka_assemble(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
+hipError_t vanka_assemble(int dim, int patch, Grid g, int prec, const void* G, Slab sl, void* B,
                           hipStream_t s);
 hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,
                     const cpx<double>* Af, cpx<double>* Ac, hipStream_t s);

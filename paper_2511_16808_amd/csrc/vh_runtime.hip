@@ -183,17 +183,38 @@ void shape_offsets(int dim, int shape, int K, int out[][3]) {
   }
 }
 
-int patch_size(int dim, int patch) { return patch == VH_PATCH_FULL ? (dim == 2 ? 9 : 27) : 1; }
+int patch_size(int dim, int patch) {
+  switch (patch) {
+    case VH_PATCH_FULL: return dim == 2 ? 9 : 27;
+    case VH_PATCH_PLUS: return 2 * dim + 1;
+    case VH_PATCH_RB: return dim == 2 ? 5 : 13;
+    case VH_PATCH_ELEMENT: return dim == 2 ? 4 : 8;
+    default: return 1;
+  }
+}
 
-// damping used when the caller passes none: the full patch values come from LFA on
-// the finest level and an exhaustive per-level search (readings of Table
-// "relaxParam" for the 2nd-order stencil); the point patch from LFA.
+// damping used when the caller passes none.  Element, Plus, RB: Table "relaxParam"
+// (2D columns; 3D columns for Element and Plus, the 3D RB patch, absent from the table,
+// takes the Plus column).  Full patch: LFA smoothing-factor minimiser on the finest
+// level and an exhaustive per-level search (not in the table); point patch: LFA.
 double default_damping(int dim, int patch, int level) {
   static const double full2[] = {0.94, 1.2, 0.4, 0.6};
   static const double full3[] = {1.08, 0.9, 0.6, 0.6};
   static const double point2[] = {0.78, 0.7, 0.4, 0.6};
   static const double point3[] = {0.84, 0.7, 0.5, 0.5};
-  const double* t = patch == VH_PATCH_FULL ? (dim == 2 ? full2 : full3) : (dim == 2 ? point2 : point3);
+  static const double elem2[] = {0.97, 0.66, 0.48, 0.88};
+  static const double plus2[] = {0.87, 0.57, 0.55, 0.74};
+  static const double rb2[] = {0.83, 0.5, 0.4, 0.65};
+  static const double elem3[] = {1.1, 0.7, 0.45, 0.6};
+  static const double plus3[] = {0.92, 0.55, 0.45, 0.55};
+  const double* t;
+  switch (patch) {
+    case VH_PATCH_FULL: t = dim == 2 ? full2 : full3; break;
+    case VH_PATCH_ELEMENT: t = dim == 2 ? elem2 : elem3; break;
+    case VH_PATCH_PLUS: t = dim == 2 ? plus2 : plus3; break;
+    case VH_PATCH_RB: t = dim == 2 ? rb2 : plus3; break;
+    default: t = dim == 2 ? point2 : point3;
+  }
   return t[level < 3 ? level : 3];
 }
 
@@ -205,7 +226,9 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (!(omega >= 0) || !std::isfinite(omega)) return fail(VH_EINVAL, "omega must be >= 0");
   if (!(shift >= 0) || !std::isfinite(shift)) return fail(VH_EINVAL, "shift must be >= 0");
   if (levels < 1 || levels > 16) return fail(VH_EINVAL, "levels must be in [1, 16]");
-  if (patch != VH_PATCH_FULL && patch != VH_PATCH_POINT) return fail(VH_EINVAL, "unknown patch");
+  if (patch != VH_PATCH_FULL && patch != VH_PATCH_POINT && patch != VH_PATCH_PLUS &&
+      patch != VH_PATCH_RB && patch != VH_PATCH_ELEMENT)
+    return fail(VH_EINVAL, "unknown patch");
   long long N = 1;
   for (int d = 0; d < dim; ++d) {
     if (n[d] < 3) return fail(VH_EINVAL, "every dimension needs >= 3 nodes");
@@ -224,6 +247,8 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 8 || o.nu2 > 8)
     return fail(VH_EINVAL, "nu1, nu2 must be in [0, 8] with nu1 + nu2 >= 1");
   if (o.bc != VH_BC_ABC && o.bc != VH_BC_DIRICHLET) return fail(VH_EINVAL, "unknown bc");
+  if (o.stencil != VH_STENCIL_FD2 && o.stencil != VH_STENCIL_COMPACT4)
+    return fail(VH_EINVAL, "unknown stencil");
   if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
     return fail(VH_EINVAL, "unknown smoother");
   if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
@@ -276,8 +301,7 @@ size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N *
 // ---------------------------------------------------------------- V-cycle
 vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(zero ? 0 : 1) : -1;
-  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2
-                   : (hd->patch == VH_PATCH_FULL ? 0 : 1);
+  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2 : hd->patch;
   VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
   return VH_OK;
@@ -380,7 +404,7 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
     int k = 0;
     for (int j = 0; j < m; ++j) {
       VH_TRY(precondition(hd, Vj(j), Zj(j)));
-      VH_HIP(stencil(hd->dim, CROSS, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
+      VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                      PREC_F64, nullptr, Vj(j + 1), hd->s));
       VH_HIP(cgs_pass(0, V, N, j + 1, nullptr, Vj(j + 1), N, hd->part, hd->nred, K->h1, hd->s));
       VH_HIP(cgs_pass(1, V, N, j + 1, K->h1, Vj(j + 1), N, hd->part, hd->nred, K->h2, hd->s));
@@ -397,7 +421,7 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
     VH_HIP(backsolve(K, k, ldh, hd->s));
     VH_HIP(update_x(K, k, hd->prec, hd->Z, N, x, N, hd->s));
     // true residual r = q - H x (FP64), V_0 = r / ||r||
-    VH_HIP(stencil(hd->dim, CROSS, hd->L[0].g, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, x,
+    VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, x,
                    PREC_F64, q, Vj(0), hd->s));
     VH_HIP(cgs_pass(2, V, N, 0, K->h2, Vj(0), N, hd->part, hd->nred, K->nrm2, hd->s));
     VH_HIP(cycle_init(K, m, hd->s));
@@ -468,8 +492,7 @@ vh_status ensure_batch(vh_handle* hd, int S) {
 vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zero) {
   Level& Lv = hd->L[l];
   const int tk = (l == 0) ? hd->tbegin(zero ? 0 : 1) : -1;
-  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2
-                   : (hd->patch == VH_PATCH_FULL ? 0 : 1);
+  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2 : hd->patch;
   if (Lv.mfma_txp[ls])
     VH_HIP(batch_sweep_mfma(Lv.g, ls, hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3,
                             Lv.mfma_txp[ls], Lv.mfma_rows[ls], Lv.B, r, u, zero, hd->s));
@@ -649,7 +672,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       const int tk = hd->tbegin(2);
       VH_TRY(vcycle_b(hd, 0, ls, qv, Zj(j)));
       hd->tend(tk);
-      VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
+      VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                            PREC_F64, nullptr, Vj(j + 1), s));
       VH_HIP(batch_cgs(0, hd->bV, ldv, j + 1, nullptr, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
                        K->h1, s));
@@ -677,7 +700,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     for (int k = 0; k < S; ++k) kmax = kcols[k] > kmax ? kcols[k] : kmax;
     VH_HIP(batch_backsolve(K, S, s));
     VH_HIP(batch_update_x(K, kmax, hd->prec, hd->bZ, ldv, hd->bX, N, ls, s));
-    VH_HIP(batch_stencil(hd->dim, CROSS, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
+    VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
                          PREC_F64, hd->bQ, Vj(0), s));
     VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->bnred, K->nrm2, s));
     VH_HIP(batch_cycle_init(K, m, S, s));
@@ -758,7 +781,7 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
     VH_HIP(fill(buf, (size_t)Np * Np * gstride, hd->prec, 0, 0, s));
     VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, g, A, Lv.w, hd->prec, buf,
                        Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
-    VH_HIP(vanka_assemble(dim, g, hd->prec, buf,
+    VH_HIP(vanka_assemble(dim, hd->patch, g, hd->prec, buf,
                           Slab{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride}, Lv.B, s));
   }
   if (p.own) {
@@ -778,7 +801,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   hd->L.resize(hd->levels);
   // grids and transfer plan
   int nn[3] = {hd->n[0], hd->n[1], dim == 3 ? hd->n[2] : 1};
-  int shape = CROSS;
+  int shape = o.stencil == VH_STENCIL_COMPACT4 ? BOX1 : CROSS;
   for (int l = 0; l < hd->levels; ++l) {
     Level& Lv = hd->L[l];
     Lv.g = make_grid(dim, nn[0], nn[1], nn[2]);
@@ -811,8 +834,12 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   std::vector<cpx<double>*> A64(hd->levels, nullptr);
   VH_TRY(hd->alloc((void**)&hd->Hfine, hd->L[0].K * N0 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&A64[0], hd->L[0].K * N0 * sizeof(cpx<double>)));
-  VH_HIP(fine_operator(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
-                       o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
+  if (o.stencil == VH_STENCIL_COMPACT4)
+    VH_HIP(fine_compact4(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
+                         o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
+  else
+    VH_HIP(fine_operator(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
+                         o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
   // Galerkin hierarchy, FP64
   for (int l = 0; l + 1 < hd->levels; ++l) {
     Level &Lf = hd->L[l], &Lc = hd->L[l + 1];
@@ -843,7 +870,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     Lv.bytes = ((size_t)Lv.K + 3) * N * hd->esz;
     if (l + 1 == hd->levels) break;
     const size_t Npad = (size_t)Lv.g.Np;  // smoother arrays use the padded row layout
-    if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch == VH_PATCH_FULL) {
+    if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch != VH_PATCH_POINT) {
       VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
     } else {
       VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
@@ -854,7 +881,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     }
     Lv.bytes += (size_t)Lv.E * Npad * hd->esz;
   }
-  if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch != VH_PATCH_FULL)
+  if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch == VH_PATCH_POINT)
     hd->opt.smoother = VH_SMOOTHER_PATCH;  // a 1x1 patch is already a 1-point stencil
   // coarsest: dense FP64 inverse
   {
@@ -1090,7 +1117,7 @@ vh_status vh_apply_operator(vh_handle* hd, int level, int which, const void* x, 
   const size_t N = (size_t)Lv.g.N;
   if (which == 0) {
     if (level != 0) return fail(VH_EINVAL, "the unshifted operator exists on level 0 only");
-    VH_HIP(stencil(hd->dim, CROSS, Lv.g, OP_APPLY, PREC_F64, hd->Hfine, PREC_F64, x, PREC_F64,
+    VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_APPLY, PREC_F64, hd->Hfine, PREC_F64, x, PREC_F64,
                    nullptr, y, hd->s));
   } else if (hd->prec == PREC_F64) {
     VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_APPLY, PREC_F64, Lv.A, PREC_F64, x, PREC_F64,
@@ -1271,8 +1298,8 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   const int Np = patch_size(dim, patch);
   size_t nn[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
   size_t total = 0, N0 = nn[0] * nn[1] * nn[2], slab_tmp = 0;
-  int shape = CROSS;
-  total += (size_t)(2 * dim + 1) * N0 * 16;  // unshifted H
+  int shape = o.stencil == VH_STENCIL_COMPACT4 ? BOX1 : CROSS;
+  total += (size_t)shape_points(dim, shape) * N0 * 16;  // unshifted H
   for (int l = 0; l < levels; ++l) {
     const size_t N = nn[0] * nn[1] * nn[2];
     const int K = shape_points(dim, shape);
@@ -1281,7 +1308,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
       total += N * N * 16;
       break;
     }
-    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && patch == VH_PATCH_FULL;
+    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && patch != VH_PATCH_POINT;
     const int E = assembled ? (dim == 2 ? 25 : 125) : Np * Np;
     const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
     total += (size_t)E * Npad * esz;

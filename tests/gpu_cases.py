@@ -11,7 +11,7 @@ from oracle import discretization as D
 class Case:
     def __init__(self, n, levels, alpha=0.1, seed=0, medium="layered", ppw=10.0,
                  patch="full", precision=0, intergrid=None, damping=None, restart=20,
-                 bc="abc", sponge_width=20, smoother=0, nu=(1, 1)):
+                 bc="abc", sponge_width=20, smoother=0, nu=(1, 1), stencil="fd2", gamma0=None):
         self.n = tuple(n)
         self.dim = len(n)
         self.N = int(np.prod(n))
@@ -20,12 +20,16 @@ class Case:
             self.kappa = synth.layered_2d(self.n, seed)
         elif medium == "layered":
             self.kappa = synth.geophysical_3d(self.n, seed)
+        elif medium == "linear":
+            self.kappa = synth.linear_kappa2(self.n, 0.25, 1.0)
         elif medium == "random":
             self.kappa = np.random.default_rng(seed).uniform(0.4, 1.0, size=tuple(reversed(n)))
         else:
             self.kappa = synth.homogeneous(self.n)
         self.omega = synth.omega_for_ppw(self.h, ppw, float(self.kappa.max()))
-        self.gamma = 0.01 * self.omega * np.ones_like(self.kappa)
+        g0 = 0.01 * self.omega if gamma0 is None else gamma0
+        self.gamma = g0 * np.ones_like(self.kappa)
+        self.stencil = stencil
         self.alpha = alpha
         self.levels = levels
         self.patch = patch
@@ -45,6 +49,10 @@ class Case:
 
     # ---- oracle side
     def oracle_ops(self):
+        if self.stencil == "compact4":
+            return D.compact4_operator(self.n, self.h, self.omega, self.kappa, self.gamma,
+                                       self.alpha, bc="sponge" if self.bc == "abc" else "dirichlet",
+                                       sponge_width=self.sponge_width)
         return D.fd2_operator(self.n, self.h, self.omega, self.kappa, self.gamma, self.alpha,
                               bc="abc" if self.bc == "abc" else "dirichlet",
                               sponge_width=self.sponge_width)
@@ -67,10 +75,13 @@ class Case:
                              bc=B.VH_BC_ABC if self.bc == "abc" else B.VH_BC_DIRICHLET,
                              sponge_width=self.sponge_width, smoother=self.smoother,
                              nu1=self.nu[0], nu2=self.nu[1],
+                             stencil=B.VH_STENCIL_COMPACT4 if self.stencil == "compact4"
+                             else B.VH_STENCIL_FD2,
                              stream=torch.cuda.current_stream(), **extra)
         kap = torch.tensor(self.kappa.ravel(), dtype=torch.float64, device="cuda")
         gam = torch.tensor(self.gamma.ravel(), dtype=torch.float64, device="cuda")
-        patch = B.VH_PATCH_FULL if self.patch == "full" else B.VH_PATCH_POINT
+        patch = {"full": B.VH_PATCH_FULL, "point": B.VH_PATCH_POINT, "plus": B.VH_PATCH_PLUS,
+                 "rb": B.VH_PATCH_RB, "element": B.VH_PATCH_ELEMENT}[self.patch]
         hd = B.vh_setup(self.dim, self.n, self.h, self.omega, kap, gam, self.alpha,
                         self.levels, patch, opt)
         return hd

@@ -54,8 +54,24 @@ WORKLOADS = {
                dim=3, n=(257, 257, 257), levels=6, alpha=0.5, medium="geophysical_3d", seed=3,
                precision=1, restart=30, damping=[1.08, 0.9, 0.6, 0.6],
                sample=dict(n=(65, 65, 65), levels=4)),
+    "p2": dict(desc="the paper's own 2D configuration scaled to 1025x1025 nodes: kappa^2 linear in "
+                    "depth over [0.25, 1] (Table heterogeneous2D model), 10 ppw at kappa_max, gamma = 0, "
+                    "20-cell absorbing layer, compact 4th-order stencil, RB patch, level-dependent "
+                    "intergrid, shift 0.25, 6-level V(1,1), GMRES(5), complex128",
+               dim=2, n=(1025, 1025), levels=6, alpha=0.25, medium="linear", seed=0,
+               precision=0, restart=5, damping=[0.83, 0.5, 0.4, 0.65], stencil="compact4",
+               patch="rb", gamma0=0.0, sample=dict(n=(513, 513), levels=5)),
+    "p3": dict(desc="the paper's own 3D configuration on the c3 medium: 257^3 nodes, compact "
+                    "4th-order 19-point stencil, Element patch (per-patch inverses, 64 entries per "
+                    "node), trilinear intergrid, gamma = 0, "
+                    "20-cell absorbing layer, shift 0.4, 6-level V(1,1), complex64 preconditioner, "
+                    "FGMRES(20) in complex128",
+               dim=3, n=(257, 257, 257), levels=6, alpha=0.4, medium="geophysical_3d", seed=3,
+               precision=1, restart=20, damping=[1.1, 0.7, 0.45, 0.6], stencil="compact4",
+               patch="element", gamma0=0.0, smoother="patch", sample=dict(n=(65, 65, 65), levels=4)),
 }
 DEFAULT_WORKLOAD = "c3"
+PATCHES = {"full": 0, "point": 1, "plus": 3, "rb": 4, "element": 5}
 
 SERVE_DESC = ("serving mix: Poisson arrivals; 70% 2D grids uniform over {257,513,1025,2049}^2 nodes, "
               "30% 3D over {97,129,193}^3; seeded layered media per request, 8-12 ppw, "
@@ -102,6 +118,7 @@ def serve_bench(args):
     rng = np.random.default_rng(5)
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(reqs)))
     arrivals -= arrivals[0]
+    args.smoother = args.smoother or "assembled"
     smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
     opts = {rs: B.make_options(precision=B.VH_PREC_C64, batch=1, restart=rs, smoother=smoother)
             for rs in (20, 30)}
@@ -150,13 +167,15 @@ def make_medium(w, n=None):
     n = tuple(n or w["n"])
     if w["medium"] == "homogeneous":
         kappa = synth.homogeneous(n)
+    elif w["medium"] == "linear":
+        kappa = synth.linear_kappa2(n, 0.25, 1.0)
     elif w["medium"] == "layered_2d":
         kappa = synth.layered_2d(n, w["seed"])
     else:
         kappa = synth.geophysical_3d(n, w["seed"])
     h = 1.0 / (n[0] - 1)
     omega = synth.omega_for_ppw(h, 10.0, float(kappa.max()))
-    gamma = 0.01 * omega * np.ones_like(kappa)
+    gamma = w.get("gamma0", 0.01 * omega) * np.ones_like(kappa)
     nsrc = w.get("nsrc", 1)
     if nsrc == 1:
         q = synth.point_source(n).ravel()
@@ -195,8 +214,10 @@ def measured_traffic(key, kernel):
     return rec["traffic"]
 
 
-def vcycle_bytes(levels_info, dim, esz, smoother_entries):
-    """Algorithmic HBM bytes of one V(1,1) cycle: each array touched once per kernel."""
+def vcycle_bytes(levels_info, dim, esz, smoother_entries, S=1):
+    """Algorithmic HBM bytes of one V(1,1) cycle for S sources sharing it: every
+    coefficient and smoother array read once per sweep, every vector of the S sources
+    touched once per kernel."""
     total = 0
     L = len(levels_info)
     for l, info in enumerate(levels_info):
@@ -204,13 +225,13 @@ def vcycle_bytes(levels_info, dim, esz, smoother_entries):
         for k in info["n"][:dim]:
             N *= k
         if l == L - 1:
-            total += N * N * 16 + 2 * N * esz
+            total += N * N * 16 + 2 * N * S * esz
             break
         Nc = 1
         for k in levels_info[l + 1]["n"][:dim]:
             Nc *= k
         K, E = info["stencil_points"], smoother_entries[l]
-        total += N * esz * (2 * E + 2 * K + 15) + Nc * esz * 2
+        total += N * esz * (2 * E + 2 * K) + N * S * esz * 15 + Nc * S * esz * 2
     return total
 
 
@@ -229,9 +250,9 @@ from oracle import discretization as D, cycle, krylov
 w = WORKLOADS[{w['key']!r}]
 n, h, omega, kappa, gamma, q = make_medium(dict(w, nsrc=1), {tuple(sample['n'])!r})
 t0 = time.perf_counter()
-ops = D.fd2_operator(n, h, omega, kappa, gamma, w['alpha'])
+ops = D.operator(w.get('stencil', 'fd2'), n, h, omega, kappa, gamma, w['alpha'])
 mg = cycle.Multigrid(ops['Hs'], n, {sample['levels']}, 'levdep' if len(n) == 2 else 'linear',
-                     'full', w['damping'])
+                     w.get('patch', 'full'), w['damping'])
 t1 = time.perf_counter()
 its = 2
 krylov.fgmres(lambda v: ops['H'] @ v, mg.apply, q, 1e-30, w['restart'], its)
@@ -274,9 +295,10 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--budget-gib", type=float, default=240.0, help="c5: HBM budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--smoother", default="assembled", choices=["patch", "assembled"],
+    ap.add_argument("--smoother", default=None, choices=["patch", "assembled"],
                     help="additive Vanka applied as stored patch inverses or as the same "
-                         "operator assembled into a 5^d-point stencil (default)")
+                         "operator assembled into a 5^d-point stencil (default: assembled, "
+                         "unless the workload names its form)")
     ap.add_argument("--contraction", default="valu", choices=["valu", "mfma_f32", "mfma_bf16x3"],
                     help="batched per-patch smoother on the vector ALUs or the matrix cores "
                          "(implies --smoother patch)")
@@ -311,6 +333,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = dict(WORKLOADS[args.workload], key=args.workload)
+    if args.smoother is None:
+        args.smoother = w.get("smoother", "assembled")
     n, h, omega, kappa, gamma, q = make_medium(w)
     dim = w["dim"]
     N = int(np.prod(n))
@@ -328,15 +352,17 @@ def main():
     nsrc = w.get("nsrc", 1)
     batch = w.get("batch", 0) if args.batch is None else args.batch
     precision = w["precision"] if args.precision is None else {"c128": 0, "c64": 1}[args.precision]
+    patch = PATCHES[w.get("patch", "full")]
+    stencil = B.VH_STENCIL_COMPACT4 if w.get("stencil") == "compact4" else B.VH_STENCIL_FD2
     opt = B.make_options(precision=precision, restart=w["restart"], damping=w["damping"],
-                         intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR,
+                         intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
                          contraction=contraction)
     torch.cuda.synchronize()
 
     def step():
         t0 = time.perf_counter()
-        hd = B.vh_setup(dim, n, h, omega, kt, gt, w["alpha"], w["levels"], B.VH_PATCH_FULL, opt)
+        hd = B.vh_setup(dim, n, h, omega, kt, gt, w["alpha"], w["levels"], patch, opt)
         t1 = time.perf_counter()
         st, stats = B.vh_solve(hd, qt, nsrc, 1e-6, ut)
         info = [B.vh_get_level_info(hd, l) for l in range(w["levels"])]
@@ -388,7 +414,7 @@ def main():
         tf = flops / (ms_l / n_l * 1e-3) / 1e12 if n_l else None
         roof = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
                 "frac": (tf / peak) if tf else None, "hbm_GBps": achieved}
-    vc_b = vcycle_bytes(info, dim, esz, E)
+    vc_b = vcycle_bytes(info, dim, esz, E, width)
     vc_n = sum(r["stats"]["vcycles"] for r in runs)
     vc_ms = sum(r["stats"]["vcycle_ms"] for r in runs)
     lat = np.array([r["step_ms"] for r in runs])

@@ -57,6 +57,7 @@ typedef int vh_status;
 #define VH_IG_LEVDEP 0      /* eq. (level1Intergrid)/(levelDepIntergrid): cubic R,P from the finest level, then linear R / cubic P */
 #define VH_IG_MIXED 1       /* linear R / cubic P on every level                      */
 #define VH_IG_LINEAR 2      /* (bi/tri)linear R and P on every level (3D default)      */
+#define VH_IG_CUBIC 3       /* eq. (bicubicIntergrid): cubic R and P on every level (2D) */
 
 /* Vanka patches, Sec. 3.2 list of patches. */
 #define VH_PATCH_FULL 0     /* 3x3 (2D) / 3x3x3 (3D) box around every node, truncated at the boundary */
@@ -84,6 +85,8 @@ typedef int vh_status;
  *              and (disc4thCompact3D), H = L - M diag(beta) (the mass stencil acting on
  *              beta u), shift i alpha omega^2 M; stencil truncated at the boundary, with
  *              VH_BC_ABC the absorbing layer only. */
+#define VH_CYCLE_V 0
+#define VH_CYCLE_W 1
 #define VH_STENCIL_FD2 0
 #define VH_STENCIL_COMPACT4 1
 
@@ -118,6 +121,9 @@ typedef struct vh_options {
                                sweep (each coefficient and patch-inverse entry is read once
                                per group), each source with its own FP64 FGMRES state    */
     int stencil;            /* VH_STENCIL_*; default VH_STENCIL_FD2                     */
+    int cycle;              /* VH_CYCLE_V (default) or VH_CYCLE_W (Sec. 2.2: the coarse
+                               correction visits each coarser level twice, except the
+                               coarsest, solved directly)                                */
     int contraction;        /* VH_CONTRACT_*: how a batch of >= 16 sources applies the
                                per-patch smoother (2D, Full patch, VH_SMOOTHER_PATCH,
                                VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */

@@ -24,6 +24,9 @@ VH_PREC_C64 = 1
 VH_IG_LEVDEP = 0
 VH_IG_MIXED = 1
 VH_IG_LINEAR = 2
+VH_IG_CUBIC = 3
+VH_CYCLE_V = 0
+VH_CYCLE_W = 1
 VH_PATCH_FULL = 0
 VH_PATCH_POINT = 1
 VH_PATCH_PLUS = 3
@@ -47,7 +50,8 @@ class vh_options(ctypes.Structure):
         ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
         ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
         ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
-        ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("contraction", ctypes.c_int),
+        ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("cycle", ctypes.c_int),
+        ("contraction", ctypes.c_int),
     ]
 
 

@@ -151,6 +151,7 @@ hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, c
     if (shape == CROSS) return bstencil_p<2, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
     if (shape == BOX1) return bstencil_p<2, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);
     if (shape == BOX2) return bstencil_p<2, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == BOX3) return bstencil_p<2, BOX3>(g, ls, mode, pc, A, px, x, py, b, y, st);
   } else {
     if (shape == CROSS) return bstencil_p<3, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
     if (shape == BOX1) return bstencil_p<3, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);

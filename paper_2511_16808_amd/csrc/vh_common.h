@@ -98,8 +98,9 @@ __host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int 
 
 // ---------------------------------------------------------------- stencil shapes
 // CROSS: centre + the 2*DIM axis neighbours, ordered centre, -x, +x, -y, +y, -z, +z.
-// BOX<r>: the (2r+1)^DIM box, x fastest.
-enum Shape : int { CROSS = 0, BOX1 = 1, BOX2 = 2 };
+// BOX<r>: the (2r+1)^DIM box, x fastest (BOX3 = 7x7: Galerkin operators below the second
+// level with cubic restriction and prolongation on every level, 2D only).
+enum Shape : int { CROSS = 0, BOX1 = 1, BOX2 = 2, BOX3 = 3 };
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 

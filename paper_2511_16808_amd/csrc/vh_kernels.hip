@@ -316,6 +316,7 @@ hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, 
     if (shape == CROSS) return stencil_p<2, CROSS>(g, mode, pc, A, px, x, py, b, y, s);
     if (shape == BOX1) return stencil_p<2, BOX1>(g, mode, pc, A, px, x, py, b, y, s);
     if (shape == BOX2) return stencil_p<2, BOX2>(g, mode, pc, A, px, x, py, b, y, s);
+    if (shape == BOX3) return stencil_p<2, BOX3>(g, mode, pc, A, px, x, py, b, y, s);
   } else {
     if (shape == CROSS) return stencil_p<3, CROSS>(g, mode, pc, A, px, x, py, b, y, s);
     if (shape == BOX1) return stencil_p<3, BOX1>(g, mode, pc, A, px, x, py, b, y, s);
@@ -655,6 +656,11 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
   VH_VS(3, CROSS, PATCH_POINT)
   VH_VS(3, BOX1, PATCH_POINT)
   VH_VS(3, BOX2, PATCH_POINT)
+  VH_VS(2, BOX3, PATCH_FULL)
+  VH_VS(2, BOX3, PATCH_POINT)
+  VH_VS(2, BOX3, PATCH_PLUS)
+  VH_VS(2, BOX3, PATCH_RB)
+  VH_VS(2, BOX3, PATCH_ELEMENT)
   VH_VS(2, CROSS, PATCH_PLUS)
   VH_VS(2, BOX1, PATCH_PLUS)
   VH_VS(2, BOX2, PATCH_PLUS)
@@ -861,6 +867,8 @@ hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc
   VH_GK(2, CROSS, BOX2, FAM_CUBIC, FAM_CUBIC)   // level-dependent, finest -> 2nd
   VH_GK(2, CROSS, BOX2, FAM_LINEAR, FAM_CUBIC)  // mixed from the finest level
   VH_GK(2, BOX2, BOX2, FAM_LINEAR, FAM_CUBIC)   // level-dependent / mixed below
+  VH_GK(2, BOX2, BOX3, FAM_CUBIC, FAM_CUBIC)    // cubic on every level: 7x7 below
+  VH_GK(2, BOX3, BOX3, FAM_CUBIC, FAM_CUBIC)
   VH_GK(2, BOX1, BOX2, FAM_CUBIC, FAM_CUBIC)    // compact fine level: level-dependent
   VH_GK(2, BOX1, BOX2, FAM_LINEAR, FAM_CUBIC)   // compact fine level: mixed
   VH_GK(2, CROSS, BOX1, FAM_LINEAR, FAM_LINEAR) // bilinear
@@ -999,7 +1007,8 @@ hipError_t dense_assemble(int dim, int shape, Grid g, const cpx<double>* A, cpx<
     VH_LAUNCH_CHECK();                                                 \
     return hipSuccess;                                                 \
   }
-  VH_DA(2, CROSS) VH_DA(2, BOX1) VH_DA(2, BOX2) VH_DA(3, CROSS) VH_DA(3, BOX1) VH_DA(3, BOX2)
+  VH_DA(2, CROSS) VH_DA(2, BOX1) VH_DA(2, BOX2) VH_DA(2, BOX3) VH_DA(3, CROSS) VH_DA(3, BOX1)
+  VH_DA(3, BOX2)
 #undef VH_DA
   return hipErrorInvalidValue;
 }

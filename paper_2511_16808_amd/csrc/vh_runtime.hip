@@ -249,6 +249,7 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (o.bc != VH_BC_ABC && o.bc != VH_BC_DIRICHLET) return fail(VH_EINVAL, "unknown bc");
   if (o.stencil != VH_STENCIL_FD2 && o.stencil != VH_STENCIL_COMPACT4)
     return fail(VH_EINVAL, "unknown stencil");
+  if (o.cycle != VH_CYCLE_V && o.cycle != VH_CYCLE_W) return fail(VH_EINVAL, "unknown cycle");
   if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
     return fail(VH_EINVAL, "unknown smoother");
   if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
@@ -287,6 +288,12 @@ vh_status transfer_plan(int dim, int ig, int l, int sin, int* rf, int* pf, int* 
     *sout = BOX2;
     return VH_OK;
   }
+  if (ig == VH_IG_CUBIC) {  // R A P with radii 2 + r + 2 over 2: 5x5 from the finest, 7x7 below
+    *rf = FAM_CUBIC;
+    *pf = FAM_CUBIC;
+    *sout = (sin == CROSS || sin == BOX1) ? BOX2 : BOX3;
+    return VH_OK;
+  }
   if (ig == VH_IG_MIXED) {
     *rf = FAM_LINEAR;
     *pf = FAM_CUBIC;
@@ -313,16 +320,23 @@ vh_status residual(vh_handle* hd, Level& Lv, const void* q, const void* u, void*
   return VH_OK;
 }
 
-vh_status vcycle(vh_handle* hd, int l, const void* q, void* u) {
+// number of visits of level l + 1 from level l: two for a W-cycle unless l + 1 is the
+// coarsest level (solved directly)
+int coarse_visits(const vh_handle* hd, int l) {
+  return (hd->opt.cycle == VH_CYCLE_W && l + 2 < hd->levels) ? 2 : 1;
+}
+
+// u <- cycle(l, q, u); u is taken as zero on entry when from_zero (its content is ignored)
+vh_status vcycle(vh_handle* hd, int l, const void* q, void* u, bool from_zero) {
   Level& Lv = hd->L[l];
   if (l == hd->levels - 1) {
     VH_HIP(dense_matvec(hd->nc, hd->Dinv, hd->prec, q, u, hd->s));
     return VH_OK;
   }
   const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
-  if (nu1 == 0) VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
+  if (nu1 == 0 && from_zero) VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
   for (int k = 0; k < nu1; ++k) {
-    if (k == 0) {
+    if (k == 0 && from_zero) {
       VH_TRY(smooth(hd, Lv, q, u, true));  // u = 0: the residual is q
     } else {
       VH_TRY(residual(hd, Lv, q, u, Lv.r));
@@ -332,7 +346,7 @@ vh_status vcycle(vh_handle* hd, int l, const void* q, void* u) {
   Level& Lc = hd->L[l + 1];
   VH_TRY(residual(hd, Lv, q, u, Lv.r));
   VH_HIP(restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s));
-  VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u));
+  for (int v = 0; v < coarse_visits(hd, l); ++v) VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u, v == 0));
   VH_HIP(prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, hd->prec, Lc.u, u, hd->s));
   for (int k = 0; k < nu2; ++k) {
     VH_TRY(residual(hd, Lv, q, u, Lv.r));
@@ -350,7 +364,7 @@ vh_status precondition(vh_handle* hd, const cpx<double>* v, void* z) {
     q = L0.q;
   }
   const int tk = hd->tbegin(2);
-  VH_TRY(vcycle(hd, 0, q, z));
+  VH_TRY(vcycle(hd, 0, q, z, true));
   hd->tend(tk);
   return VH_OK;
 }
@@ -572,7 +586,7 @@ vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, 
 }
 
 // the V-cycle of vcycle() on a batch of 1 << ls sources
-vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u) {
+vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u, bool from_zero) {
   Level& Lv = hd->L[l];
   if (l == hd->levels - 1) {
     VH_HIP(batch_dense(hd->nc, ls, hd->Dinv, hd->prec, q, u, hd->s));
@@ -580,9 +594,9 @@ vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u) {
   }
   const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
   void* r = hd->br[l];
-  if (nu1 == 0) VH_HIP(fill(u, (size_t)Lv.g.N << ls, hd->prec, 0.0, 0.0, hd->s));
+  if (nu1 == 0 && from_zero) VH_HIP(fill(u, (size_t)Lv.g.N << ls, hd->prec, 0.0, 0.0, hd->s));
   for (int k = 0; k < nu1; ++k) {
-    if (k == 0) {
+    if (k == 0 && from_zero) {
       VH_TRY(bsmooth(hd, l, ls, q, u, true));
     } else {
       VH_TRY(bresidual(hd, l, ls, q, u, r));
@@ -592,7 +606,8 @@ vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u) {
   Level& Lc = hd->L[l + 1];
   VH_TRY(bresidual(hd, l, ls, q, u, r));
   VH_HIP(batch_restrict(hd->dim, Lv.rf, Lv.g, Lc.g, ls, hd->prec, r, hd->bq[l + 1], hd->s));
-  VH_TRY(vcycle_b(hd, l + 1, ls, hd->bq[l + 1], hd->bu[l + 1]));
+  for (int v = 0; v < coarse_visits(hd, l); ++v)
+    VH_TRY(vcycle_b(hd, l + 1, ls, hd->bq[l + 1], hd->bu[l + 1], v == 0));
   VH_HIP(batch_prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, ls, hd->prec, hd->bu[l + 1], u, hd->s));
   for (int k = 0; k < nu2; ++k) {
     VH_TRY(bresidual(hd, l, ls, q, u, r));
@@ -670,7 +685,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
         qv = hd->bq[0];
       }
       const int tk = hd->tbegin(2);
-      VH_TRY(vcycle_b(hd, 0, ls, qv, Zj(j)));
+      VH_TRY(vcycle_b(hd, 0, ls, qv, Zj(j), true));
       hd->tend(tk);
       VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                            PREC_F64, nullptr, Vj(j + 1), s));
@@ -976,7 +991,7 @@ vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omeg
   VH_TRY(validate(dim, n, h, omega, shift, levels, patch, o));
   if (!kappa) return fail(VH_EINVAL, "kappa is NULL");
   const int ig = resolve_intergrid(dim, o.intergrid);
-  if (ig != VH_IG_LEVDEP && ig != VH_IG_MIXED && ig != VH_IG_LINEAR)
+  if (ig != VH_IG_LEVDEP && ig != VH_IG_MIXED && ig != VH_IG_LINEAR && ig != VH_IG_CUBIC)
     return fail(VH_EINVAL, "unknown intergrid");
   if (dim == 3 && ig != VH_IG_LINEAR)
     return fail(VH_EUNSUPPORTED, "3D supports only the trilinear intergrid");
@@ -1137,7 +1152,7 @@ vh_status vh_apply_vcycle(vh_handle* hd, const void* v, void* z) {
   Level& L0 = hd->L[0];
   const size_t N = (size_t)L0.g.N;
   if (hd->prec == PREC_F64) {
-    VH_TRY(vcycle(hd, 0, v, z));
+    VH_TRY(vcycle(hd, 0, v, z, true));
   } else {
     VH_TRY(precondition(hd, (const cpx<double>*)v, L0.u));
     VH_HIP(convert(L0.u, hd->prec, z, PREC_F64, N, hd->s));
@@ -1207,7 +1222,7 @@ vh_status vh_apply_vcycle_batch(vh_handle* hd, int nsrc, const void* v, void* z)
   VH_TRY(tune_mfma(hd, ls));
   const long long n = hd->L[0].g.N;
   VH_TRY(to_batch(hd, n, S, nsrc, v, hd->bq[0]));
-  VH_TRY(vcycle_b(hd, 0, ls, hd->bq[0], hd->bZ));
+  VH_TRY(vcycle_b(hd, 0, ls, hd->bq[0], hd->bZ, true));
   VH_TRY(from_batch(hd, n, S, nsrc, hd->bZ, z));
   VH_HIP(hipStreamSynchronize(hd->s));
   return VH_OK;
@@ -1317,7 +1332,8 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
       const SlabPlan p = slab_plan(dim, g, Np, esz, (size_t)(o.restart + 1) * N0 * 16);
       if (p.own && (size_t)p.cnt_max * p.per_plane > slab_tmp) slab_tmp = (size_t)p.cnt_max * p.per_plane;
     }
-    shape = (ig == VH_IG_LINEAR) ? BOX1 : BOX2;
+    shape = (ig == VH_IG_LINEAR) ? BOX1
+            : (ig == VH_IG_CUBIC && shape != CROSS && shape != BOX1) ? BOX3 : BOX2;
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }
   total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz + slab_tmp;

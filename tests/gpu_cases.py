@@ -11,7 +11,8 @@ from oracle import discretization as D
 class Case:
     def __init__(self, n, levels, alpha=0.1, seed=0, medium="layered", ppw=10.0,
                  patch="full", precision=0, intergrid=None, damping=None, restart=20,
-                 bc="abc", sponge_width=20, smoother=0, nu=(1, 1), stencil="fd2", gamma0=None):
+                 bc="abc", sponge_width=20, smoother=0, nu=(1, 1), stencil="fd2", gamma0=None,
+                 cycle="V"):
         self.n = tuple(n)
         self.dim = len(n)
         self.N = int(np.prod(n))
@@ -30,6 +31,7 @@ class Case:
         g0 = 0.01 * self.omega if gamma0 is None else gamma0
         self.gamma = g0 * np.ones_like(self.kappa)
         self.stencil = stencil
+        self.cycle = cycle
         self.alpha = alpha
         self.levels = levels
         self.patch = patch
@@ -61,7 +63,7 @@ class Case:
         if self._oracle is None:
             ops = self.oracle_ops()
             mg = cycle.Multigrid(ops["Hs"], self.n, self.levels, self.intergrid, self.patch,
-                                 self.damping, nu1=self.nu[0], nu2=self.nu[1])
+                                 self.damping, nu1=self.nu[0], nu2=self.nu[1], cycle=self.cycle)
             self._oracle = (ops, mg)
         return self._oracle
 
@@ -69,7 +71,8 @@ class Case:
     def gpu(self, **extra):
         import torch
         from paper_2511_16808_amd import binding as B
-        ig = {"levdep": B.VH_IG_LEVDEP, "mixed": B.VH_IG_MIXED, "linear": B.VH_IG_LINEAR}
+        ig = {"levdep": B.VH_IG_LEVDEP, "mixed": B.VH_IG_MIXED, "linear": B.VH_IG_LINEAR,
+              "cubic": B.VH_IG_CUBIC}
         opt = B.make_options(precision=self.precision, restart=self.restart,
                              intergrid=ig[self.intergrid], damping=self.damping,
                              bc=B.VH_BC_ABC if self.bc == "abc" else B.VH_BC_DIRICHLET,
@@ -77,6 +80,7 @@ class Case:
                              nu1=self.nu[0], nu2=self.nu[1],
                              stencil=B.VH_STENCIL_COMPACT4 if self.stencil == "compact4"
                              else B.VH_STENCIL_FD2,
+                             cycle=B.VH_CYCLE_W if self.cycle == "W" else B.VH_CYCLE_V,
                              stream=torch.cuda.current_stream(), **extra)
         kap = torch.tensor(self.kappa.ravel(), dtype=torch.float64, device="cuda")
         gam = torch.tensor(self.gamma.ravel(), dtype=torch.float64, device="cuda")

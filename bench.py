@@ -69,6 +69,14 @@ WORKLOADS = {
                dim=3, n=(257, 257, 257), levels=6, alpha=0.4, medium="geophysical_3d", seed=3,
                precision=1, restart=20, damping=[1.1, 0.7, 0.45, 0.6], stencil="compact4",
                patch="element", gamma0=0.0, smoother="patch", sample=dict(n=(65, 65, 65), levels=4)),
+    "p3c": dict(desc="p3 with the paper's combined smoother (Sec. 5.5/5.6): damped Jacobi on the "
+                     "fine level, Element-patch Vanka on the coarser levels; 257^3 nodes, compact "
+                     "stencil, trilinear, gamma = 0, shift 0.4, 6-level V(1,1), complex64 "
+                     "preconditioner, FGMRES(20) in complex128",
+                dim=3, n=(257, 257, 257), levels=6, alpha=0.4, medium="geophysical_3d", seed=3,
+                precision=1, restart=20, damping=[0.6, 0.7, 0.45, 0.6], stencil="compact4",
+                patch="element", fine_patch="point", gamma0=0.0, smoother="patch",
+                sample=dict(n=(65, 65, 65), levels=4)),
 }
 DEFAULT_WORKLOAD = "c3"
 PATCHES = {"full": 0, "point": 1, "plus": 3, "rb": 4, "element": 5}
@@ -251,8 +259,11 @@ w = WORKLOADS[{w['key']!r}]
 n, h, omega, kappa, gamma, q = make_medium(dict(w, nsrc=1), {tuple(sample['n'])!r})
 t0 = time.perf_counter()
 ops = D.operator(w.get('stencil', 'fd2'), n, h, omega, kappa, gamma, w['alpha'])
+patch = w.get('patch', 'full')
+if w.get('fine_patch'):
+    patch = [w['fine_patch']] + [patch] * ({sample['levels']} - 2)
 mg = cycle.Multigrid(ops['Hs'], n, {sample['levels']}, 'levdep' if len(n) == 2 else 'linear',
-                     w.get('patch', 'full'), w['damping'])
+                     patch, w['damping'])
 t1 = time.perf_counter()
 its = 2
 krylov.fgmres(lambda v: ops['H'] @ v, mg.apply, q, 1e-30, w['restart'], its)
@@ -358,6 +369,8 @@ def main():
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
                          contraction=contraction)
+    if w.get("fine_patch"):
+        opt.fine_patch = PATCHES[w["fine_patch"]]
     torch.cuda.synchronize()
 
     def step():

@@ -121,6 +121,10 @@ typedef struct vh_options {
                                sweep (each coefficient and patch-inverse entry is read once
                                per group), each source with its own FP64 FGMRES state    */
     int stencil;            /* VH_STENCIL_*; default VH_STENCIL_FD2                     */
+    int fine_patch;         /* VH_PATCH_* of the finest level's smoother, or -1 (default)
+                               for the patch of vh_setup on every level.  Sec. 5.5/5.6:
+                               damped Jacobi (VH_PATCH_POINT) on the fine level with
+                               Element-patch Vanka below                                  */
     int cycle;              /* VH_CYCLE_V (default) or VH_CYCLE_W (Sec. 2.2: the coarse
                                correction visits each coarser level twice, except the
                                coarsest, solved directly)                                */

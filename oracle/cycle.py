@@ -5,7 +5,9 @@ residual r_H = R(q - A u), coarse solve, u += P e_H, nu2 post-relaxations.  A
 V-cycle replaces the coarse solve by one recursive cycle, a W-cycle by two.  The
 coarsest system is solved directly (Sec. 1, Sec. 5.4 LU), here with
 scipy.linalg.lu_factor.  Relaxation is the damped additive Vanka smoother of
-eq. (smoother) with a damping w_l per level (Table "relaxParam").
+eq. (smoother) with a damping w_l per level (Table "relaxParam").  The patch may be
+one kind for every level or one per level: Sec. 5.5/5.6 combine damped Jacobi (the
+point patch) on the fine level with Element-patch Vanka on the coarser levels.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -27,7 +29,8 @@ class Multigrid:
         while len(damping) < L - 1:
             damping.append(damping[-1])
         self.damping = damping[: max(L - 1, 0)]
-        self.smoothers = [AdditiveVanka(self.h.A[l], self.h.n[l], patch)
+        patches = [patch] * max(L - 1, 0) if isinstance(patch, str) else list(patch)
+        self.smoothers = [AdditiveVanka(self.h.A[l], self.h.n[l], patches[l])
                           for l in range(L - 1)]
         self.coarse_lu = sla.lu_factor(self.h.A[-1].toarray())
 

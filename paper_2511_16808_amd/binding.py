@@ -50,7 +50,8 @@ class vh_options(ctypes.Structure):
         ("bc", ctypes.c_int), ("sponge_width", ctypes.c_int), ("sponge_amp", ctypes.c_double),
         ("smoother", ctypes.c_int), ("ndamping", ctypes.c_int),
         ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
-        ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("cycle", ctypes.c_int),
+        ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("fine_patch", ctypes.c_int),
+        ("cycle", ctypes.c_int),
         ("contraction", ctypes.c_int),
     ]
 

@@ -60,6 +60,8 @@ struct Level {
   int rf = FAM_LINEAR, pf = FAM_LINEAR;  // transfers to level l+1
   double w = 1.0;                         // damping
   size_t bytes = 0;
+  int patch = VH_PATCH_FULL;              // patch kind of this level's smoother
+  int form = 0;                           // sweep form: the patch kind, or 2 = assembled
   int mfma_txp[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned matrix-core sweep tile per log2(S)
   int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
 };
@@ -196,8 +198,14 @@ int patch_size(int dim, int patch) {
 // damping used when the caller passes none.  Element, Plus, RB: Table "relaxParam"
 // (2D columns; 3D columns for Element and Plus, the 3D RB patch, absent from the table,
 // takes the Plus column).  Full patch: LFA smoothing-factor minimiser on the finest
-// level and an exhaustive per-level search (not in the table); point patch: LFA.
-double default_damping(int dim, int patch, int level) {
+// level and an exhaustive per-level search (not in the table).  Point patch (damped
+// Jacobi): the table's Jacobi column with the compact stencil, for which the table was
+// made; the LFA minimiser with the 2nd-order stencil.
+double default_damping(int dim, int patch, int level, int stencil) {
+  static const double jac2[] = {0.89, 0.9, 0.3, 0.71};
+  static const double jac3[] = {0.6, 0.4, 0.3, 0.5};
+  if (patch == VH_PATCH_POINT && stencil == VH_STENCIL_COMPACT4)
+    return (dim == 2 ? jac2 : jac3)[level < 3 ? level : 3];
   static const double full2[] = {0.94, 1.2, 0.4, 0.6};
   static const double full3[] = {1.08, 0.9, 0.6, 0.6};
   static const double point2[] = {0.78, 0.7, 0.4, 0.6};
@@ -250,13 +258,18 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (o.stencil != VH_STENCIL_FD2 && o.stencil != VH_STENCIL_COMPACT4)
     return fail(VH_EINVAL, "unknown stencil");
   if (o.cycle != VH_CYCLE_V && o.cycle != VH_CYCLE_W) return fail(VH_EINVAL, "unknown cycle");
+  if (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL && o.fine_patch != VH_PATCH_POINT &&
+      o.fine_patch != VH_PATCH_PLUS && o.fine_patch != VH_PATCH_RB &&
+      o.fine_patch != VH_PATCH_ELEMENT)
+    return fail(VH_EINVAL, "unknown fine_patch");
   if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
     return fail(VH_EINVAL, "unknown smoother");
   if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
   if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
     return fail(VH_EINVAL, "unknown contraction");
   if (o.contraction != VH_CONTRACT_VALU &&
-      (dim != 2 || patch != VH_PATCH_FULL || o.smoother != VH_SMOOTHER_PATCH ||
+      (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
+       o.smoother != VH_SMOOTHER_PATCH ||
        o.precision != VH_PREC_C64))
     return fail(VH_EUNSUPPORTED,
                 "the matrix-core contraction needs dim 2, the Full patch, the per-patch "
@@ -308,7 +321,7 @@ size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N *
 // ---------------------------------------------------------------- V-cycle
 vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(zero ? 0 : 1) : -1;
-  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2 : hd->patch;
+  const int form = Lv.form;
   VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
   return VH_OK;
@@ -506,7 +519,7 @@ vh_status ensure_batch(vh_handle* hd, int S) {
 vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zero) {
   Level& Lv = hd->L[l];
   const int tk = (l == 0) ? hd->tbegin(zero ? 0 : 1) : -1;
-  const int form = hd->opt.smoother == VH_SMOOTHER_ASSEMBLED ? 2 : hd->patch;
+  const int form = Lv.form;
   if (Lv.mfma_txp[ls])
     VH_HIP(batch_sweep_mfma(Lv.g, ls, hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3,
                             Lv.mfma_txp[ls], Lv.mfma_rows[ls], Lv.B, r, u, zero, hd->s));
@@ -794,9 +807,9 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
     const long long b0 = p0 - 2 > 0 ? p0 - 2 : 0;
     const long long c0 = p0 - 1 > 0 ? p0 - 1 : 0, c1 = p1 + 1 < p.n_out ? p1 + 1 : p.n_out;
     VH_HIP(fill(buf, (size_t)Np * Np * gstride, hd->prec, 0, 0, s));
-    VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, g, A, Lv.w, hd->prec, buf,
+    VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, g, A, Lv.w, hd->prec, buf,
                        Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
-    VH_HIP(vanka_assemble(dim, hd->patch, g, hd->prec, buf,
+    VH_HIP(vanka_assemble(dim, Lv.patch, g, hd->prec, buf,
                           Slab{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride}, Lv.B, s));
   }
   if (p.own) {
@@ -822,9 +835,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     Lv.g = make_grid(dim, nn[0], nn[1], nn[2]);
     Lv.shape = shape;
     Lv.K = shape_points(dim, shape);
+    Lv.patch = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : hd->patch;
     Lv.w = (l < o.ndamping) ? o.damping[l]
                             : (o.ndamping > 0 ? o.damping[o.ndamping - 1]
-                                              : default_damping(dim, hd->patch, l));
+                                              : default_damping(dim, Lv.patch, l, o.stencil));
     if (l + 1 < hd->levels) {
       int sout;
       VH_TRY(transfer_plan(dim, ig, l, shape, &Lv.rf, &Lv.pf, &sout));
@@ -866,7 +880,6 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   hd->m = o.restart;
   VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
   // per level: operator at the preconditioner precision, patch inverses, vectors
-  const int Np = patch_size(dim, hd->patch);
   for (int l = 0; l < hd->levels; ++l) {
     Level& Lv = hd->L[l];
     const size_t N = (size_t)Lv.g.N;
@@ -885,14 +898,17 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     Lv.bytes = ((size_t)Lv.K + 3) * N * hd->esz;
     if (l + 1 == hd->levels) break;
     const size_t Npad = (size_t)Lv.g.Np;  // smoother arrays use the padded row layout
-    if (o.smoother == VH_SMOOTHER_ASSEMBLED && hd->patch != VH_PATCH_POINT) {
+    const int Np = patch_size(dim, Lv.patch);
+    if (o.smoother == VH_SMOOTHER_ASSEMBLED && Lv.patch != VH_PATCH_POINT) {
       VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
+      Lv.form = 2;
     } else {
       VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
       VH_HIP(fill(Lv.B, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
-      VH_HIP(vanka_setup(dim, Lv.shape, hd->patch, Lv.g, A64[l], Lv.w, hd->prec, Lv.B,
+      VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, Lv.g, A64[l], Lv.w, hd->prec, Lv.B,
                          Slab{0, (long long)N, 0, Npad}, s));
       Lv.E = Np * Np;
+      Lv.form = Lv.patch;
     }
     Lv.bytes += (size_t)Lv.E * Npad * hd->esz;
   }
@@ -959,6 +975,7 @@ void vh_options_default(vh_options* o) {
   o->sponge_width = 20;
   o->sponge_amp = 1.0;
   o->smoother = VH_SMOOTHER_PATCH;
+  o->fine_patch = -1;
   o->ndamping = 0;
   o->stream = nullptr;
 }
@@ -1310,7 +1327,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     if (n[d] < 3) return 0;
   const size_t esz = o.precision == VH_PREC_FP64 ? 16 : 8;
   const int ig = resolve_intergrid(dim, o.intergrid);
-  const int Np = patch_size(dim, patch);
+  const int Np_c = patch_size(dim, patch);
   size_t nn[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
   size_t total = 0, N0 = nn[0] * nn[1] * nn[2], slab_tmp = 0;
   int shape = o.stencil == VH_STENCIL_COMPACT4 ? BOX1 : CROSS;
@@ -1323,7 +1340,9 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
       total += N * N * 16;
       break;
     }
-    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && patch != VH_PATCH_POINT;
+    const int lp = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : patch;
+    const int Np = (l == 0 && o.fine_patch >= 0) ? patch_size(dim, lp) : Np_c;
+    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && lp != VH_PATCH_POINT;
     const int E = assembled ? (dim == 2 ? 25 : 125) : Np * Np;
     const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
     total += (size_t)E * Npad * esz;

@@ -12,7 +12,7 @@ class Case:
     def __init__(self, n, levels, alpha=0.1, seed=0, medium="layered", ppw=10.0,
                  patch="full", precision=0, intergrid=None, damping=None, restart=20,
                  bc="abc", sponge_width=20, smoother=0, nu=(1, 1), stencil="fd2", gamma0=None,
-                 cycle="V"):
+                 cycle="V", fine_patch=None):
         self.n = tuple(n)
         self.dim = len(n)
         self.N = int(np.prod(n))
@@ -32,6 +32,7 @@ class Case:
         self.gamma = g0 * np.ones_like(self.kappa)
         self.stencil = stencil
         self.cycle = cycle
+        self.fine_patch = fine_patch
         self.alpha = alpha
         self.levels = levels
         self.patch = patch
@@ -62,7 +63,9 @@ class Case:
     def oracle(self):
         if self._oracle is None:
             ops = self.oracle_ops()
-            mg = cycle.Multigrid(ops["Hs"], self.n, self.levels, self.intergrid, self.patch,
+            patches = self.patch if self.fine_patch is None else \
+                [self.fine_patch] + [self.patch] * (self.levels - 2)
+            mg = cycle.Multigrid(ops["Hs"], self.n, self.levels, self.intergrid, patches,
                                  self.damping, nu1=self.nu[0], nu2=self.nu[1], cycle=self.cycle)
             self._oracle = (ops, mg)
         return self._oracle
@@ -84,8 +87,11 @@ class Case:
                              stream=torch.cuda.current_stream(), **extra)
         kap = torch.tensor(self.kappa.ravel(), dtype=torch.float64, device="cuda")
         gam = torch.tensor(self.gamma.ravel(), dtype=torch.float64, device="cuda")
-        patch = {"full": B.VH_PATCH_FULL, "point": B.VH_PATCH_POINT, "plus": B.VH_PATCH_PLUS,
-                 "rb": B.VH_PATCH_RB, "element": B.VH_PATCH_ELEMENT}[self.patch]
+        kinds = {"full": B.VH_PATCH_FULL, "point": B.VH_PATCH_POINT, "plus": B.VH_PATCH_PLUS,
+                 "rb": B.VH_PATCH_RB, "element": B.VH_PATCH_ELEMENT}
+        patch = kinds[self.patch]
+        if self.fine_patch is not None:
+            opt.fine_patch = kinds[self.fine_patch]
         hd = B.vh_setup(self.dim, self.n, self.h, self.omega, kap, gam, self.alpha,
                         self.levels, patch, opt)
         return hd

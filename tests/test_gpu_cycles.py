@@ -115,3 +115,57 @@ def test_operator_complexity_table_on_the_gpu(paper, levels):
         assert round(sum(nnz) / nnz[0], 3) == pytest.approx(ref, abs=5e-4), nnz
     finally:
         B.vh_destroy(hd)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_combined_jacobi_fine_element_coarse(dim):
+    """Sec. 5.5/5.6 combined smoother (damped Jacobi on the fine level, Element-patch
+    Vanka below, trilinear intergrid, compact stencil): every smoothing step to 1e-12 and
+    the V-cycle to 1e-10 against the oracle with the same per-level patches."""
+    if dim == 2:
+        c = Case(n=(65, 49), levels=3, alpha=0.3, medium="layered", seed=5, sponge_width=6,
+                 patch="element", fine_patch="point", intergrid="linear", stencil="compact4",
+                 damping=[0.89, 0.66, 0.48])
+    else:
+        c = Case(n=(17, 25, 17), levels=3, alpha=0.5, medium="random", seed=6, sponge_width=4,
+                 patch="element", fine_patch="point", intergrid="linear", stencil="compact4",
+                 damping=[0.6, 0.7, 0.45])
+    ops, mg = c.oracle()
+    hd = c.gpu()
+    try:
+        assert B.vh_get_level_info(hd, 0)["smoother_entries"] == 1
+        assert B.vh_get_level_info(hd, 1)["smoother_entries"] == (2 ** dim) ** 2
+        for l in range(c.levels - 1):
+            N = int(np.prod(mg.h.n[l]))
+            q, u = crandn(N, 10 + l), crandn(N, 20 + l)
+            ug = gpu(u)
+            B.vh_apply_smoother(hd, l, gpu(q), ug)
+            assert rel(ug.cpu().numpy(), mg.relax(l, q, u)) <= 1e-12, l
+        v = crandn(c.N, 7)
+        z = torch.empty(c.N, dtype=torch.complex128, device="cuda")
+        B.vh_apply_vcycle(hd, gpu(v), z)
+        assert rel(z.cpu().numpy(), mg.apply(v)) <= 1e-10
+    finally:
+        B.vh_destroy(hd)
+
+
+def test_combined_smoother_solve_3d():
+    """3D 33^3, linear kappa^2 in [0.25, 1] (the model of Sec. 5.5), compact stencil,
+    gamma = 0, layer, 3-level V(1,1), GMRES(5): the combined smoother's GPU iteration
+    count equals the oracle's (+-10 %)."""
+    c = Case(n=(33, 33, 33), levels=3, alpha=0.2, medium="linear", patch="element",
+             fine_patch="point", intergrid="linear", stencil="compact4", gamma0=0.0,
+             restart=5, damping=[0.6, 0.7, 0.45], sponge_width=8)
+    ops, mg = c.oracle()
+    q = synth.point_source(c.n).ravel()
+    hd = c.gpu()
+    try:
+        u = torch.empty(c.N, dtype=torch.complex128, device="cuda")
+        st, stats = B.vh_solve(hd, gpu(q), 1, 1e-6, u)
+        assert st == B.VH_OK
+        assert np.linalg.norm(q - ops["H"] @ u.cpu().numpy()) / np.linalg.norm(q) <= 1e-6
+    finally:
+        B.vh_destroy(hd)
+    _, info = krylov.fgmres(lambda v: ops["H"] @ v, mg.apply, q, 1e-6, 5, 1000)
+    its = stats[0]["iterations"]
+    assert abs(its - info["iterations"]) <= max(1, 0.1 * info["iterations"]), (its, info["iterations"])

@@ -78,6 +78,37 @@ def test_three_level_cycle_recursion(ctype):
     assert np.allclose(np.eye(N) - M @ A0, E0, atol=1e-9)
 
 
+def test_combined_jacobi_fine_vanka_coarse_cycle():
+    """Sec. 5.5/5.6: damped Jacobi on the fine level, Element-patch Vanka below.  The fine
+    smoother is u + w D^{-1}(q - A u) with D the diagonal of A (written out here, not
+    taken from the patch code); the level-1 smoother is the Element one; and the 3-level
+    V-cycle error operator is eq. (2G) nested with those two smoothers."""
+    n = (17, 17)
+    ops = small_problem(n, alpha=0.6)
+    w = [0.6, 0.7]
+    mg = cycle.Multigrid(ops["Hs"], n, 3, "linear", ["point", "element"], w)
+    ref = cycle.Multigrid(ops["Hs"], n, 3, "linear", "element", w)
+    A0 = ops["Hs"].toarray()
+    N = A0.shape[0]
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    u = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    jac = u + w[0] * (q - A0 @ u) / np.diag(A0)
+    assert np.allclose(mg.relax(0, q, u), jac, rtol=1e-13, atol=0)
+    A1 = mg.h.A[1].toarray()
+    assert np.allclose(mg.smoothers[1].dense(), ref.smoothers[1].dense(), rtol=1e-13, atol=0)
+    A2 = mg.h.A[2].toarray()
+    N1 = A1.shape[0]
+    S0 = np.eye(N) - w[0] * np.diag(1.0 / np.diag(A0)) @ A0
+    S1 = np.eye(N1) - w[1] * mg.smoothers[1].dense() @ A1
+    R1, P1 = mg.h.R[1].toarray(), mg.h.P[1].toarray()
+    E1 = S1 @ (np.eye(N1) - P1 @ np.linalg.solve(A2, R1 @ A1)) @ S1
+    R0, P0 = mg.h.R[0].toarray(), mg.h.P[0].toarray()
+    E0 = S0 @ (np.eye(N) - P0 @ (np.eye(N1) - E1) @ np.linalg.inv(A1) @ R0 @ A0) @ S0
+    M = dense_of(mg.apply, N)
+    assert np.allclose(np.eye(N) - M @ A0, E0, atol=1e-9)
+
+
 def test_givens_rotation():
     rng = np.random.default_rng(1)
     for _ in range(10):

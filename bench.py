@@ -69,7 +69,7 @@ WORKLOADS = {
                dim=3, n=(257, 257, 257), levels=6, alpha=0.4, medium="geophysical_3d", seed=3,
                precision=1, restart=20, damping=[1.1, 0.7, 0.45, 0.6], stencil="compact4",
                patch="element", gamma0=0.0, smoother="patch", sample=dict(n=(65, 65, 65), levels=4)),
-    "p3c": dict(desc="p3 with the paper's combined smoother (Sec. 5.5/5.6): damped Jacobi on the "
+    "p3c": dict(desc="p3 with the paper's combined smoother (Sec. 5.5, Sec. 6): damped Jacobi on the "
                      "fine level, Element-patch Vanka on the coarser levels; 257^3 nodes, compact "
                      "stencil, trilinear, gamma = 0, shift 0.4, 6-level V(1,1), complex64 "
                      "preconditioner, FGMRES(20) in complex128",

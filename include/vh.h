@@ -122,7 +122,7 @@ typedef struct vh_options {
                                per group), each source with its own FP64 FGMRES state    */
     int stencil;            /* VH_STENCIL_*; default VH_STENCIL_FD2                     */
     int fine_patch;         /* VH_PATCH_* of the finest level's smoother, or -1 (default)
-                               for the patch of vh_setup on every level.  Sec. 5.5/5.6:
+                               for the patch of vh_setup on every level.  Sec. 5.5, Sec. 6:
                                damped Jacobi (VH_PATCH_POINT) on the fine level with
                                Element-patch Vanka below                                  */
     int cycle;              /* VH_CYCLE_V (default) or VH_CYCLE_W (Sec. 2.2: the coarse
@@ -249,6 +249,98 @@ vh_status vh_sample_level(const vh_handle *hd, int level, int which, int count,
  * call), used for admission by footprint. */
 size_t vh_footprint_bytes(int dim, const int *n, int levels, int patch, int nsrc,
                           const vh_options *opt);
+
+/* ---- parameter selection: local Fourier analysis, convergence factor, tuners ------ */
+
+/* Local Fourier analysis of one smoother on an infinite grid with constant coefficients
+ * (Sec. 2.4, Sec. 4).  The interior stencil A of the operator is the 5/7-point stencil
+ * (VH_STENCIL_FD2) or the compact one (VH_STENCIL_COMPACT4) for sigma = omega^2 kappa^2
+ * (no attenuation), plus i*shift times the mass stencil.  For a patch with members o_k
+ * (vh.h patch order) the smoother symbol is eq. (smoother_symbol),
+ *     S(theta) = 1 - w * (phi^H A_i^{-1} phi / Np) * A(theta),  phi_k = exp(i theta.o_k),
+ * with A_i the patch matrix of the stencil.  theta runs over npts^dim samples
+ * theta_k = -pi/2 + 2 pi k / npts of [-pi/2, 3pi/2)^dim.
+ *   mu(w)  = max |S(theta)| over the high frequencies (Definition "def_mu_loc");
+ *   rho(w) = max spectral radius of the two-grid symbol of eq. (symbolTG),
+ *            S^nu2 (I - P H_c^{-1} R A) S^nu1 on the 2^dim harmonics of every low
+ *            frequency theta != 0, with H_c = sum_h R(theta_h) A(theta_h) P(theta_h)
+ *            (Galerkin) and the restriction / prolongation symbols of the 1D
+ *            families (Definition "def_rho_loc", Sec. 4.2).
+ * All of it runs on the device in FP64. */
+typedef struct vh_lfa_problem {
+    int dim;                 /* 2 or 3                                                   */
+    int stencil;             /* VH_STENCIL_FD2 or VH_STENCIL_COMPACT4                     */
+    int patch;               /* VH_PATCH_*                                               */
+    double h;                /* grid spacing (> 0)                                       */
+    double sigma;            /* omega^2 kappa^2 (>= 0)                                   */
+    double shift;            /* imaginary shift alpha omega^2 of the mass term (>= 0)    */
+    int rfam, pfam;          /* VH_IG_LINEAR or VH_IG_CUBIC: 1D restriction / prolongation
+                                weights (1/4)[1 2 1] or (1/16)[1 4 6 4 1]; default cubic  */
+    int npts;                /* samples per dimension: even, <= 512 (2D) / <= 128 (3D);
+                                default 256 (2D), 64 (3D)                                 */
+    int nu1, nu2;            /* smoothing steps of the two-grid cycle; default 1, 1       */
+    void *stream;            /* hipStream_t, NULL = the null stream                       */
+} vh_lfa_problem;
+
+void vh_lfa_problem_default(vh_lfa_problem *p);
+
+/* mu[j] = mu(w[j]), rho[j] = rho(w[j]) for the nw damping values w (HOST arrays; mu or
+ * rho may be NULL to skip that factor).  VH_EINVAL for bad fields or nw < 1. */
+vh_status vh_lfa_factors(const vh_lfa_problem *p, int nw, const double *w, double *mu,
+                         double *rho);
+
+/* LFA damping tuner (Sec. 5.2: the fine-level damping is the minimiser of the LFA
+ * factor): evaluates objective 0 = mu, 1 = rho on the nw candidates w (HOST) and
+ * returns the first minimiser in *w_best and its factor in *f_best (HOST). */
+vh_status vh_lfa_tune(const vh_lfa_problem *p, int objective, int nw, const double *w,
+                      double *w_best, double *f_best);
+
+/* The cycle as a stationary solver (Sec. 5.1, eq. (cf)): from x = 0,
+ *     x <- x + M^{-1} (q - A x)
+ * with A = H (which = 0, FP64) or A = H_s (which = 1; handles built with VH_PREC_FP64
+ * only, else VH_EUNSUPPORTED), until ||q - A x|| <= tol ||q|| or maxit cycles, or
+ * until the residual exceeds 1e12 ||q|| (divergence).
+ *   q, x : device c128[N] (x receives the last iterate; may not alias q).
+ *   hist : HOST double[maxit + 1] or NULL, ||r^(k)|| / ||q|| for k = 0..iterations.
+ * The convergence factor is c_f = (||r^(k)|| / ||r^(warmup)||)^(1/(k - warmup)) at the
+ * last k (NaN when k <= warmup). */
+typedef struct vh_cf_stats {
+    int iterations;          /* cycles applied                                           */
+    int converged;           /* 1 when tol was reached                                   */
+    double relres;           /* ||q - A x|| / ||q|| at exit                              */
+    double cf;               /* c_f of eq. (cf)                                          */
+} vh_cf_stats;
+
+vh_status vh_mg_iterate(vh_handle *hd, int which, const void *q, void *x, int warmup,
+                        int maxit, double tol, double *hist, vh_cf_stats *stats);
+
+/* Per-level damping by exhaustive search (Sec. 5.2): for l = 0 .. levels-2 in turn,
+ * each candidate w[j] (HOST, nw values) is tried as w_l with w_0..w_{l-1} fixed at the
+ * values already chosen and the deeper levels at opt's values (or the defaults); a
+ * handle is built with vh_setup's arguments (shift, levels, patch, opt) and scored by
+ *   objective 0: FGMRES iterations to tol (vh_solve; maxit + 1 if not converged),
+ *   objective 1: c_f of vh_mg_iterate(which = 1, warmup, maxit, tol) (inf if the cycle
+ *                does not run warmup + 1 steps).
+ * The first minimiser is kept.  q: device c128[N], the source.  damping: HOST
+ * double[levels-1] receives the chosen w_l; scores: HOST double[(levels-1)*nw] or NULL,
+ * score of candidate j on level l at scores[l*nw + j].  opt->precision is forced to
+ * VH_PREC_FP64 when objective = 1. */
+vh_status vh_tune_damping(int dim, const int *n, double h, double omega, const double *kappa,
+                          const double *gamma, double shift, int levels, int patch,
+                          const vh_options *opt, const void *q, int objective, int warmup,
+                          int maxit, double tol, int nw, const double *w, double *damping,
+                          double *scores);
+
+/* Shift selection (Sec. 5.2, 5.5): the smallest alpha among the na candidates alphas
+ * (HOST, increasing) for which the cycle on H_s converges as a stationary solver
+ * (c_f of vh_mg_iterate(which = 1, warmup, maxit, tol) below 1, or tol reached), on the
+ * problem given by vh_setup's arguments.  *alpha (HOST) receives it; cfs: HOST
+ * double[na] or NULL receives every candidate's c_f (tried in order, NaN after the
+ * chosen one).  VH_ENOCONV if no candidate converges. */
+vh_status vh_tune_shift(int dim, const int *n, double h, double omega, const double *kappa,
+                        const double *gamma, int levels, int patch, const vh_options *opt,
+                        const void *q, int na, const double *alphas, int warmup, int maxit,
+                        double tol, double *alpha, double *cfs);
 
 /* ---- serving: persistent request loop with admission by HBM footprint ----------
  * Requests are copied at submission and queued.  Up to max_slots requests run at

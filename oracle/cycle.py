@@ -6,7 +6,7 @@ V-cycle replaces the coarse solve by one recursive cycle, a W-cycle by two.  The
 coarsest system is solved directly (Sec. 1, Sec. 5.4 LU), here with
 scipy.linalg.lu_factor.  Relaxation is the damped additive Vanka smoother of
 eq. (smoother) with a damping w_l per level (Table "relaxParam").  The patch may be
-one kind for every level or one per level: Sec. 5.5/5.6 combine damped Jacobi (the
+one kind for every level or one per level: Sec. 5.5, Sec. 6 combine damped Jacobi (the
 point patch) on the fine level with Element-patch Vanka on the coarser levels.
 """
 import numpy as np

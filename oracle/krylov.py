@@ -90,3 +90,23 @@ def convergence_factor(history, warmup=5):
         return float("nan")
     k = h.size - 1 - warmup
     return float((h[-1] / h[warmup]) ** (1.0 / k))
+
+
+def stationary(matvec, precond, b, maxit, tol):
+    """The cycle as a stationary solver (Sec. 5.1): x <- x + M^{-1}(b - A x) from x = 0.
+    Stops when ||r|| <= tol ||b||, when the residual exceeds 1e12 ||b|| (divergence) or
+    after maxit cycles.  Returns (x, history) with history[k] = ||r^(k)|| / ||b||."""
+    b = np.asarray(b, dtype=complex)
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, [0.0]
+    hist = []
+    for k in range(maxit + 1):
+        r = b - matvec(x)
+        rel = np.linalg.norm(r) / bnorm
+        hist.append(rel)
+        if not np.isfinite(rel) or rel <= tol or rel > 1e12 or k == maxit:
+            break
+        x = x + precond(r)
+    return x, hist

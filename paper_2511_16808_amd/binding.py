@@ -96,6 +96,23 @@ class vh_server_info(ctypes.Structure):
     ]
 
 
+class vh_lfa_problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("stencil", ctypes.c_int), ("patch", ctypes.c_int),
+        ("h", ctypes.c_double), ("sigma", ctypes.c_double), ("shift", ctypes.c_double),
+        ("rfam", ctypes.c_int), ("pfam", ctypes.c_int), ("npts", ctypes.c_int),
+        ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("stream", ctypes.c_void_p),
+    ]
+
+
+class vh_cf_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres", ctypes.c_double), ("cf", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class VhError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"vh status {status}: {msg}")
@@ -134,6 +151,19 @@ _SIGNATURES = {
                               ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "vh_server_get_info": (_I, [_P, ctypes.POINTER(vh_server_info)]),
     "vh_server_destroy": (_I, [_P]),
+    "vh_lfa_problem_default": (None, [ctypes.POINTER(vh_lfa_problem)]),
+    "vh_lfa_factors": (_I, [ctypes.POINTER(vh_lfa_problem), _I, ctypes.POINTER(_D),
+                            ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "vh_lfa_tune": (_I, [ctypes.POINTER(vh_lfa_problem), _I, _I, ctypes.POINTER(_D),
+                         ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "vh_mg_iterate": (_I, [_P, _I, _P, _P, _I, _I, _D, ctypes.POINTER(_D),
+                           ctypes.POINTER(vh_cf_stats)]),
+    "vh_tune_damping": (_I, [_I, ctypes.POINTER(_I), _D, _D, _P, _P, _D, _I, _I,
+                             ctypes.POINTER(vh_options), _P, _I, _I, _I, _D, _I,
+                             ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "vh_tune_shift": (_I, [_I, ctypes.POINTER(_I), _D, _D, _P, _P, _I, _I,
+                           ctypes.POINTER(vh_options), _P, _I, ctypes.POINTER(_D), _I, _I, _D,
+                           ctypes.POINTER(_D), ctypes.POINTER(_D)]),
 }
 
 
@@ -338,6 +368,79 @@ def vh_server_get_info(srv):
 
 def vh_server_destroy(srv):
     check(lib().vh_server_destroy(srv))
+
+
+def make_lfa_problem(**kw):
+    """vh_lfa_problem with the library's defaults, overridden by keyword arguments."""
+    p = vh_lfa_problem()
+    lib().vh_lfa_problem_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "stream":
+            p.stream = v if isinstance(v, int) or v is None else v.cuda_stream
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _dvec(values):
+    return (_D * len(values))(*[float(v) for v in values])
+
+
+def vh_lfa_factors(p, w, mu=True, rho=True):
+    """Returns (mu list or None, rho list or None) for the damping values w."""
+    nw = len(w)
+    m = (_D * nw)() if mu else None
+    r = (_D * nw)() if rho else None
+    check(lib().vh_lfa_factors(ctypes.byref(p), nw, _dvec(w), m, r))
+    return (list(m) if mu else None), (list(r) if rho else None)
+
+
+def vh_lfa_tune(p, objective, w):
+    """Returns (w_best, f_best): objective 0 = mu, 1 = rho."""
+    wb, fb = _D(), _D()
+    check(lib().vh_lfa_tune(ctypes.byref(p), objective, len(w), _dvec(w), ctypes.byref(wb),
+                            ctypes.byref(fb)))
+    return wb.value, fb.value
+
+
+def vh_mg_iterate(hd, which, q, x, warmup, maxit, tol):
+    """q, x: complex128 GPU tensors.  Returns (stats dict, residual history list)."""
+    hist = (_D * (maxit + 1))()
+    st = vh_cf_stats()
+    check(lib().vh_mg_iterate(hd, which, _ptr(q, "complex128"), _ptr(x, "complex128"), warmup,
+                              maxit, float(tol), hist, ctypes.byref(st)))
+    return st.as_dict(), list(hist[:st.iterations + 1])
+
+
+def vh_tune_damping(dim, n, h, omega, kappa, gamma, shift, levels, patch, opt, q, objective,
+                    warmup, maxit, tol, w):
+    """Returns (chosen damping per level, scores[level][candidate])."""
+    arr = (_I * 3)(*(list(n) + [1] * (3 - len(n))))
+    nl = levels - 1
+    damp = (_D * nl)()
+    scores = (_D * (nl * len(w)))()
+    check(lib().vh_tune_damping(dim, arr, float(h), float(omega), _ptr(kappa, "float64"),
+                                _ptr(gamma, "float64"), float(shift), levels, patch,
+                                ctypes.byref(opt) if opt is not None else None,
+                                _ptr(q, "complex128"), objective, warmup, maxit, float(tol),
+                                len(w), _dvec(w), damp, scores))
+    return list(damp), [list(scores[l * len(w):(l + 1) * len(w)]) for l in range(nl)]
+
+
+def vh_tune_shift(dim, n, h, omega, kappa, gamma, levels, patch, opt, q, alphas, warmup, maxit,
+                  tol):
+    """Returns (status, chosen alpha or None, c_f per candidate)."""
+    arr = (_I * 3)(*(list(n) + [1] * (3 - len(n))))
+    a = _D()
+    cfs = (_D * len(alphas))()
+    st = lib().vh_tune_shift(dim, arr, float(h), float(omega), _ptr(kappa, "float64"),
+                             _ptr(gamma, "float64"), levels, patch,
+                             ctypes.byref(opt) if opt is not None else None,
+                             _ptr(q, "complex128"), len(alphas), _dvec(alphas), warmup, maxit,
+                             float(tol), ctypes.byref(a), cfs)
+    if st not in (VH_OK, VH_ENOCONV):
+        check(st)
+    return st, (a.value if st == VH_OK else None), list(cfs)
 
 
 def make_options(**kw):

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvh.so")
-SOURCES = ["vh_kernels.hip", "vh_batch.hip", "vh_mfma.hip", "vh_runtime.hip", "vh_server.hip"]
+SOURCES = ["vh_kernels.hip", "vh_batch.hip", "vh_mfma.hip", "vh_runtime.hip", "vh_server.hip",
+           "vh_lfa.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

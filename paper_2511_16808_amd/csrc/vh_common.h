@@ -210,6 +210,21 @@ __host__ __device__ constexpr double fam_r(int fam, int t) {
 // 1D prolongation weight of coarse node J at fine node 2J + t
 __host__ __device__ constexpr double fam_p(int fam, int t) { return 2.0 * fam_r(fam, t); }
 
+// Weights of the compact 4th-order stencil, eq. (disc4thCompact) / (disc4thCompact3D), by
+// the l1 distance of the offset from the centre: the Laplacian part L (times 1/h^2) and the
+// mass part M.
+template <int DIM>
+__host__ __device__ constexpr double compact_L(int l1, double ih2) {
+  // 2D: centre 10/3, axis -2/3, diagonal -1/6;  3D: centre 4, face -1/3, edge -1/6, corner 0
+  return DIM == 2 ? (l1 == 0 ? 10.0 / 3 : l1 == 1 ? -2.0 / 3 : -1.0 / 6) * ih2
+                  : (l1 == 0 ? 4.0 : l1 == 1 ? -1.0 / 3 : l1 == 2 ? -1.0 / 6 : 0.0) * ih2;
+}
+template <int DIM>
+__host__ __device__ constexpr double compact_M(int l1) {
+  // 2D: centre 2/3, axis 1/12;  3D: centre 1/2, axis 1/12
+  return l1 == 0 ? (DIM == 2 ? 2.0 / 3 : 0.5) : (l1 == 1 ? 1.0 / 12 : 0.0);
+}
+
 // ---------------------------------------------------------------- launch helpers
 // Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD owns one
 // contiguous range of the domain (its L2 then sees neighbouring rows).

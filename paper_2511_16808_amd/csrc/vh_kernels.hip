@@ -144,17 +144,6 @@ __global__ __launch_bounds__(256) void k_fine_operator(Grid g, const double* __r
 // printed for constant kappa), H_s = H + i alpha omega^2 M.  Both as 3^DIM-box arrays
 // (x fastest); weights pointing outside the grid are dropped; with bc = BC_ABC the
 // absorbing layer is added to gamma (no Sommerfeld rows for this stencil).
-template <int DIM>
-__host__ __device__ constexpr double compact_L(int l1, double ih2) {
-  // 2D: centre 10/3, axis -2/3, diagonal -1/6;  3D: centre 4, face -1/3, edge -1/6, corner 0
-  return DIM == 2 ? (l1 == 0 ? 10.0 / 3 : l1 == 1 ? -2.0 / 3 : -1.0 / 6) * ih2
-                  : (l1 == 0 ? 4.0 : l1 == 1 ? -1.0 / 3 : l1 == 2 ? -1.0 / 6 : 0.0) * ih2;
-}
-template <int DIM>
-__host__ __device__ constexpr double compact_M(int l1) {
-  // 2D: centre 2/3, axis 1/12;  3D: centre 1/2, axis 1/12
-  return l1 == 0 ? (DIM == 2 ? 2.0 / 3 : 0.5) : (l1 == 1 ? 1.0 / 12 : 0.0);
-}
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_fine_compact4(Grid g, const double* __restrict__ kappa,

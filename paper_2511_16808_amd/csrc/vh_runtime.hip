@@ -1315,6 +1315,219 @@ vh_status vh_sample_level(const vh_handle* hdc, int level, int which, int count,
   return VH_OK;
 }
 
+// ---------------------------------------------------------------- parameter selection
+// The cycle as a stationary solver, x <- x + M^{-1} (q - A x) from x = 0, and the
+// convergence factor of eq. (cf) (Sec. 5.1).  The residual lives in basis column 0 and
+// the correction in Z column 0; the update x += Z_0 * 1 reuses the FGMRES solution
+// update with y = (1).
+vh_status vh_mg_iterate(vh_handle* hd, int which, const void* q, void* x, int warmup, int maxit,
+                        double tol, double* hist, vh_cf_stats* stats) {
+  if (!hd || !q || !x || q == x || (which != 0 && which != 1) || warmup < 0 || maxit < 1 ||
+      !(tol >= 0.0))
+    return fail(VH_EINVAL, "bad argument");
+  if (which == 1 && hd->prec != PREC_F64)
+    return fail(VH_EUNSUPPORTED, "the stationary iteration on H_s needs a VH_PREC_FP64 handle");
+  Level& L0 = hd->L[0];
+  const size_t N = (size_t)L0.g.N;
+  KrylovDev* K = hd->K;
+  cpx<double>* r = hd->V;
+  const void* A = which == 0 ? (const void*)hd->Hfine : L0.A;
+  cpx<double>* xd = (cpx<double>*)x;
+  const cpx<double> one = cmk(1.0, 0.0);
+  VH_HIP(hipMemcpyAsync(K->y, &one, sizeof(one), hipMemcpyHostToDevice, hd->s));
+  VH_HIP(hipStreamSynchronize(hd->s));
+  VH_HIP(fill(x, N, PREC_F64, 0.0, 0.0, hd->s));
+  double rq = 0.0, rw = NAN, rn = 0.0, rel = 0.0;
+  int k = 0;
+  bool conv = false;
+  for (;; ++k) {
+    VH_HIP(stencil(hd->dim, L0.shape, L0.g, OP_RESID, PREC_F64, A, PREC_F64, xd, PREC_F64, q, r,
+                   hd->s));
+    VH_HIP(cgs_pass(2, hd->V, N, 0, K->h2, r, N, hd->part, hd->nred, K->nrm2, hd->s));
+    VH_HIP(cycle_init(K, hd->m, hd->s));
+    VH_TRY(read_status(hd));
+    rn = hd->hstat[3];
+    if (k == 0) {
+      rq = rn;
+      if (rq == 0.0) {
+        conv = true;
+        rel = 0.0;
+        if (hist) hist[0] = 0.0;
+        break;
+      }
+    }
+    rel = rn / rq;
+    if (hist) hist[k] = rel;
+    if (k == warmup) rw = rn;
+    if (!std::isfinite(rn)) break;
+    if (rel <= tol) {
+      conv = true;
+      break;
+    }
+    if (rel > 1e12 || k == maxit) break;
+    VH_TRY(precondition(hd, r, hd->Z));
+    VH_HIP(update_x(K, 1, hd->prec, hd->Z, N, xd, N, hd->s));
+  }
+  VH_HIP(hipStreamSynchronize(hd->s));
+  if (stats) {
+    stats->iterations = k;
+    stats->converged = conv ? 1 : 0;
+    stats->relres = rel;
+    stats->cf = (k > warmup && rw > 0.0 && std::isfinite(rw))
+                    ? std::pow(rn / rw, 1.0 / (double)(k - warmup))
+                    : NAN;
+  }
+  return VH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The damping the build would use on each of the first levels-1 levels.
+void effective_damping(int dim, int levels, int patch, const vh_options& o, double* w) {
+  for (int l = 0; l + 1 < levels && l < 16; ++l) {
+    const int pl = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : patch;
+    w[l] = (l < o.ndamping) ? o.damping[l]
+                            : (o.ndamping > 0 ? o.damping[o.ndamping - 1]
+                                              : default_damping(dim, pl, l, o.stencil));
+  }
+}
+
+struct DeviceVec {
+  void* p = nullptr;
+  ~DeviceVec() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// score of one configuration: FGMRES iterations (objective 0) or c_f (objective 1);
+// +inf when the configuration breaks down.  Setup errors other than a breakdown are
+// returned.
+vh_status score_config(int dim, const int* n, double h, double omega, const double* kappa,
+                       const double* gamma, double shift, int levels, int patch,
+                       const vh_options& o, const void* q, void* x, int objective, int warmup,
+                       int maxit, double tol, double* score, vh_cf_stats* cfs) {
+  vh_handle* hd = nullptr;
+  vh_status st = vh_setup(&hd, dim, n, h, omega, kappa, gamma, shift, levels, patch, &o);
+  if (st != VH_OK) return st;
+  if (objective == 0) {
+    vh_solve_stats ss{};
+    st = vh_solve(hd, q, 1, tol, x, &ss);
+    if (st == VH_OK)
+      *score = ss.iterations;
+    else if (st == VH_ENOCONV)
+      *score = o.maxit + 1;
+    else if (st == VH_EBREAKDOWN)
+      *score = INFINITY;
+  } else {
+    vh_cf_stats cs{};
+    st = vh_mg_iterate(hd, 1, q, x, warmup, maxit, tol, nullptr, &cs);
+    if (st == VH_OK) {
+      if (cs.converged && cs.iterations <= warmup)
+        *score = 0.0;
+      else
+        *score = std::isfinite(cs.cf) ? cs.cf : INFINITY;
+      if (cfs) *cfs = cs;
+    }
+  }
+  const vh_status sd = vh_destroy(hd);
+  if (st == VH_ENOCONV || st == VH_EBREAKDOWN) st = VH_OK;
+  return st != VH_OK ? st : sd;
+}
+
+}  // namespace
+
+extern "C" {
+
+vh_status vh_tune_damping(int dim, const int* n, double h, double omega, const double* kappa,
+                          const double* gamma, double shift, int levels, int patch,
+                          const vh_options* opt, const void* q, int objective, int warmup,
+                          int maxit, double tol, int nw, const double* w, double* damping,
+                          double* scores) {
+  if (!n || !kappa || !q || !w || !damping || nw < 1 || levels < 2 || levels > 16 ||
+      (objective != 0 && objective != 1) || warmup < 0 || maxit < 1 || !(tol > 0.0) ||
+      (dim != 2 && dim != 3))
+    return fail(VH_EINVAL, "bad argument");
+  for (int j = 0; j < nw; ++j)
+    if (!std::isfinite(w[j])) return fail(VH_EINVAL, "non-finite damping candidate");
+  vh_options o;
+  if (opt)
+    o = *opt;
+  else
+    vh_options_default(&o);
+  if (objective == 1) o.precision = VH_PREC_FP64;
+  if (objective == 0) o.maxit = maxit;
+  o.timing = 0;
+  double cur[16] = {0};
+  effective_damping(dim, levels, patch, o, cur);
+  long long N = 1;
+  for (int d = 0; d < dim; ++d) N *= (n[d] > 0 ? n[d] : 0);
+  if (N <= 0) return fail(VH_EINVAL, "bad grid");
+  DeviceVec x;
+  VH_HIP(hipMalloc(&x.p, (size_t)N * sizeof(cpx<double>)));
+  bool all_ok = true;
+  for (int l = 0; l + 1 < levels; ++l) {
+    double best = INFINITY;
+    int bj = -1;
+    for (int j = 0; j < nw; ++j) {
+      cur[l] = w[j];
+      o.ndamping = levels - 1;
+      for (int i = 0; i + 1 < levels; ++i) o.damping[i] = cur[i];
+      double sc = INFINITY;
+      VH_TRY(score_config(dim, n, h, omega, kappa, gamma, shift, levels, patch, o, q, x.p,
+                          objective, warmup, maxit, tol, &sc, nullptr));
+      if (scores) scores[(size_t)l * nw + j] = sc;
+      if (sc < best) {
+        best = sc;
+        bj = j;
+      }
+    }
+    if (bj < 0) all_ok = false;
+    cur[l] = bj >= 0 ? w[bj] : w[0];
+    damping[l] = cur[l];
+  }
+  return all_ok ? VH_OK : fail(VH_ENOCONV, "every candidate broke down on some level");
+}
+
+vh_status vh_tune_shift(int dim, const int* n, double h, double omega, const double* kappa,
+                        const double* gamma, int levels, int patch, const vh_options* opt,
+                        const void* q, int na, const double* alphas, int warmup, int maxit,
+                        double tol, double* alpha, double* cfs) {
+  if (!n || !kappa || !q || !alphas || !alpha || na < 1 || warmup < 0 || maxit < 1 ||
+      !(tol > 0.0) || (dim != 2 && dim != 3))
+    return fail(VH_EINVAL, "bad argument");
+  vh_options o;
+  if (opt)
+    o = *opt;
+  else
+    vh_options_default(&o);
+  o.precision = VH_PREC_FP64;
+  o.timing = 0;
+  long long N = 1;
+  for (int d = 0; d < dim; ++d) N *= (n[d] > 0 ? n[d] : 0);
+  if (N <= 0) return fail(VH_EINVAL, "bad grid");
+  DeviceVec x;
+  VH_HIP(hipMalloc(&x.p, (size_t)N * sizeof(cpx<double>)));
+  if (cfs)
+    for (int j = 0; j < na; ++j) cfs[j] = NAN;
+  for (int j = 0; j < na; ++j) {
+    if (!(alphas[j] >= 0.0) || !std::isfinite(alphas[j]))
+      return fail(VH_EINVAL, "shift candidates must be finite and >= 0");
+    double sc = INFINITY;
+    vh_cf_stats cs{};
+    cs.cf = NAN;
+    VH_TRY(score_config(dim, n, h, omega, kappa, gamma, alphas[j], levels, patch, o, q, x.p, 1,
+                        warmup, maxit, tol, &sc, &cs));
+    if (cfs) cfs[j] = cs.cf;
+    if (sc < 1.0) {
+      *alpha = alphas[j];
+      return VH_OK;
+    }
+  }
+  return fail(VH_ENOCONV, "no candidate shift gives a convergent cycle");
+}
+
 size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc,
                           const vh_options* opt) {
   vh_options o;

@@ -72,6 +72,13 @@ class Case:
 
     # ---- GPU side
     def gpu(self, **extra):
+        from paper_2511_16808_amd import binding as B
+        a = self.gpu_args(**extra)
+        return B.vh_setup(self.dim, self.n, self.h, self.omega, a["kappa"], a["gamma"],
+                          self.alpha, self.levels, a["patch"], a["opt"])
+
+    def gpu_args(self, **extra):
+        """kappa and gamma on the GPU, the patch code and the options of vh_setup."""
         import torch
         from paper_2511_16808_amd import binding as B
         ig = {"levdep": B.VH_IG_LEVDEP, "mixed": B.VH_IG_MIXED, "linear": B.VH_IG_LINEAR,
@@ -92,9 +99,7 @@ class Case:
         patch = kinds[self.patch]
         if self.fine_patch is not None:
             opt.fine_patch = kinds[self.fine_patch]
-        hd = B.vh_setup(self.dim, self.n, self.h, self.omega, kap, gam, self.alpha,
-                        self.levels, patch, opt)
-        return hd
+        return {"kappa": kap, "gamma": gam, "patch": patch, "opt": opt}
 
 
 def stencil_entries(A, n, offsets):

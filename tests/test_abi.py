@@ -74,3 +74,32 @@ def test_footprint_matches_the_layout():
     f64 = B.vh_footprint_bytes(2, n, 7, B.VH_PATCH_FULL, 200, ob)
     assert fp < f9 == f16 < f64
     assert B.vh_footprint_bytes(2, (2, 5), 1, B.VH_PATCH_FULL, 1) == 0
+
+
+def test_lfa_and_tuners_reject_bad_arguments_before_any_device_work():
+    p = B.make_lfa_problem()
+    assert (p.dim, p.npts, p.nu1, p.nu2, p.rfam) == (2, 256, 1, 1, B.VH_IG_CUBIC)
+    for field, value in (("npts", 3), ("npts", 514), ("dim", 4), ("patch", 2), ("h", 0.0),
+                         ("sigma", -1.0), ("rfam", B.VH_IG_LEVDEP), ("stencil", 7)):
+        q = B.make_lfa_problem(**{field: value})
+        with pytest.raises(B.VhError) as e:
+            B.vh_lfa_factors(q, [0.8])
+        assert e.value.status == B.VH_EINVAL, field
+    with pytest.raises(B.VhError) as e:
+        B.vh_lfa_factors(B.make_lfa_problem(dim=3, npts=130), [0.8])
+    assert e.value.status == B.VH_EINVAL
+    with pytest.raises(B.VhError) as e:
+        B.vh_lfa_tune(p, 2, [0.8])
+    assert e.value.status == B.VH_EINVAL
+    with pytest.raises(B.VhError) as e:
+        B.vh_lfa_factors(p, [float("nan")])
+    assert e.value.status == B.VH_EINVAL
+    with pytest.raises(B.VhError) as e:  # one level has nothing to tune
+        B.vh_tune_damping(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 1, B.VH_PATCH_FULL,
+                          None, None, 0, 0, 10, 1e-6, [0.8])
+    assert e.value.status == B.VH_EINVAL
+    st = B.lib().vh_tune_shift(2, None, 1.0, 1.0, None, None, 2, 0, None, None, 0, None, 0, 1,
+                               1e-6, None, None)
+    assert st == B.VH_EINVAL
+    st = B.lib().vh_mg_iterate(None, 1, None, None, 0, 1, 1e-6, None, None)
+    assert st == B.VH_EINVAL

@@ -119,7 +119,7 @@ def test_operator_complexity_table_on_the_gpu(paper, levels):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_combined_jacobi_fine_element_coarse(dim):
-    """Sec. 5.5/5.6 combined smoother (damped Jacobi on the fine level, Element-patch
+    """Sec. 5.5, Sec. 6 combined smoother (damped Jacobi on the fine level, Element-patch
     Vanka below, trilinear intergrid, compact stencil): every smoothing step to 1e-12 and
     the V-cycle to 1e-10 against the oracle with the same per-level patches."""
     if dim == 2:

@@ -79,7 +79,7 @@ def test_three_level_cycle_recursion(ctype):
 
 
 def test_combined_jacobi_fine_vanka_coarse_cycle():
-    """Sec. 5.5/5.6: damped Jacobi on the fine level, Element-patch Vanka below.  The fine
+    """Sec. 5.5, Sec. 6: damped Jacobi on the fine level, Element-patch Vanka below.  The fine
     smoother is u + w D^{-1}(q - A u) with D the diagonal of A (written out here, not
     taken from the patch code); the level-1 smoother is the Element one; and the 3-level
     V-cycle error operator is eq. (2G) nested with those two smoothers."""
@@ -189,3 +189,31 @@ def test_table_heterogeneous2d_two_level(paper):
         mg = cycle.Multigrid(ops["Hs"], n, levels, "levdep", "rb", paper["damping_2d"]["rb"])
         _, info = krylov.fgmres(lambda v: ops["H"] @ v, mg.apply, q, 1e-6, 5, 1000)
         assert abs(info["iterations"] - target) <= tol, (levels, info["iterations"])
+
+
+def test_stationary_iteration_residuals_are_powers_of_the_error_operator():
+    """Sec. 5.1: x <- x + M^{-1}(q - A x) from x = 0 gives r^(k) = (I - A M^{-1})^k q;
+    checked against dense matrix powers (M^{-1} assembled column by column), and the
+    convergence factor of eq. (cf) against the same norms; an exact preconditioner
+    stops after one cycle."""
+    n = (9, 9)
+    ops = small_problem(n)
+    A = ops["Hs"].toarray()
+    mg = cycle.Multigrid(ops["Hs"], n, 2, "levdep", "full", [0.8])
+    Minv = dense_of(mg.apply, 81)
+    q = np.random.default_rng(3).standard_normal(81) + 1j * np.random.default_rng(4).standard_normal(81)
+    x, hist = krylov.stationary(lambda v: ops["Hs"] @ v, mg.apply, q, 6, 1e-14)
+    E = np.eye(81) - A @ Minv
+    ref = [np.linalg.norm(np.linalg.matrix_power(E, k) @ q) / np.linalg.norm(q)
+           for k in range(len(hist))]
+    assert len(hist) == 7
+    assert np.allclose(hist, ref, rtol=1e-8, atol=0)
+    cf = krylov.convergence_factor(hist, warmup=2)
+    assert cf == pytest.approx((ref[6] / ref[2]) ** (1 / 4), rel=1e-8)
+    # exact inverse: one cycle
+    x, hist = krylov.stationary(lambda v: ops["Hs"] @ v,
+                                lambda v: np.linalg.solve(A, v), q, 10, 1e-12)
+    assert len(hist) == 2 and hist[1] <= 1e-12
+    # divergence stops at 1e12
+    x, hist = krylov.stationary(lambda v: ops["Hs"] @ v, lambda v: -50.0 * v, q, 400, 1e-12)
+    assert hist[-1] > 1e12 and len(hist) < 400

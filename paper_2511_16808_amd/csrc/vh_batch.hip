@@ -10,6 +10,8 @@
 // with lane shuffles (stride S) and a fixed-order tree: a source's result does not
 // depend on the values of the other sources, only (through the summation order) on
 // the batch width S.
+#include <type_traits>
+
 #include "vh_launch.h"
 
 namespace vh {
@@ -347,6 +349,147 @@ __global__ __launch_bounds__(256) void kb_sweep2d_wide(Grid g, const cpx<T>* __r
   }
 }
 
+// 2D, 64 sources: one wave = one node x 64 sources (lane = source).  A block of 4 waves
+// covers 4 grid rows and walks along x over a strip of columns, one column per step.
+//  - residual: each lane keeps the 5 x 5 window of its node in registers (a ring over
+//    the 5 columns, indexed at compile time by unrolling the walk by 5); a step brings in
+//    the next column of the block's 8 residual rows (y0 - 2 .. y0 + 5) through a 5-slot
+//    LDS ring, so a residual value is loaded from memory twice per sweep (8 rows for 4
+//    outputs) and read from LDS 5 times;
+//  - smoother entries: wave-uniform per node, staged in LDS for 5 steps at a time with
+//    row-segment loads and read as broadcasts;
+//  - every global load is issued 5 steps (or one 5-step chunk) before its use, so the
+//    walk does not wait on memory latency at each step.
+// One barrier per step: column k is written to ring slot k % 5 before the barrier of
+// step k and read after it, its next writer is step k + 5; the entries of chunk q + 1
+// are written after the barrier of step 5q (chunk q - 1, the previous user of that
+// buffer, was read before it) and first read after the barrier of step 5q + 5.
+constexpr int B64_ROWS = 4, B64_TX = 16;
+
+__device__ __forceinline__ void lds_barrier_b() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int FORM, bool ZERO, class T>
+__global__ __launch_bounds__(256) void kb_sweep2d_s64(Grid g, int tx,
+                                                      const cpx<T>* __restrict__ G,
+                                                      const cpx<T>* __restrict__ r,
+                                                      cpx<T>* __restrict__ u) {
+  constexpr int E = bsm_entries<2, FORM>();
+  constexpr int CR = B64_ROWS + 4, CH = 5;
+  constexpr int GN = B64_ROWS * E * CH, GPT = (GN + 255) / 256;
+  __shared__ cpx<T> col[CH][CR][64];
+  __shared__ cpx<T> gch[2][B64_ROWS][E][CH];
+  const int nsx = (g.nx + tx - 1) / tx;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int xs = (int)(b % (unsigned)nsx) * tx, y0 = (int)(b / (unsigned)nsx) * B64_ROWS;
+  const int xe = min(xs + tx, g.nx);  // outputs xs .. xe - 1
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int y = y0 + wv;
+  const bool row_ok = y < g.ny;
+  // this thread's two residual rows of every column: y0 - 2 + wv and y0 + 2 + wv
+  const int ya = y0 - 2 + wv, yb = y0 + 2 + wv;
+  const bool ya_ok = (unsigned)ya < (unsigned)g.ny, yb_ok = (unsigned)yb < (unsigned)g.ny;
+  const cpx<T>* ra = r + (size_t)lin_b(g, 0, ya_ok ? ya : 0, 0) * 64 + lane;
+  const cpx<T>* rb = r + (size_t)lin_b(g, 0, yb_ok ? yb : 0, 0) * 64 + lane;
+  const size_t Np = (size_t)g.Np;
+  cpx<T>* ur = u + (size_t)lin_b(g, 0, row_ok ? y : 0, 0) * 64 + lane;
+  const int nstep = xe - xs + 4;  // step k reads column xs - 2 + k, outputs xs + k - 4
+  cpx<T> w[5][5];                 // [dy][column ring slot]
+  cpx<T> pa[CH], pb[CH];          // residual columns in flight, by ring slot
+  cpx<T> uf[CH];                  // u of the outputs in flight, by ring slot
+  cpx<T> gp[GPT];                 // smoother entries of the next chunk
+  auto fetch_col = [&](int cx, cpx<T>& a, cpx<T>& c) {
+    const bool ok = (unsigned)cx < (unsigned)g.nx;
+    a = (ok && ya_ok) ? ra[(size_t)cx * 64] : cmk<T>(0, 0);
+    c = (ok && yb_ok) ? rb[(size_t)cx * 64] : cmk<T>(0, 0);
+  };
+  auto fetch_u = [&](int x) -> cpx<T> {
+    return (!ZERO && x >= xs && x < xe && row_ok) ? ur[(size_t)x * 64] : cmk<T>(0, 0);
+  };
+  // chunk q: output nodes xs + 5q - 4 + j (j < 5), rows y0 .. y0 + 3, entries [e]
+  auto fetch_g = [&](int q) {
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      const int j = idx % CH, e = (idx / CH) % E, row = idx / (CH * E);
+      const int x = xs + CH * q - 4 + j, yy = y0 + row;
+      gp[i] = (idx < GN && x >= xs && x < xe && yy < g.ny)
+                  ? G[(size_t)e * Np + linp_b(g, x, yy, 0)]
+                  : cmk<T>(0, 0);
+    }
+  };
+  auto store_g = [&](int q) {
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      if (idx < GN) (&gch[q & 1][0][0][0])[idx] = gp[i];
+    }
+  };
+  auto step = [&](int k, auto ph) {
+    constexpr int PH = decltype(ph)::value;  // k % 5
+    col[PH][wv][lane] = pa[PH];
+    col[PH][wv + 4][lane] = pb[PH];
+    if (k + CH < nstep) fetch_col(xs - 2 + k + CH, pa[PH], pb[PH]);
+    lds_barrier_b();
+    if (PH == 0) {
+      const int q = k / CH;
+      if (CH * (q + 1) < nstep) store_g(q + 1);
+      if (CH * (q + 2) < nstep) fetch_g(q + 2);
+    }
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy) w[dy][PH] = col[PH][wv + dy][lane];
+    const cpx<T> uo = uf[PH];
+    if (!ZERO) uf[PH] = fetch_u(xs + k + 1);  // the output of step k + 5
+    if (k >= 4 && row_ok) {
+      const cpx<T>* gq = &gch[(k / CH) & 1][wv][0][PH];
+      cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
+        acc = cfma(gq[e * CH], w[dy + 2][(PH + dx + 3) % 5], acc);
+      }
+      ur[(size_t)(xs + k - 4) * 64] = ZERO ? acc : (uo + acc);
+    }
+  };
+  // prologue: columns of steps 0..4, u of their outputs, entries of chunks 0 (in LDS)
+  // and 1 (in registers)
+#pragma unroll
+  for (int p = 0; p < CH; ++p) {
+    fetch_col(xs - 2 + p, pa[p], pb[p]);
+    uf[p] = fetch_u(xs + p - 4);
+  }
+  fetch_g(0);
+  store_g(0);
+  fetch_g(1);
+#pragma unroll 1
+  for (int k0 = 0; k0 < nstep; k0 += CH) {
+    step(k0, std::integral_constant<int, 0>{});
+    if (k0 + 1 < nstep) step(k0 + 1, std::integral_constant<int, 1>{});
+    if (k0 + 2 < nstep) step(k0 + 2, std::integral_constant<int, 2>{});
+    if (k0 + 3 < nstep) step(k0 + 3, std::integral_constant<int, 3>{});
+    if (k0 + 4 < nstep) step(k0 + 4, std::integral_constant<int, 4>{});
+  }
+}
+
+template <int FORM, class T>
+static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero, hipStream_t st) {
+  // balanced strips of at most B64_TX columns
+  const int nsx = (g.nx + B64_TX - 1) / B64_TX;
+  const int tx = (g.nx + nsx - 1) / nsx;
+  const int nsx2 = (g.nx + tx - 1) / tx;
+  const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + B64_ROWS - 1) / B64_ROWS);
+  if (zero)
+    kb_sweep2d_s64<FORM, true, T><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                      (cpx<T>*)u);
+  else
+    kb_sweep2d_s64<FORM, false, T><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
+                                                       (const cpx<T>*)r, (cpx<T>*)u);
+}
+
 template <int FORM, class T, int LS>
 static void launch_wide(Grid g, const void* G, const void* r, void* u, bool zero, size_t lds,
                         hipStream_t st) {
@@ -362,6 +505,13 @@ static void launch_wide(Grid g, const void* G, const void* r, void* u, bool zero
 template <int DIM, int FORM, class T>
 static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u, bool zero,
                            hipStream_t st) {
+  if constexpr (DIM == 2 && FORM == 2) {
+    if (ls == 6) {
+      launch_s64<FORM, T>(g, G, r, u, zero, st);
+      VHB_CHECK();
+      return hipSuccess;
+    }
+  }
   if (DIM == 2 && ls >= 4) {
     const size_t lds = ((size_t)bsm_entries<2, FORM>() * BW_NB +
                         (size_t)(BW_NB + 4) * 5 * ((size_t)1 << ls)) * sizeof(cpx<T>);

@@ -98,3 +98,38 @@ def test_batch_of_64_sources_2d_ragged_tile(smoother):
     st1, stats1, u1 = solve(c, q[5], batch=1)
     assert stats1[0]["iterations"] == stats[5]["iterations"]
     assert np.linalg.norm(u1[0] - u[5]) <= 1e-10 * np.linalg.norm(u[5])
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_batch_of_64_assembled_smoothing_step_every_level(precision, tol):
+    """64 sources, assembled smoother, on an 81 x 69 grid (strips of 27 columns, a last
+    block of one row) and its 41 x 35 level: one smoothing step per source and level
+    against the oracle's relaxation (FP64 1e-12, complex64 1e-5), from a non-zero u, and
+    one V-cycle (FP64 1e-10, complex64 1e-5)."""
+    c = Case(n=(81, 69), levels=3, alpha=0.3, medium="layered", seed=6, sponge_width=8,
+             smoother=B.VH_SMOOTHER_ASSEMBLED, precision=precision)
+    ops, mg = c.oracle()
+    hd = c.gpu(batch=1)
+    rng = np.random.default_rng(11)
+    try:
+        for l in range(c.levels - 1):
+            N = int(np.prod(mg.h.n[l]))
+            q = rng.standard_normal((64, N)) + 1j * rng.standard_normal((64, N))
+            u = rng.standard_normal((64, N)) + 1j * rng.standard_normal((64, N))
+            ug = torch.tensor(u, dtype=torch.complex128, device="cuda")
+            qg = torch.tensor(q, dtype=torch.complex128, device="cuda")
+            B.vh_apply_smoother_batch(hd, l, 64, qg, ug)
+            out = ug.cpu().numpy()
+            for s in (0, 17, 40, 63):
+                ref = mg.relax(l, q[s], u[s])
+                assert np.linalg.norm(out[s] - ref) <= tol * np.linalg.norm(ref), (l, s)
+        v = rng.standard_normal((64, c.N)) + 1j * rng.standard_normal((64, c.N))
+        z = torch.empty((64, c.N), dtype=torch.complex128, device="cuda")
+        B.vh_apply_vcycle_batch(hd, 64, torch.tensor(v, dtype=torch.complex128, device="cuda"), z)
+        out = z.cpu().numpy()
+        for s in (0, 63):
+            ref = mg.apply(v[s])
+            vt = 1e-10 if precision == 0 else 1e-5
+            assert np.linalg.norm(out[s] - ref) <= vt * np.linalg.norm(ref), s
+    finally:
+        B.vh_destroy(hd)

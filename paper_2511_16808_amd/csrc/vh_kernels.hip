@@ -5,6 +5,8 @@
 // Blocks are remapped so that each XCD owns a contiguous slab of the domain.
 // No atomics anywhere: overlap-adds are gathers, reductions run in a fixed order,
 // so every result is bitwise reproducible.
+#include <type_traits>
+
 #include "vh_launch.h"
 
 namespace vh {
@@ -446,6 +448,16 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
 // G[(i*Np + m)][c + off_i].
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
+// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>): a loop whose
+// index is a compile-time constant in every iteration
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // is (x, y, z) the anchor of a patch?  Every node is, except for ELEMENT patches, which
 // are anchored at the lowest corner of every cell
 template <int DIM, int PATCH>
@@ -485,7 +497,7 @@ __host__ __device__ constexpr int setup_waves() {
 }
 
 template <int DIM, int SHAPE, int PATCH, class T>
-__global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
+__global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
                                                      double w, cpx<T>* __restrict__ G, Slab sl) {
   constexpr int Np = patch_Np<DIM, PATCH>();
   constexpr int PPW = 64 / Np;
@@ -529,49 +541,59 @@ __global__ __launch_bounds__(256) void k_vanka_setup(Grid g, const cpx<double>* 
     }
   }
 
-  // Gauss-Jordan steps: the step loop stays rolled and every access to the row a[]
-  // uses a compile-time index (select by comparison), so a[] lives in registers.
+  // Gauss-Jordan steps with a rotating row: at step s, a[0] holds column s of the
+  // working matrix, a[1 .. Np-1-s] the columns after it and a[Np-s ..] the inverse's
+  // columns of steps 0 .. s-1; every step shifts the row down by one and appends the
+  // new inverse column, so the loop stays rolled and every register index is static.
+  // The pivot is the unused row with the largest |re| + |im| in a[0] (the first one on
+  // ties), found by a tree over the patch's lanes; its raw row is broadcast with lane
+  // shuffles and every row takes a[m] <- keep * a[m+1] + c * p[m+1], a[Np-1] <- c, with
+  // keep = 0, c = 1/p[0] on the pivot row and keep = 1, c = -a[0]/p[0] on the others
+  // (no divergent branch).  After the last step a[s] = A^{-1}[step(L)][piv[s]].
   // The pivot sequence of each patch is kept in LDS.
   __shared__ unsigned char pivs[PB * Np];
   bool used = false;
   int mystep = k;
 #pragma unroll 1
   for (int s = 0; s < Np; ++s) {
-    cpx<double> as = cmk(0.0, 0.0);
+    const cpx<double> as = a[0];
+    double bv = in_slot ? (used ? -1.0 : (fabs(as.re) + fabs(as.im))) : -3.0;
+    int bi = k;
 #pragma unroll
-    for (int m = 0; m < Np; ++m)
-      if (m == s) as = a[m];
-    const double v = used ? -1.0 : (fabs(as.re) + fabs(as.im));
-    int best = 0;
-    double bv = -2.0;
-#pragma unroll
-    for (int r = 0; r < Np; ++r) {
-      const double vr = shfl_d(v, base + r);
-      if (vr > bv) {
-        bv = vr;
-        best = r;
+    for (int off = 16; off >= 1; off >>= 1) {
+      if (off >= Np) continue;
+      const double pv = shfl_d(bv, (int)lane + off);
+      const int pi = __shfl(bi, (int)lane + off, 64);
+      if (k + off < Np && (pv > bv || (pv == bv && pi < bi))) {
+        bv = pv;
+        bi = pi;
       }
     }
+    const int best = __shfl(bi, base, 64);
     if (in_slot && k == 0) pivs[pslot * Np + s] = (unsigned char)best;
-    const bool am = (k == best);
-    if (am) {
-      const cpx<double> inv = cinv(as);
+    const int src = base + best;
+    const bool am = in_slot && (k == best);
+    cpx<double> ps;
+    ps.re = shfl_d(as.re, src);
+    ps.im = shfl_d(as.im, src);
+    const double dd = 1.0 / (ps.re * ps.re + ps.im * ps.im);
+    const cpx<double> inv = cmk(ps.re * dd, -ps.im * dd);
+    const cpx<double> c = am ? inv : cmk(0.0, 0.0) - as * inv;
+    const double keep = am ? 0.0 : 1.0;
 #pragma unroll
-      for (int m = 0; m < Np; ++m) a[m] = ((m == s) ? cmk(1.0, 0.0) : a[m]) * inv;
+    for (int m = 0; m + 1 < Np; ++m) {
+      cpx<double> p;
+      p.re = shfl_d(a[m + 1].re, src);
+      p.im = shfl_d(a[m + 1].im, src);
+      cpx<double> t;
+      t.re = fma(keep, a[m + 1].re, fma(c.re, p.re, -c.im * p.im));
+      t.im = fma(keep, a[m + 1].im, fma(c.re, p.im, c.im * p.re));
+      a[m] = t;
+    }
+    a[Np - 1] = c;
+    if (am) {
       used = true;
       mystep = s;
-    }
-    const cpx<double> f = as;
-    const int src = base + best;
-#pragma unroll
-    for (int m = 0; m < Np; ++m) {
-      cpx<double> p;
-      p.re = shfl_d(a[m].re, src);
-      p.im = shfl_d(a[m].im, src);
-      if (!am) {
-        const cpx<double> cur = (m == s) ? cmk(0.0, 0.0) : a[m];
-        a[m] = cur - f * p;
-      }
     }
   }
   __syncthreads();
@@ -672,6 +694,25 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
 // Assembled form of the same operator: B[d][i] = sum over (a, m) with
 // off_m - off_a = d of G[(a*Np+m)][i]  (d in the 5^DIM box, FULL patch), summed
 // in FP64.  u += B r is then a 5^DIM-point stencil sweep.
+// member index of the offset (mx, my, mz) from the anchor, or -1, in closed form
+// (same order as patch_member: 3^DIM-box order for Full, Plus and RB, 2^DIM-box order
+// for Element)
+template <int DIM, int PATCH>
+__device__ __forceinline__ int member_of(int mx, int my, int mz) {
+  if (PATCH == PATCH_ELEMENT) {
+    if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > (DIM == 3 ? 1 : 0)) return -1;
+    return mx + 2 * my + 4 * mz;
+  }
+  if (mx < -1 || mx > 1 || my < -1 || my > 1 || mz < (DIM == 3 ? -1 : 0) || mz > (DIM == 3 ? 1 : 0))
+    return -1;
+  const int t = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+  if (PATCH == PATCH_FULL) return t;
+  if (!box_member<DIM, PATCH>(t)) return -1;
+  int k = 0;  // members of the box before t
+  for (int q = 0; q < t; ++q) k += box_member<DIM, PATCH>(q) ? 1 : 0;
+  return k;
+}
+
 template <int DIM, int PATCH, class T>
 __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __restrict__ G,
                                                         Slab sl, cpx<T>* __restrict__ B) {
@@ -684,16 +725,18 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
   decode((unsigned)i, g, cx, cy, cz);
   const long long ip = linp(g, cx, cy, cz);
   const size_t ig = (size_t)(ip - sl.gbase);
+  // entry e of the box collects every (a, m) with off_m - off_a = off_e; both loops are
+  // unrolled, so the member lookups fold to constants and only existing pairs are loaded
+#pragma unroll
   for (int e = 0; e < K5; ++e) {
     const int dx = shape_off<DIM, BOX2>(e, 0), dy = shape_off<DIM, BOX2>(e, 1),
               dz = shape_off<DIM, BOX2>(e, 2);
     cpx<double> acc = cmk(0.0, 0.0);
 #pragma unroll
     for (int a = 0; a < Np; ++a) {
-      const int mx = dx + patch_off<DIM, PATCH>(a, 0),
-                my = dy + patch_off<DIM, PATCH>(a, 1),
-                mz = dz + patch_off<DIM, PATCH>(a, 2);
-      const int m = patch_member<DIM, PATCH>(mx, my, mz);
+      const int m = member_of<DIM, PATCH>(dx + patch_off<DIM, PATCH>(a, 0),
+                                          dy + patch_off<DIM, PATCH>(a, 1),
+                                          dz + patch_off<DIM, PATCH>(a, 2));
       if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
     }
     B[(size_t)e * N + ip] = ccast<T>(acc);

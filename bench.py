@@ -411,6 +411,8 @@ def main():
         kname = "k_vanka_sweep"
     elif contraction != B.VH_CONTRACT_VALU and width >= 16:
         kname = "kb_sweep_mfma"
+    elif dim == 2 and width == 64 and E[0] == 25:
+        kname = "kb_sweep2d_s64"
     elif dim == 2:
         kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
     else:

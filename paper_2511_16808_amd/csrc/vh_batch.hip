@@ -1026,6 +1026,282 @@ __global__ __launch_bounds__(256) void kb_scale(const BatchKrylovDev* __restrict
   v[t] = K->inv_nrm[t & ((1 << ls) - 1)] * w[t];
 }
 
+// ------------------------------------------------------------------ delayed CGS2
+// Delayed classical Gram-Schmidt with one reorthogonalisation (the reorthogonalisation
+// of each basis vector is merged into the next step's projection).  At step j the
+// basis holds final columns v_0..v_{j-1}, the lagged vector u = V_j (projected once,
+// scaled to about unit norm) and w = A z_j, z_j = M^{-1} u.  Pass A (one read of the
+// basis) gives b = V^H u, d = V^H w, u^H w, u^H u, w^H w; then
+//   v_j = (u - V b) / beta,  beta^2 = u^H u - |b|^2,
+//   A z_{j-1} = V (c' + nu' b) + nu' beta v_j     (Hessenberg column j-1 completed),
+//   c = [d; (u^H w - b^H d) / beta] = the first projection of w on v_0..v_j,
+//   u' = (w - V d' - gam u) / nu, d' = d - b c_j / beta, gam = c_j / beta,
+//   nu^2 = w^H w - |c|^2,
+// and pass B (a second read) writes v_j and u'.  FGMRES accepts z_j = M^{-1} u in place
+// of M^{-1} v_j because it keeps Z: A Z = V H holds column by column.
+
+// pass A over the columns [c0, c0 + nc) of one group; the first group also sums the
+// three products of u and w.  Output rows: b (nc), d (nc), then u^H w, u^H u, w^H w.
+template <int NJ>
+__global__ __launch_bounds__(256) void kb_dcgs_a(const cpx<double>* __restrict__ V, size_t ldv,
+                                                 int c0, int nc, int j, int wcol, int first,
+                                                 long long N, int ls,
+                                                 cpx<double>* __restrict__ part) {
+  __shared__ cpx<double> red[4][64];
+  const int S = 1 << ls;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = lane & (S - 1);
+  const int nodes_per_block = 256 >> ls;
+  const int sub = threadIdx.x >> ls;
+  const long long stride = (long long)gridDim.x * nodes_per_block;
+  const cpx<double>* u = V + (size_t)j * ldv;
+  const cpx<double>* w = V + (size_t)wcol * ldv;
+  cpx<double> ab[NJ], ad[NJ], e = cmk(0.0, 0.0), f = cmk(0.0, 0.0), gw = cmk(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < NJ; ++q) ab[q] = ad[q] = cmk(0.0, 0.0);
+  for (long long i = (long long)blockIdx.x * nodes_per_block + sub; i < N; i += stride) {
+    const size_t o = (size_t)i * S + s;
+    const cpx<double> ui = u[o], wi = w[o];
+    if (nc > 0) {
+#pragma unroll
+      for (int q = 0; q < NJ; ++q) {
+        const cpx<double> v = V[(size_t)(c0 + (q < nc ? q : nc - 1)) * ldv + o];
+        ab[q] = cfma_conj(v, ui, ab[q]);
+        ad[q] = cfma_conj(v, wi, ad[q]);
+      }
+    }
+    if (first) {
+      e = cfma_conj(ui, wi, e);
+      f.re += ui.re * ui.re + ui.im * ui.im;
+      gw.re += wi.re * wi.re + wi.im * wi.im;
+    }
+  }
+  // rows in the layout of K->pa: b at [0, DG), d at [DG, 2 DG), then u^H w, u^H u, w^H w
+  // (rows past nc hold sums that are never read)
+#pragma unroll
+  for (int q = 0; q < 2 * DG + 3; ++q) {
+    cpx<double> v = cmk(0.0, 0.0);
+    if (q < DG) {
+      if (q < NJ) v = ab[q < NJ ? q : 0];
+    } else if (q < 2 * DG) {
+      if (q - DG < NJ) v = ad[q - DG < NJ ? q - DG : 0];
+    } else {
+      v = q == 2 * DG ? e : (q == 2 * DG + 1 ? f : gw);
+    }
+    for (int k = 32; k >= S; k >>= 1) {
+      v.re += __shfl_down(v.re, k, 64);
+      v.im += __shfl_down(v.im, k, 64);
+    }
+    __syncthreads();
+    if (lane < S) red[wv][lane] = v;
+    __syncthreads();
+    if (threadIdx.x < S) {
+      cpx<double> t = red[0][threadIdx.x];
+      for (int k = 1; k < 4; ++k) t = t + red[k][threadIdx.x];
+      part[((size_t)blockIdx.x * BKMAX + q) * 64 + threadIdx.x] = t;
+    }
+  }
+}
+
+template <int NJ>
+static int dcgs_a_launch(const cpx<double>* V, size_t ldv, int c0, int nc, int j, int wcol,
+                         int first, long long N, int ls, cpx<double>* part, int nb,
+                         hipStream_t st) {
+  static const int res = resident_blocks(kb_dcgs_a<NJ>);
+  const int g = nb < res ? nb : res;
+  kb_dcgs_a<NJ><<<g, 256, 0, st>>>(V, ldv, c0, nc, j, wcol, first, N, ls, part);
+  return g;
+}
+
+hipError_t batch_dcgs_a(const cpx<double>* V, size_t ldv, int j, int wcol, long long N, int ls,
+                        cpx<double>* part, int nb, BatchKrylovDev* K, hipStream_t st) {
+  if (j < 0 || j > MMAX || wcol < j || wcol > MMAX) return hipErrorInvalidValue;
+  const int ng = j > 0 ? (j + DG - 1) / DG : 1;
+  cpx<double>* part2 = part + (size_t)nb * BKMAX * 64;
+  for (int q = 0; q < ng; ++q) {
+    const int c0 = q * DG, nc = j - c0 < DG ? j - c0 : DG;
+    const int first = q == 0;
+    int rows;
+    if (nc <= 4)
+      rows = dcgs_a_launch<4>(V, ldv, c0, nc, j, wcol, first, N, ls, part, nb, st);
+    else if (nc <= 8)
+      rows = dcgs_a_launch<8>(V, ldv, c0, nc, j, wcol, first, N, ls, part, nb, st);
+    else
+      rows = dcgs_a_launch<DG>(V, ldv, c0, nc, j, wcol, first, N, ls, part, nb, st);
+    VHB_CHECK();
+    kb_reduce<<<dim3(2 * DG + 3, RSL), 256, 0, st>>>(part, rows, ls, part2);
+    VHB_CHECK();
+    kb_reduce_fin<<<2 * DG + 3, 64, 0, st>>>(part2, 1 << ls, K->pa + (size_t)q * 27 * 64);
+    VHB_CHECK();
+  }
+  return hipSuccess;
+}
+
+// one thread per source: complete Hessenberg column j-1 (j >= 1) with its Givens
+// rotation and residual estimate; unless closing, prepare pass B of step j
+__global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int closing) {
+  const int s = threadIdx.x;
+  if (s >= S) return;
+  const int ldh = MMAX + 1;
+  auto H = [&](int col, int row) -> cpx<double>& {
+    return K->H[((size_t)col * ldh + row) * 64 + s];
+  };
+  auto bv = [&](int i) {
+    const int q = i / DG, li = i % DG;
+    return K->pa[((size_t)q * 27 + li) * 64 + s];
+  };
+  auto dv = [&](int i) {
+    const int q = i / DG, li = i % DG;
+    return K->pa[((size_t)q * 27 + DG + li) * 64 + s];
+  };
+  const cpx<double> e = K->pa[(size_t)(2 * DG) * 64 + s];
+  const double f = K->pa[(size_t)(2 * DG + 1) * 64 + s].re;
+  const double gw = K->pa[(size_t)(2 * DG + 2) * 64 + s].re;
+  double beta = 1.0;
+  bool bad = false;
+  if (j >= 1) {
+    double bb = 0.0;
+    for (int i = 0; i < j; ++i) {
+      const cpx<double> b = bv(i);
+      bb += b.re * b.re + b.im * b.im;
+    }
+    const double b2 = f - bb;
+    beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    const double nu = K->nuprev[s];
+    const int jj = j - 1;  // the column completed now
+    for (int i = 0; i < j; ++i) H(jj, i) = K->cprev[i * 64 + s] + nu * bv(i);
+    const double nrm = nu * beta;
+    for (int i = 0; i < jj; ++i) {
+      const cpx<double> a = H(jj, i), b = H(jj, i + 1);
+      const double c = K->cs[i * 64 + s];
+      const cpx<double> sn = K->sn[i * 64 + s];
+      H(jj, i) = c * a + sn * b;
+      H(jj, i + 1) = c * b - cmk(sn.re, -sn.im) * a;
+    }
+    const cpx<double> a = H(jj, jj);
+    double c;
+    cpx<double> sn;
+    const double aa = sqrt(a.re * a.re + a.im * a.im);
+    if (aa == 0.0) {
+      c = 0.0;
+      sn = cmk(1.0, 0.0);
+    } else {
+      const double r = sqrt(aa * aa + nrm * nrm);
+      c = aa / r;
+      sn = cmk(a.re / aa * nrm / r, a.im / aa * nrm / r);
+    }
+    K->cs[jj * 64 + s] = c;
+    K->sn[jj * 64 + s] = sn;
+    H(jj, jj) = c * a + sn * cmk(nrm, 0.0);
+    H(jj, jj + 1) = cmk(0.0, 0.0);
+    const cpx<double> gj = K->g[jj * 64 + s];
+    K->g[(jj + 1) * 64 + s] = cmk(0.0, 0.0) - cmk(sn.re, -sn.im) * gj;
+    K->g[jj * 64 + s] = c * gj;
+    const cpx<double> gn = K->g[(jj + 1) * 64 + s];
+    const double est = sqrt(gn.re * gn.re + gn.im * gn.im);
+    K->status[s * 4 + 0] = est;
+    K->status[s * 4 + 1] = nrm;
+    bad = !(nrm == nrm) || !(est == est) || isinf(nrm);
+  }
+  if (!closing) {
+    const double ibeta = beta > 0.0 ? 1.0 / beta : 0.0;
+    cpx<double> bd = cmk(0.0, 0.0);
+    for (int i = 0; i < j; ++i) {
+      const cpx<double> b = bv(i);
+      bd = cfma_conj(b, dv(i), bd);
+    }
+    const cpx<double> cj = ibeta * (e - bd);
+    const cpx<double> gam = ibeta * cj;
+    double cc = cj.re * cj.re + cj.im * cj.im;
+    for (int i = 0; i < j; ++i) {
+      const cpx<double> d = dv(i), b = bv(i);
+      cc += d.re * d.re + d.im * d.im;
+      K->cprev[i * 64 + s] = d;
+      K->xb[i * 64 + s] = b;
+      K->yd[i * 64 + s] = d - b * gam;
+    }
+    K->cprev[j * 64 + s] = cj;
+    const double n2 = gw - cc;
+    const double nu = n2 > 1e-28 * gw ? sqrt(n2) : sqrt(1e-28 * gw);
+    K->nuprev[s] = nu;
+    K->gam[s] = gam;
+    K->ib[s] = ibeta;
+    K->inu[s] = nu > 0.0 ? 1.0 / nu : 0.0;
+    bad = bad || !(nu == nu) || isinf(nu) || !(cj.re == cj.re) || !(cj.im == cj.im);
+  }
+  K->status[s * 4 + 2] = bad ? 1.0 : 0.0;
+}
+
+// pass B over the column group [c0, c0 + nc): t0 = V_j - sum xb_i v_i,
+// t1 = V_{j+1} - sum yd_i v_i (minus gam u in the first group); the last group scales
+// by ib and inu.  Columns past nc re-read the last one with a zero coefficient.
+template <int NJ>
+__global__ __launch_bounds__(256) void kb_dcgs_b(cpx<double>* __restrict__ V, size_t ldv, int c0,
+                                                 int nc, int j, int first, int last, long long N,
+                                                 int ls, const BatchKrylovDev* __restrict__ K) {
+  __shared__ cpx<double> xs[NJ][64], ys[NJ][64];
+  const int S = 1 << ls;
+  for (int e = threadIdx.x; e < NJ * 64; e += 256) {
+    const int q = e >> 6;
+    xs[q][e & 63] = q < nc ? K->xb[(size_t)(c0 + q) * 64 + (e & 63)] : cmk(0.0, 0.0);
+    ys[q][e & 63] = q < nc ? K->yd[(size_t)(c0 + q) * 64 + (e & 63)] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int s = threadIdx.x & (S - 1);
+  const cpx<double> gam = K->gam[s];
+  const double ib = K->ib[s], inu = K->inu[s];
+  cpx<double>* u = V + (size_t)j * ldv;
+  cpx<double>* w = V + (size_t)(j + 1) * ldv;
+  const long long total = N << ls;
+  for (long long t = (long long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x; t < total;
+       t += (long long)gridDim.x * 256) {
+    const size_t o = (size_t)t;
+    cpx<double> t0 = u[o], t1 = w[o];
+    if (first) t1 = t1 - gam * t0;
+    if (nc > 0) {
+#pragma unroll
+      for (int q = 0; q < NJ; ++q) {
+        const cpx<double> v = V[(size_t)(c0 + (q < nc ? q : nc - 1)) * ldv + o];
+        t0 = t0 - xs[q][s] * v;
+        t1 = t1 - ys[q][s] * v;
+      }
+    }
+    if (last) {
+      t0 = ib * t0;
+      t1 = inu * t1;
+    }
+    u[o] = t0;
+    w[o] = t1;
+  }
+}
+
+hipError_t batch_dcgs_fin(BatchKrylovDev* K, int j, int S, int closing, hipStream_t st) {
+  if (j < 0 || j > MMAX) return hipErrorInvalidValue;
+  kb_dcgs_fin<<<1, 64, 0, st>>>(K, j, S, closing);
+  VHB_CHECK();
+  return hipSuccess;
+}
+
+hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
+                        const BatchKrylovDev* K, hipStream_t st) {
+  if (j < 0 || j >= MMAX) return hipErrorInvalidValue;
+  const int ng = j > 0 ? (j + DG - 1) / DG : 1;
+  const long long total = N << ls;
+  const unsigned nb = (unsigned)std::min<long long>((total + 255) / 256, 4096);
+  for (int q = 0; q < ng; ++q) {
+    const int c0 = q * DG, nc = j - c0 < DG ? j - c0 : DG;
+    const int first = q == 0, last = q == ng - 1;
+    if (nc <= 4)
+      kb_dcgs_b<4><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+    else if (nc <= 8)
+      kb_dcgs_b<8><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+    else
+      kb_dcgs_b<DG><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+    VHB_CHECK();
+  }
+  return hipSuccess;
+}
+
 hipError_t batch_finalize(BatchKrylovDev* K, int j, int S, hipStream_t st) {
   kb_finalize<<<1, 64, 0, st>>>(K, j, S);
   VHB_CHECK();

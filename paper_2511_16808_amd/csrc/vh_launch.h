@@ -41,7 +41,16 @@ struct BatchKrylovDev {
   double status[64 * 4];  // per source: |g_{j+1}|, ||w||, breakdown flag, beta
   double inv_nrm[64];
   int kcols[64];          // columns used by the next solution update (0 = frozen source)
+  // delayed reorthogonalisation (one reduction pass and one update pass per step)
+  cpx<double> pa[6 * 27 * 64];         // pass-A sums, column group q at rows q*27 ...
+  cpx<double> cprev[(MMAX + 1) * 64];  // first-pass coefficients of the last A z
+  double nuprev[64];                   // norm of its lagged residual
+  cpx<double> xb[MMAX * 64];           // pass B: v_j = (u - sum xb_i v_i) * ib
+  cpx<double> yd[MMAX * 64];           //   u' = (w - sum yd_i v_i - gam u) * inu
+  cpx<double> gam[64];
+  double ib[64], inu[64];
 };
+constexpr int DG = 12;  // basis columns per group of the delayed passes
 
 hipError_t fill(void* p, size_t n, int prec, double re, double im, hipStream_t s);
 hipError_t convert(const void* a, int pa, void* b, int pb, size_t n, hipStream_t s);
@@ -126,5 +135,15 @@ hipError_t batch_update_x(const BatchKrylovDev* K, int kmax, int pz, const void*
                           cpx<double>* x, long long N, int ls, hipStream_t st);
 hipError_t batch_scale(const BatchKrylovDev* K, const cpx<double>* w, cpx<double>* v, long long N,
                        int ls, hipStream_t st);
+// delayed classical Gram-Schmidt with reorthogonalisation, step j: pass A reduces the
+// dots of the final columns 0..j-1 with u = V_j (the lagged vector) and with
+// w = V_wcol, and u^H w, u^H u, w^H w, into K->pa; dcgs_fin completes Hessenberg column
+// j-1 (closing = 1: only that) and prepares pass B, which writes the final v_j into V_j
+// and the next lagged vector into V_{j+1}
+hipError_t batch_dcgs_a(const cpx<double>* V, size_t ldv, int j, int wcol, long long N, int ls,
+                        cpx<double>* part, int nb, BatchKrylovDev* K, hipStream_t st);
+hipError_t batch_dcgs_fin(BatchKrylovDev* K, int j, int S, int closing, hipStream_t st);
+hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
+                        const BatchKrylovDev* K, hipStream_t st);
 
 }  // namespace vh

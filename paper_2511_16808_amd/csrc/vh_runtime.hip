@@ -690,8 +690,26 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     if (!any) break;
     std::vector<int> stopped(S, 0);
     for (int k = 0; k < S; ++k) kcols[k] = 0;
-    int j = 0;
-    for (; j < m; ++j) {
+    // Arnoldi with delayed reorthogonalisation: step j applies the preconditioner to the
+    // lagged vector V_j and completes Hessenberg column j-1 (iteration j), so the
+    // residual estimate of an iteration is known one step later; a cycle that runs to m
+    // closes column m-1 with one more reduction pass.
+    auto account = [&](int done) -> vh_status {
+      VH_TRY(read_bstatus(hd, S));
+      bool all_stopped = true;
+      for (int k = 0; k < S; ++k) {
+        if (!active[k] || stopped[k]) continue;
+        if (hd->bstat[k * 4 + 2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
+        ++its[k];
+        kcols[k] = done;
+        est[k] = hd->bstat[k * 4 + 0] / bnorm[k];
+        if (est[k] <= tol || its[k] >= hd->opt.maxit || hd->bstat[k * 4 + 1] == 0.0) stopped[k] = 1;
+        all_stopped = all_stopped && stopped[k];
+      }
+      return all_stopped ? VH_ENOCONV : VH_OK;  // VH_ENOCONV here: every source stopped
+    };
+    bool finished = false;
+    for (int j = 0; j < m && !finished; ++j) {
       const void* qv = Vj(j);
       if (hd->prec != PREC_F64) {
         VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
@@ -702,26 +720,23 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       hd->tend(tk);
       VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                            PREC_F64, nullptr, Vj(j + 1), s));
-      VH_HIP(batch_cgs(0, hd->bV, ldv, j + 1, nullptr, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
-                       K->h1, s));
-      VH_HIP(batch_cgs(1, hd->bV, ldv, j + 1, K->h1, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
-                       K->h2, s));
-      VH_HIP(batch_cgs(2, hd->bV, ldv, j + 1, K->h2, Vj(j + 1), N, ls, hd->bpart, hd->bnred,
-                       K->nrm2, s));
-      VH_HIP(batch_finalize(K, j, S, s));
-      VH_HIP(batch_scale(K, Vj(j + 1), Vj(j + 1), N, ls, s));
-      VH_TRY(read_bstatus(hd, S));
-      bool all_stopped = true;
-      for (int k = 0; k < S; ++k) {
-        if (!active[k] || stopped[k]) continue;
-        if (hd->bstat[k * 4 + 2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
-        ++its[k];
-        kcols[k] = j + 1;
-        est[k] = hd->bstat[k * 4 + 0] / bnorm[k];
-        if (est[k] <= tol || its[k] >= hd->opt.maxit || hd->bstat[k * 4 + 1] == 0.0) stopped[k] = 1;
-        all_stopped = all_stopped && stopped[k];
+      VH_HIP(batch_dcgs_a(hd->bV, ldv, j, j + 1, N, ls, hd->bpart, hd->bnred, K, s));
+      VH_HIP(batch_dcgs_fin(K, j, S, 0, s));
+      if (j >= 1) {
+        const vh_status a = account(j);
+        if (a == VH_ENOCONV) {
+          finished = true;
+          break;
+        }
+        VH_TRY(a);
       }
-      if (all_stopped) break;
+      VH_HIP(batch_dcgs_b(hd->bV, ldv, j, N, ls, K, s));
+    }
+    if (!finished) {
+      VH_HIP(batch_dcgs_a(hd->bV, ldv, m, m, N, ls, hd->bpart, hd->bnred, K, s));
+      VH_HIP(batch_dcgs_fin(K, m, S, 1, s));
+      const vh_status a = account(m);
+      if (a != VH_ENOCONV) VH_TRY(a);
     }
     VH_HIP(hipMemcpyAsync(K->kcols, kcols, S * sizeof(int), hipMemcpyHostToDevice, s));
     int kmax = 0;

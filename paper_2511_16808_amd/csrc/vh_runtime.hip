@@ -91,6 +91,11 @@ struct vh_handle {
   int bnred = 512;  // same for the multi-source path
   KrylovDev* K = nullptr;
   double* hstat = nullptr;  // pinned host copy of K->status
+  // one-source FGMRES state for the delayed reorthogonalisation (source slot 0 of the
+  // multi-source state, with its own partial-sum rows)
+  BatchKrylovDev* dK = nullptr;
+  cpx<double>* dpart = nullptr;
+  int dnb = 512;
   std::vector<void*> allocs;
   size_t bytes = 0;
   // optional event timing (vh_options.timing): pairs of events with a kind tag
@@ -391,24 +396,40 @@ vh_status read_status(vh_handle* hd) {
 }
 
 // ---------------------------------------------------------------- FGMRES(m)
+// One source.  Arnoldi by classical Gram-Schmidt with one reorthogonalisation, delayed
+// into the next step (one reduction pass and one update pass over the basis per step,
+// the multi-source kernels on one source slot): step j applies the preconditioner to
+// the lagged vector V_j and completes Hessenberg column j-1, so the residual estimate
+// of an iteration is known one step later; a cycle that runs to m closes column m-1
+// with one more reduction pass.
+vh_status read_dstatus(vh_handle* hd) {
+  VH_HIP(hipMemcpyAsync(hd->hstat, hd->dK->status, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                        hd->s));
+  VH_HIP(hipStreamSynchronize(hd->s));
+  hd->tflush();
+  return VH_OK;
+}
+
 vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double tol,
                      vh_solve_stats* st) {
   const size_t N = (size_t)hd->L[0].g.N;
-  const int m = hd->m, ldh = MMAX + 1;
-  KrylovDev* K = hd->K;
+  const int m = hd->m;
+  BatchKrylovDev* K = hd->dK;
   cpx<double>* V = hd->V;
   auto Vj = [&](int j) { return V + (size_t)j * N; };
   auto Zj = [&](int j) { return (void*)((char*)hd->Z + (size_t)j * N * hd->esz); };
-  const int K0 = 2 * hd->dim + 1;
-  (void)K0;
+  const long long NL = (long long)N;
 
   VH_HIP(fill(x, N, PREC_F64, 0.0, 0.0, hd->s));
-  // r = q (x = 0); beta = ||q||
+  // r = q (x = 0); beta = ||q||; V_0 = r / beta
+  auto restart_vector = [&]() -> vh_status {
+    VH_HIP(batch_cgs(2, V, N, 0, K->h2, Vj(0), NL, 0, hd->dpart, hd->dnb, K->nrm2, hd->s));
+    VH_HIP(batch_cycle_init(K, m, 1, hd->s));
+    VH_HIP(batch_scale(K, Vj(0), Vj(0), NL, 0, hd->s));
+    return read_dstatus(hd);
+  };
   VH_HIP(hipMemcpyAsync(Vj(0), q, N * sizeof(cpx<double>), hipMemcpyDeviceToDevice, hd->s));
-  VH_HIP(cgs_pass(2, V, N, 0, K->h2, Vj(0), N, hd->part, hd->nred, K->nrm2, hd->s));
-  VH_HIP(cycle_init(K, m, hd->s));
-  VH_HIP(scale_vec(&K->inv_nrm, Vj(0), Vj(0), N, hd->s));
-  VH_TRY(read_status(hd));
+  VH_TRY(restart_vector());
   const double bnorm = hd->hstat[3];
   double beta = bnorm;
   int its = 0, restarts = 0;
@@ -429,31 +450,41 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
     }
     if (its >= hd->opt.maxit) break;
     int k = 0;
-    for (int j = 0; j < m; ++j) {
-      VH_TRY(precondition(hd, Vj(j), Zj(j)));
-      VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
-                     PREC_F64, nullptr, Vj(j + 1), hd->s));
-      VH_HIP(cgs_pass(0, V, N, j + 1, nullptr, Vj(j + 1), N, hd->part, hd->nred, K->h1, hd->s));
-      VH_HIP(cgs_pass(1, V, N, j + 1, K->h1, Vj(j + 1), N, hd->part, hd->nred, K->h2, hd->s));
-      VH_HIP(cgs_pass(2, V, N, j + 1, K->h2, Vj(j + 1), N, hd->part, hd->nred, K->nrm2, hd->s));
-      VH_HIP(arnoldi_finalize(K, j, ldh, hd->s));
-      VH_HIP(scale_vec(&K->inv_nrm, Vj(j + 1), Vj(j + 1), N, hd->s));
-      ++its;
-      k = j + 1;
-      VH_TRY(read_status(hd));
+    bool stop = false;
+    // iteration `done` completed: read its estimate; true when the cycle ends here
+    auto account = [&](int done) -> vh_status {
+      VH_TRY(read_dstatus(hd));
       if (hd->hstat[2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
+      ++its;
+      k = done;
       est = hd->hstat[0] / bnorm;
-      if (est <= tol || its >= hd->opt.maxit || hd->hstat[1] == 0.0) break;
+      stop = est <= tol || its >= hd->opt.maxit || hd->hstat[1] == 0.0;
+      return VH_OK;
+    };
+    for (int j = 0; j < m && !stop; ++j) {
+      VH_TRY(precondition(hd, Vj(j), Zj(j)));
+      VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec,
+                     Zj(j), PREC_F64, nullptr, Vj(j + 1), hd->s));
+      VH_HIP(batch_dcgs_a(V, N, j, j + 1, NL, 0, hd->dpart, hd->dnb, K, hd->s));
+      VH_HIP(batch_dcgs_fin(K, j, 1, 0, hd->s));
+      if (j >= 1) {
+        VH_TRY(account(j));
+        if (stop) break;
+      }
+      VH_HIP(batch_dcgs_b(V, N, j, NL, 0, K, hd->s));
     }
-    VH_HIP(backsolve(K, k, ldh, hd->s));
-    VH_HIP(update_x(K, k, hd->prec, hd->Z, N, x, N, hd->s));
+    if (!stop) {
+      VH_HIP(batch_dcgs_a(V, N, m, m, NL, 0, hd->dpart, hd->dnb, K, hd->s));
+      VH_HIP(batch_dcgs_fin(K, m, 1, 1, hd->s));
+      VH_TRY(account(m));
+    }
+    VH_HIP(hipMemcpyAsync(K->kcols, &k, sizeof(int), hipMemcpyHostToDevice, hd->s));
+    VH_HIP(batch_backsolve(K, 1, hd->s));
+    VH_HIP(batch_update_x(K, k, hd->prec, hd->Z, N, x, NL, 0, hd->s));
     // true residual r = q - H x (FP64), V_0 = r / ||r||
     VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, x,
                    PREC_F64, q, Vj(0), hd->s));
-    VH_HIP(cgs_pass(2, V, N, 0, K->h2, Vj(0), N, hd->part, hd->nred, K->nrm2, hd->s));
-    VH_HIP(cycle_init(K, m, hd->s));
-    VH_HIP(scale_vec(&K->inv_nrm, Vj(0), Vj(0), N, hd->s));
-    VH_TRY(read_status(hd));
+    VH_TRY(restart_vector());
     beta = hd->hstat[3];
     ++restarts;
     if (!(beta == beta) || std::isinf(beta)) return fail(VH_EBREAKDOWN, "non-finite residual");
@@ -962,6 +993,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   VH_TRY(hd->alloc((void**)&hd->part, (size_t)hd->nred * 65 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->K, sizeof(KrylovDev)));
   VH_HIP(hipMemsetAsync(hd->K, 0, sizeof(KrylovDev), s));
+  hd->dnb = hd->nred < 1024 ? hd->nred : 1024;
+  VH_TRY(hd->alloc((void**)&hd->dpart, ((size_t)hd->dnb + 16) * 65 * 64 * sizeof(cpx<double>)));
+  VH_TRY(hd->alloc((void**)&hd->dK, sizeof(BatchKrylovDev)));
+  VH_HIP(hipMemsetAsync(hd->dK, 0, sizeof(BatchKrylovDev), s));
   VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
   if (o.timing) {
     hd->ev.assign(128, nullptr);
@@ -1585,6 +1620,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   }
   total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz + slab_tmp;
   total += (size_t)2048 * 65 * 16 + sizeof(KrylovDev);
+  total += (size_t)(1024 + 16) * 65 * 64 * 16 + sizeof(BatchKrylovDev);  // delayed CGS2 state
   if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
     size_t S = 1;
     while (S < (size_t)(nsrc < 64 ? nsrc : 64)) S *= 2;

@@ -401,9 +401,33 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   u[i] = ZERO ? acc : (u[i] + acc);
 }
 
+// The 1x1 patch (damped point Jacobi) needs no neighbour: u_i (+)= G_i r_i, streamed
+// without a residual tile.
+template <bool ZERO, class T>
+__global__ __launch_bounds__(256) void k_point_sweep(Grid g, const cpx<T>* __restrict__ G,
+                                                     const cpx<T>* __restrict__ r,
+                                                     cpx<T>* __restrict__ u) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int x, y, z;
+  decode(i, g, x, y, z);
+  const cpx<T> d = ld_stream(G + linp(g, x, y, z));
+  const cpx<T> acc = cfma(d, r[i], cmk<T>(0, 0));
+  u[i] = ZERO ? acc : (u[i] + acc);
+}
+
 template <int DIM, int FORM, class T>
 static hipError_t vanka_sweep_t(Grid g, const void* G, const void* r, void* u, bool zero,
                                 hipStream_t s) {
+  if constexpr (FORM == SM_POINT) {
+    const unsigned nb = nblocks((size_t)g.N, 256);
+    if (zero)
+      k_point_sweep<true, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r, (cpx<T>*)u);
+    else
+      k_point_sweep<false, T><<<nb, 256, 0, s>>>(g, (const cpx<T>*)G, (const cpx<T>*)r, (cpx<T>*)u);
+    VH_LAUNCH_CHECK();
+    return hipSuccess;
+  }
   const unsigned nb = (unsigned)(((g.nx + VT_X - 1) / VT_X) * ((g.ny + VT_Y - 1) / VT_Y) * g.nz);
   if (zero)
     k_vanka_sweep<DIM, FORM, true, T><<<nb, VT_X * VT_Y, 0, s>>>(g, (const cpx<T>*)G,

@@ -117,9 +117,160 @@ __global__ __launch_bounds__(256) void kb_stencil(Grid g, int ls, const cpx<TC>*
     y[o] = ccast<TY>(ccast<TC>(y[o]) + acc);
 }
 
+// 2D, 64 sources, radius-R stencils (CROSS, BOX1: R = 1; BOX2: R = 2): the walk of
+// kb_sweep2d_s64 (defined below) applied to the operator: one wavefront = one node x 64
+// sources, a block of 4 wavefronts covers 4 rows and walks along x; the (2R+1)^2 window of
+// x lives in registers (TC precision), the next column of the block's 4 + 2R rows comes
+// through a (2R+1)-slot LDS ring, the K coefficients of the block's nodes are staged in LDS
+// 2R+1 columns at a time, and every global load is issued 2R+1 steps before its use.
+constexpr int S64_ROWS = 4, S64_TX = 16;
+
+__device__ __forceinline__ void lds_barrier_s() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int SHAPE, int MODE, class TC, class TX, class TY>
+__global__ __launch_bounds__(256) void kb_stencil2d_s64(Grid g, int tx,
+                                                        const cpx<TC>* __restrict__ A,
+                                                        const cpx<TX>* __restrict__ x,
+                                                        const cpx<TY>* __restrict__ b,
+                                                        cpx<TY>* __restrict__ y) {
+  constexpr int R = shape_radius<2, SHAPE>(), CH = 2 * R + 1, CR = S64_ROWS + 2 * R;
+  constexpr int K = shape_K<2, SHAPE>();
+  constexpr int CL = (CR * 64 + 255) / 256;  // column values per thread
+  constexpr int GN = S64_ROWS * K * CH, GPT = (GN + 255) / 256;
+  __shared__ cpx<TX> col[CH][CR][64];
+  __shared__ cpx<TC> gch[2][S64_ROWS][K][CH];
+  const int nsx = (g.nx + tx - 1) / tx;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int xs = (int)(blk % (unsigned)nsx) * tx, y0 = (int)(blk / (unsigned)nsx) * S64_ROWS;
+  const int xe = min(xs + tx, g.nx);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int yy = y0 + wv;
+  const bool row_ok = yy < g.ny;
+  const size_t N = (size_t)g.N;
+  const size_t orow = (size_t)lin_b(g, 0, row_ok ? yy : 0, 0) * 64 + lane;
+  const int nstep = xe - xs + 2 * R;  // step k reads column xs - R + k, outputs xs + k - 2R
+  cpx<TC> w[CH][CH];                  // [dy][column ring slot]
+  cpx<TX> pc[CH][CL];                 // columns in flight, by ring slot
+  cpx<TY> bf[CH];                     // b (RESID) or y (ADD) of the outputs in flight
+  cpx<TC> gp[GPT];
+  auto fetch_col = [&](int cx, cpx<TX>* dst) {
+    const bool xok = (unsigned)cx < (unsigned)g.nx;
+#pragma unroll
+    for (int c = 0; c < CL; ++c) {
+      const int v = (int)threadIdx.x + 256 * c, row = v >> 6;
+      const int ry = y0 - R + row;
+      dst[c] = (row < CR && xok && (unsigned)ry < (unsigned)g.ny)
+                   ? x[(size_t)lin_b(g, cx, ry, 0) * 64 + lane]
+                   : cmk<TX>(0, 0);
+    }
+  };
+  auto fetch_out = [&](int xo) -> cpx<TY> {
+    if (MODE == OP_APPLY || xo < xs || xo >= xe || !row_ok) return cmk<TY>(0, 0);
+    return MODE == OP_RESID ? b[orow + (size_t)xo * 64] : y[orow + (size_t)xo * 64];
+  };
+  // chunk q: output nodes xs + CH q - 2R + j (j < CH), rows y0 .. y0 + 3, entries [e]
+  auto fetch_g = [&](int q) {
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      const int j = idx % CH, e = (idx / CH) % K, row = idx / (CH * K);
+      const int xo = xs + CH * q - 2 * R + j, ry = y0 + row;
+      gp[i] = (idx < GN && xo >= xs && xo < xe && ry < g.ny)
+                  ? A[(size_t)e * N + (size_t)lin_b(g, xo, ry, 0)]
+                  : cmk<TC>(0, 0);
+    }
+  };
+  auto store_g = [&](int q) {
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      if (idx < GN) (&gch[q & 1][0][0][0])[idx] = gp[i];
+    }
+  };
+  auto step = [&](int k, auto ph) {
+    constexpr int PH = decltype(ph)::value;  // k % CH
+#pragma unroll
+    for (int c = 0; c < CL; ++c) {
+      const int v = (int)threadIdx.x + 256 * c, row = v >> 6;
+      if (row < CR) col[PH][row][lane] = pc[PH][c];
+    }
+    if (k + CH < nstep) fetch_col(xs - R + k + CH, pc[PH]);
+    lds_barrier_s();
+    if (PH == 0) {
+      const int q = k / CH;
+      if (CH * (q + 1) < nstep) store_g(q + 1);
+      if (CH * (q + 2) < nstep) fetch_g(q + 2);
+    }
+#pragma unroll
+    for (int dy = 0; dy < CH; ++dy) w[dy][PH] = ccast<TC>(col[PH][wv + dy][lane]);
+    const cpx<TY> bo = bf[PH];
+    if (MODE != OP_APPLY) bf[PH] = fetch_out(xs + k + CH - 2 * R);  // the output of step k + CH
+    if (k >= 2 * R && row_ok) {
+      const cpx<TC>* gq = &gch[(k / CH) & 1][wv][0][PH];
+      cpx<TC> acc = cmk<TC>(0, 0);
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        const int dx = shape_off<2, SHAPE>(e, 0), dy = shape_off<2, SHAPE>(e, 1);
+        acc = cfma(gq[e * CH], w[dy + R][(PH + dx - R + 2 * CH) % CH], acc);
+      }
+      const size_t o = orow + (size_t)(xs + k - 2 * R) * 64;
+      if (MODE == OP_APPLY)
+        y[o] = ccast<TY>(acc);
+      else if (MODE == OP_RESID)
+        y[o] = ccast<TY>(ccast<TC>(bo) - acc);
+      else
+        y[o] = ccast<TY>(ccast<TC>(bo) + acc);
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < CH; ++p) {
+    fetch_col(xs - R + p, pc[p]);
+    bf[p] = fetch_out(xs + p - 2 * R);
+  }
+  fetch_g(0);
+  store_g(0);
+  fetch_g(1);
+#pragma unroll 1
+  for (int k0 = 0; k0 < nstep; k0 += CH) {
+    step(k0, std::integral_constant<int, 0>{});
+    if constexpr (CH > 1) if (k0 + 1 < nstep) step(k0 + 1, std::integral_constant<int, 1 % CH>{});
+    if constexpr (CH > 2) if (k0 + 2 < nstep) step(k0 + 2, std::integral_constant<int, 2 % CH>{});
+    if constexpr (CH > 3) if (k0 + 3 < nstep) step(k0 + 3, std::integral_constant<int, 3 % CH>{});
+    if constexpr (CH > 4) if (k0 + 4 < nstep) step(k0 + 4, std::integral_constant<int, 4 % CH>{});
+  }
+}
+
+template <int SHAPE, int MODE, class TC, class TX, class TY>
+static void launch_stencil_s64(Grid g, const void* A, const void* x, const void* b, void* y,
+                               hipStream_t st) {
+  const int nsx = (g.nx + S64_TX - 1) / S64_TX;
+  const int tx = (g.nx + nsx - 1) / nsx;
+  const int nsx2 = (g.nx + tx - 1) / tx;
+  const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + S64_ROWS - 1) / S64_ROWS);
+  kb_stencil2d_s64<SHAPE, MODE, TC, TX, TY><<<nb, 256, 0, st>>>(
+      g, tx, (const cpx<TC>*)A, (const cpx<TX>*)x, (const cpx<TY>*)b, (cpx<TY>*)y);
+}
+
 template <int DIM, int SHAPE, class TC, class TX, class TY>
 static hipError_t bstencil_t(Grid g, int ls, int mode, const void* A, const void* x, const void* b,
                              void* y, hipStream_t st) {
+  if constexpr (DIM == 2 && SHAPE != BOX3) {
+    if (ls == 6) {
+      if (mode == OP_APPLY)
+        launch_stencil_s64<SHAPE, OP_APPLY, TC, TX, TY>(g, A, x, b, y, st);
+      else if (mode == OP_RESID)
+        launch_stencil_s64<SHAPE, OP_RESID, TC, TX, TY>(g, A, x, b, y, st);
+      else
+        launch_stencil_s64<SHAPE, OP_ADD, TC, TX, TY>(g, A, x, b, y, st);
+      VHB_CHECK();
+      return hipSuccess;
+    }
+  }
   const unsigned nb = nblk(g.N << ls, 256);
   auto Ap = (const cpx<TC>*)A;
   auto xp = (const cpx<TX>*)x;

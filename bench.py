@@ -239,6 +239,8 @@ def vcycle_bytes(levels_info, dim, esz, smoother_entries, S=1):
         for k in levels_info[l + 1]["n"][:dim]:
             Nc *= k
         K, E = info["stencil_points"], smoother_entries[l]
+        if l == 0 and K == 2 * dim + 1:
+            K = 1  # 5/7-point operator: only the centre entries are read (fixed off-diagonals)
         total += N * esz * (2 * E + 2 * K) + N * S * esz * 15 + Nc * S * esz * 2
     return total
 

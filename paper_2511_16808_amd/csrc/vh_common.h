@@ -77,6 +77,11 @@ struct Grid {
   long long N;    // nx*ny*nz
   int nxp;        // x extent of the padded layout used by the smoother arrays
   long long Np;   // nxp*ny*nz
+  // off-diagonals of a 5/7-point operator: 0 = read from the coefficient array;
+  // 1 (Dirichlet rows) / 2 (absorbing rows) = the fixed values -ih2, -2 ih2 times the
+  // boundary scaling, computed in the kernel (only the centre coefficient is read)
+  int offrule;
+  double ih2;
 };
 
 // Smoother arrays ([entry][node], one row per entry) use rows of nxp = nx rounded up
@@ -93,6 +98,8 @@ __host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int 
   g.N = (long long)g.nx * g.ny * g.nz;
   g.nxp = (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
   g.Np = (long long)g.nxp * g.ny * g.nz;
+  g.offrule = 0;
+  g.ih2 = 0.0;
   return g;
 }
 

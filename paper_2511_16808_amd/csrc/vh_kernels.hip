@@ -253,13 +253,40 @@ __global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restri
   constexpr int K = shape_K<DIM, SHAPE>();
   const size_t N = (size_t)g.N;
   cpx<TC> acc = cmk<TC>(0, 0);
+  if (SHAPE == CROSS && g.offrule != 0) {
+    // the 5/7-point operator with fixed off-diagonals (the values the fine operator
+    // stores, so the result is the same): only the centre coefficient is read
+    const int c[3] = {cx, cy, cz}, n[3] = {g.nx, g.ny, g.nz};
+    double scale = 1.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
-              dz = shape_off<DIM, SHAPE>(k, 2);
-    if (inside(g, cx + dx, cy + dy, cz + dz)) {
-      const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-      acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[j]), acc);
+    for (int d = 0; d < DIM; ++d)
+      if (g.offrule == 2 && (c[d] == 0 || c[d] == n[d] - 1)) scale *= 0.5;
+    acc = cfma(A[i], ccast<TC>(x[i]), acc);
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      const int d = (k - 1) / 2;
+      const bool up = ((k - 1) & 1) != 0;
+      const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+                dz = shape_off<DIM, SHAPE>(k, 2);
+      if (inside(g, cx + dx, cy + dy, cz + dz)) {
+        const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
+        const double wv = (g.offrule == 2 && ((up && lo) || (!up && hi))) ? -2.0 * g.ih2 : -g.ih2;
+        const TC ov = (TC)(scale * wv);
+        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+        const cpx<TC> xv = ccast<TC>(x[j]);
+        acc.re = fma(ov, xv.re, acc.re);
+        acc.im = fma(ov, xv.im, acc.im);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+                dz = shape_off<DIM, SHAPE>(k, 2);
+      if (inside(g, cx + dx, cy + dy, cz + dz)) {
+        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+        acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[j]), acc);
+      }
     }
   }
   if (MODE == OP_APPLY) {

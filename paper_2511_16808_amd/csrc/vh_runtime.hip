@@ -915,6 +915,11 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   else
     VH_HIP(fine_operator(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
                          o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
+  if (o.stencil != VH_STENCIL_COMPACT4) {
+    // every later application of the 5/7-point operator reads only its centre entries
+    hd->L[0].g.offrule = o.bc == VH_BC_ABC ? 2 : 1;
+    hd->L[0].g.ih2 = 1.0 / (hd->h * hd->h);
+  }
   // Galerkin hierarchy, FP64
   for (int l = 0; l + 1 < hd->levels; ++l) {
     Level &Lf = hd->L[l], &Lc = hd->L[l + 1];

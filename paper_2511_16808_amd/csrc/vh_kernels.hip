@@ -603,6 +603,7 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   // (no divergent branch).  After the last step a[s] = A^{-1}[step(L)][piv[s]].
   // The pivot sequence of each patch is kept in LDS.
   __shared__ unsigned char pivs[PB * Np];
+  __shared__ cpx<double> prow[WPB][PPW][Np];
   bool used = false;
   int mystep = k;
 #pragma unroll 1
@@ -622,20 +623,26 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     }
     const int best = __shfl(bi, base, 64);
     if (in_slot && k == 0) pivs[pslot * Np + s] = (unsigned char)best;
-    const int src = base + best;
     const bool am = in_slot && (k == best);
-    cpx<double> ps;
-    ps.re = shfl_d(as.re, src);
-    ps.im = shfl_d(as.im, src);
+    // the pivot row goes through LDS: its lane writes it, every lane of the patch reads
+    // it back as 16-byte broadcasts (one LDS instruction per entry instead of four
+    // 4-byte lane permutes); a wave's LDS operations complete in order
+    cpx<double>* pr = prow[wib][in_slot ? slot : 0];
+    if (am) {
+#pragma unroll
+      for (int m = 0; m < Np; ++m) pr[m] = a[m];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    const cpx<double> ps = pr[0];
     const double dd = 1.0 / (ps.re * ps.re + ps.im * ps.im);
     const cpx<double> inv = cmk(ps.re * dd, -ps.im * dd);
     const cpx<double> c = am ? inv : cmk(0.0, 0.0) - as * inv;
     const double keep = am ? 0.0 : 1.0;
 #pragma unroll
     for (int m = 0; m + 1 < Np; ++m) {
-      cpx<double> p;
-      p.re = shfl_d(a[m + 1].re, src);
-      p.im = shfl_d(a[m + 1].im, src);
+      const cpx<double> p = pr[m + 1];
       cpx<double> t;
       t.re = fma(keep, a[m + 1].re, fma(c.re, p.re, -c.im * p.im));
       t.im = fma(keep, a[m + 1].im, fma(c.re, p.im, c.im * p.re));
@@ -646,6 +653,10 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
       used = true;
       mystep = s;
     }
+    // every lane has read the row before the next step's pivot lane overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
   }
   __syncthreads();
 

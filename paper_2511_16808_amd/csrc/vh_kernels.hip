@@ -799,7 +799,11 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
       const int m = member_of<DIM, PATCH>(dx + patch_off<DIM, PATCH>(a, 0),
                                           dy + patch_off<DIM, PATCH>(a, 1),
                                           dz + patch_off<DIM, PATCH>(a, 2));
-      if (m >= 0) acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
+      // rows of patches that do not exist (anchor outside the grid) were never written
+      if (m >= 0 && anchor_ok<DIM, PATCH>(g, cx - patch_off<DIM, PATCH>(a, 0),
+                                          cy - patch_off<DIM, PATCH>(a, 1),
+                                          cz - patch_off<DIM, PATCH>(a, 2)))
+        acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
     }
     B[(size_t)e * N + ip] = ccast<T>(acc);
   }

@@ -847,12 +847,11 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
   const int K5 = dim == 2 ? 25 : 125;
   const size_t Npad = (size_t)g.Np;
   VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * Npad * hd->esz));
-  VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));
+  VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));  // row padding stays zero
   for (long long p0 = 0; p0 < p.n_out; p0 += p.SZ) {
     const long long p1 = p0 + p.SZ < p.n_out ? p0 + p.SZ : p.n_out;
     const long long b0 = p0 - 2 > 0 ? p0 - 2 : 0;
     const long long c0 = p0 - 1 > 0 ? p0 - 1 : 0, c1 = p1 + 1 < p.n_out ? p1 + 1 : p.n_out;
-    VH_HIP(fill(buf, (size_t)Np * Np * gstride, hd->prec, 0, 0, s));
     VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, g, A, Lv.w, hd->prec, buf,
                        Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
     VH_HIP(vanka_assemble(dim, Lv.patch, g, hd->prec, buf,

@@ -394,12 +394,25 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   const int bx = (int)(b % (unsigned)nbx), by = (int)((b / (unsigned)nbx) % (unsigned)nby);
   const int bz = (int)(b / (unsigned)(nbx * nby));
   const int x0 = bx * VT_X, y0 = by * VT_Y, z0 = bz;
-  for (int e = threadIdx.x; e < SX * SY * SZ; e += blockDim.x) {
+  // all loads of the residual tile are issued before the first LDS write; the barrier
+  // orders LDS only, so the smoother-entry loads below may start before it
+  constexpr int NTL = SX * SY * SZ, NPT = (NTL + VT_X * VT_Y - 1) / (VT_X * VT_Y);
+  cpx<T> tv[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int e = (int)threadIdx.x + VT_X * VT_Y * k;
     const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
     const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
-    tile[e] = inside(g, gx, gy, gz) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
+    tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int e = (int)threadIdx.x + VT_X * VT_Y * k;
+    if (e < NTL) tile[e] = tv[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   const int lx = threadIdx.x % VT_X, ly = threadIdx.x / VT_X;
   const int x = x0 + lx, y = y0 + ly, z = z0;
   if (x >= g.nx || y >= g.ny) return;

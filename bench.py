@@ -418,7 +418,7 @@ def main():
     elif dim == 2:
         kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
     else:
-        kname = "kb_sweep3d"
+        kname = "kb_sweep"
     tkey = f"{args.workload}_{'batch_' + args.contraction if batch else args.smoother}"
     traffic = measured_traffic(tkey, kname)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

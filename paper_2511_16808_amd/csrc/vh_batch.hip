@@ -396,50 +396,6 @@ __global__ __launch_bounds__(256) void kb_sweep2d(Grid g, int ls, const cpx<T>* 
   u[o] = ZERO ? acc : (u[o] + acc);
 }
 
-// 3D: one block = a row segment of NB nodes x S sources (NB*S <= 256 threads); the
-// residual of the segment with a halo of 2 in x, y and z (5 x 5 rows) is staged in LDS.
-template <int FORM, bool ZERO, class T>
-__global__ __launch_bounds__(256) void kb_sweep3d(Grid g, int ls, int NB,
-                                                  const cpx<T>* __restrict__ G,
-                                                  const cpx<T>* __restrict__ r,
-                                                  cpx<T>* __restrict__ u) {
-  extern __shared__ unsigned char smem[];
-  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);
-  const int S = 1 << ls, SX = NB + 4;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const int nbx = (g.nx + NB - 1) / NB;
-  const int x0 = (int)(b % (unsigned)nbx) * NB;
-  const int yz = (int)(b / (unsigned)nbx);
-  const int y0 = yz % g.ny, z0 = yz / g.ny;
-  const int nthreads = NB << ls;
-  for (int e = threadIdx.x; e < SX * 25 * S; e += nthreads) {
-    const int pos = e >> ls, s = e & (S - 1);
-    const int gx = x0 + pos % SX - 2, gy = y0 + (pos / SX) % 5 - 2, gz = z0 + pos / (SX * 5) - 2;
-    tile[e] = inside_b(g, gx, gy, gz) ? r[(size_t)lin_b(g, gx, gy, gz) * S + s] : cmk<T>(0, 0);
-  }
-  __syncthreads();
-  const int ns = threadIdx.x >> ls, s = threadIdx.x & (S - 1);
-  const int x = x0 + ns;
-  if (x >= g.nx) return;
-  const long long i = lin_b(g, x, y0, z0), ip = linp_b(g, x, y0, z0);
-  const size_t Np = (size_t)g.Np;
-  constexpr int E = bsm_entries<3, FORM>();
-  constexpr int UNR = FORM == 0 ? 81 : E;
-  const cpx<T>* t0 = tile + ((size_t)(ns + 2) + (size_t)SX * (2 + 5 * 2)) * S + s;
-  cpx<T> acc = cmk<T>(0, 0);
-#pragma unroll 1
-  for (int e0 = 0; e0 < E; e0 += UNR) {
-#pragma unroll
-    for (int q = 0; q < UNR; ++q) {
-      const int e = e0 + q;
-      const int dx = bsm_off<3, FORM>(e, 0), dy = bsm_off<3, FORM>(e, 1), dz = bsm_off<3, FORM>(e, 2);
-      acc = cfma(G[(size_t)e * Np + ip], t0[(dx + SX * (dy + 5 * dz)) * S], acc);
-    }
-  }
-  const size_t o = (size_t)i * S + s;
-  u[o] = ZERO ? acc : (u[o] + acc);
-}
-
 // 2D, 16 to 64 sources: a block covers a row segment of 16 nodes x S sources (each
 // thread 16*S/256 (node, source) pairs).  With many sources per node, per-lane loads of
 // the smoother entries would be 8-byte broadcasts; instead the block stages the
@@ -516,6 +472,7 @@ __global__ __launch_bounds__(256) void kb_sweep2d_wide(Grid g, const cpx<T>* __r
 // are written after the barrier of step 5q (chunk q - 1, the previous user of that
 // buffer, was read before it) and first read after the barrier of step 5q + 5.
 constexpr int B64_ROWS = 4, B64_TX = 16;
+
 
 __device__ __forceinline__ void lds_barrier_b() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -673,25 +630,6 @@ static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u
         launch_wide<FORM, T, 5>(g, G, r, u, zero, lds, st);
       else
         launch_wide<FORM, T, 6>(g, G, r, u, zero, lds, st);
-      VHB_CHECK();
-      return hipSuccess;
-    }
-  }
-  if (DIM == 3) {
-    // widest row segment whose tile fits in 64 KB of LDS and 256 threads
-    const size_t S = (size_t)1 << ls;
-    int NB = (int)(256 >> ls);
-    while (NB > 1 && (size_t)(NB + 4) * 25 * S * sizeof(cpx<T>) > 65536) NB >>= 1;
-    const size_t lds = (size_t)(NB + 4) * 25 * S * sizeof(cpx<T>);
-    if (lds <= 65536) {
-      const unsigned nb = (unsigned)(((g.nx + NB - 1) / NB) * (long long)g.ny * g.nz);
-      const unsigned nt = (unsigned)(NB << ls);
-      if (zero)
-        kb_sweep3d<FORM, true, T><<<nb, nt, lds, st>>>(g, ls, NB, (const cpx<T>*)G,
-                                                       (const cpx<T>*)r, (cpx<T>*)u);
-      else
-        kb_sweep3d<FORM, false, T><<<nb, nt, lds, st>>>(g, ls, NB, (const cpx<T>*)G,
-                                                        (const cpx<T>*)r, (cpx<T>*)u);
       VHB_CHECK();
       return hipSuccess;
     }

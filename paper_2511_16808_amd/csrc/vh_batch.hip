@@ -610,9 +610,126 @@ static void launch_wide(Grid g, const void* G, const void* r, void* u, bool zero
                                                               (const cpx<T>*)r, (cpx<T>*)u);
 }
 
+// 3D assembled smoother, 16 sources: a block of 256 threads covers an x-y tile of
+// 256/S nodes x S sources and walks along z.  The residual planes of the tile with a halo
+// of 2 pass through a 6-slot LDS ring (one new plane per step, its loads issued a step
+// ahead), so a residual value is loaded about (TX+4)(TY+4)/(TX TY) times per sweep instead
+// of once per neighbour; the 125 smoother entries of a node are read by its S lanes as
+// broadcast loads.  One barrier per step: plane k is written to slot k % 6 before the
+// barrier of step k and read by steps k .. k + 4; its next writer, step k + 6, runs after
+// the barrier of step k + 5, which every reader of step k + 4 has passed.
+template <int LS>
+struct Tile3 {
+  static constexpr int S = 1 << LS, NT = 256 >> LS;
+  static constexpr int TX = LS == 4 ? 4 : 8, TY = NT / TX;
+  static constexpr int PX = TX + 4, PY = TY + 4, PV = PX * PY * S, PPT = (PV + 255) / 256;
+};
+constexpr int Z3_STRIP = 32;
+
+template <bool ZERO, class T, int LS>
+__global__ __launch_bounds__(256) void kb_sweep3d_zw(Grid g, int zt, const cpx<T>* __restrict__ G,
+                                                     const cpx<T>* __restrict__ r,
+                                                     cpx<T>* __restrict__ u) {
+  using TL = Tile3<LS>;
+  constexpr int S = TL::S, TX = TL::TX, TY = TL::TY, PX = TL::PX, PY = TL::PY, PV = TL::PV,
+                PPT = TL::PPT;
+  constexpr int E = shape_K<3, BOX2>();
+  __shared__ cpx<T> ring[6][PV];
+  const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = (int)(b % (unsigned)nbx), by = (int)((b / (unsigned)nbx) % (unsigned)nby);
+  const int bz = (int)(b / (unsigned)(nbx * nby));
+  const int x0 = bx * TX, y0 = by * TY, zs = bz * zt;
+  const int ze = min(zs + zt, g.nz);
+  const int s = threadIdx.x & (S - 1), j = threadIdx.x >> LS;
+  const int jx = j % TX, jy = j / TX;
+  const int x = x0 + jx, y = y0 + jy;
+  const bool ok = x < g.nx && y < g.ny;
+  const size_t Np = (size_t)g.Np;
+  cpx<T> pv[PPT];
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+      const int v = (int)threadIdx.x + 256 * c;
+      const int n = v >> LS, sv = v & (S - 1);
+      const int gx = x0 + n % PX - 2, gy = y0 + n / PX - 2;
+      pv[c] = (v < PV && inside_b(g, gx, gy, z)) ? r[(size_t)lin_b(g, gx, gy, z) * S + sv]
+                                                 : cmk<T>(0, 0);
+    }
+  };
+  const int nstep = ze - zs + 4;  // step k loads plane zs - 2 + k, outputs plane zs + k - 4
+  auto step = [&](int k, auto ph) {
+    constexpr int PH = decltype(ph)::value;  // k % 6
+#pragma unroll
+    for (int c = 0; c < PPT; ++c) {
+      const int v = (int)threadIdx.x + 256 * c;
+      if (v < PV) ring[PH][v] = pv[c];
+    }
+    if (k + 1 < nstep) fetch(zs - 1 + k);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    const int z = zs + k - 4;
+    if (k >= 4 && ok) {
+      const long long ip = linp_b(g, x, y, z);
+      const size_t o = (size_t)lin_b(g, x, y, z) * S + s;
+      cpx<T> uo = cmk<T>(0, 0);
+      if (!ZERO) uo = u[o];
+      cpx<T> acc = cmk<T>(0, 0);
+      // one plane of 25 entries at a time keeps 25 loads in flight per thread (the
+      // register budget of several resident blocks) instead of all 125
+#pragma unroll 1
+      for (int dz = -2; dz <= 2; ++dz) {
+        const cpx<T>* rp = &ring[(PH + dz + 4) % 6][0];
+        const cpx<T>* gp = G + (size_t)(dz + 2) * 25 * Np + ip;
+#pragma unroll
+        for (int e = 0; e < 25; ++e) {
+          const int dx = e % 5 - 2, dy = e / 5 - 2;
+          acc = cfma(gp[(size_t)e * Np], rp[((jy + 2 + dy) * PX + (jx + 2 + dx)) * S + s], acc);
+        }
+      }
+      u[o] = ZERO ? acc : (uo + acc);
+    }
+  };
+  fetch(zs - 2);
+#pragma unroll 1
+  for (int k0 = 0; k0 < nstep; k0 += 6) {
+    step(k0, std::integral_constant<int, 0>{});
+    if (k0 + 1 < nstep) step(k0 + 1, std::integral_constant<int, 1>{});
+    if (k0 + 2 < nstep) step(k0 + 2, std::integral_constant<int, 2>{});
+    if (k0 + 3 < nstep) step(k0 + 3, std::integral_constant<int, 3>{});
+    if (k0 + 4 < nstep) step(k0 + 4, std::integral_constant<int, 4>{});
+    if (k0 + 5 < nstep) step(k0 + 5, std::integral_constant<int, 5>{});
+  }
+}
+
+template <class T, int LS>
+static void launch_zw(Grid g, const void* G, const void* r, void* u, bool zero, hipStream_t st) {
+  using TL = Tile3<LS>;
+  const int nsz = (g.nz + Z3_STRIP - 1) / Z3_STRIP;
+  const int zt = (g.nz + nsz - 1) / nsz;
+  const int nsz2 = (g.nz + zt - 1) / zt;
+  const unsigned nb = (unsigned)(((g.nx + TL::TX - 1) / TL::TX) * ((g.ny + TL::TY - 1) / TL::TY) * nsz2);
+  if (zero)
+    kb_sweep3d_zw<true, T, LS><<<nb, 256, 0, st>>>(g, zt, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                   (cpx<T>*)u);
+  else
+    kb_sweep3d_zw<false, T, LS><<<nb, 256, 0, st>>>(g, zt, (const cpx<T>*)G, (const cpx<T>*)r,
+                                                    (cpx<T>*)u);
+}
+
 template <int DIM, int FORM, class T>
 static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u, bool zero,
                            hipStream_t st) {
+  if constexpr (DIM == 3 && FORM == 2) {
+    // measured: the z walk pays off with 16 sources; with fewer, the per-thread gather
+    // through the caches below is faster
+    if (ls == 4) {
+      launch_zw<T, 4>(g, G, r, u, zero, st);
+      VHB_CHECK();
+      return hipSuccess;
+    }
+  }
   if constexpr (DIM == 2 && FORM == 2) {
     if (ls == 6) {
       launch_s64<FORM, T>(g, G, r, u, zero, st);

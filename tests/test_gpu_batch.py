@@ -133,3 +133,37 @@ def test_batch_of_64_assembled_smoothing_step_every_level(precision, tol):
             assert np.linalg.norm(out[s] - ref) <= vt * np.linalg.norm(ref), s
     finally:
         B.vh_destroy(hd)
+
+
+@pytest.mark.parametrize("nsrc", [3, 8, 13])
+def test_batch_3d_assembled_smoothing_and_vcycle(nsrc):
+    """3D assembled smoother with 4, 8 (cache gather) and 16 sources per batch (the
+    z-walking sweep) on a
+    17 x 21 x 41 grid (ragged x-y tiles, two z strips on the finest level): one smoothing
+    step per level and one V-cycle per source against the oracle (complex64, 1e-5)."""
+    c = Case(n=(17, 21, 41), levels=3, alpha=0.5, medium="random", seed=8, sponge_width=4,
+             smoother=B.VH_SMOOTHER_ASSEMBLED, precision=1)
+    ops, mg = c.oracle()
+    hd = c.gpu(batch=1)
+    rng = np.random.default_rng(12)
+    try:
+        for l in range(c.levels - 1):
+            N = int(np.prod(mg.h.n[l]))
+            q = rng.standard_normal((nsrc, N)) + 1j * rng.standard_normal((nsrc, N))
+            u = rng.standard_normal((nsrc, N)) + 1j * rng.standard_normal((nsrc, N))
+            ug = torch.tensor(u, dtype=torch.complex128, device="cuda")
+            B.vh_apply_smoother_batch(hd, l, nsrc, torch.tensor(q, dtype=torch.complex128,
+                                                                 device="cuda"), ug)
+            out = ug.cpu().numpy()
+            for s in (0, nsrc - 1):
+                ref = mg.relax(l, q[s], u[s])
+                assert np.linalg.norm(out[s] - ref) <= 1e-5 * np.linalg.norm(ref), (l, s)
+        v = rng.standard_normal((nsrc, c.N)) + 1j * rng.standard_normal((nsrc, c.N))
+        z = torch.empty((nsrc, c.N), dtype=torch.complex128, device="cuda")
+        B.vh_apply_vcycle_batch(hd, nsrc, torch.tensor(v, dtype=torch.complex128, device="cuda"), z)
+        out = z.cpu().numpy()
+        for s in (0, nsrc - 1):
+            ref = mg.apply(v[s])
+            assert np.linalg.norm(out[s] - ref) <= 1e-5 * np.linalg.norm(ref), s
+    finally:
+        B.vh_destroy(hd)

@@ -891,23 +891,38 @@ hipError_t batch_prolong_add(int dim, int pf, Grid gf, Grid gc, int ls, int prec
 }
 
 // Y[row][s] = sum_j D[row][j] X[j][s], D the FP64 coarsest inverse (one thread per (row, s))
+// Y = D X for the coarsest level (D the dense FP64 inverse, n x n; X, Y n x S): each
+// output is summed by DKS threads over interleaved columns, then combined in LDS in a
+// fixed order, so that the short coarsest solve spreads over enough blocks
+constexpr int DKS = 8;
+
 template <class T>
 __global__ __launch_bounds__(256) void kb_dense(int n, int ls, const cpx<double>* __restrict__ D,
                                                 const cpx<T>* __restrict__ X,
                                                 cpx<T>* __restrict__ Y) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ((long long)n << ls)) return;
-  const int row = (int)(t >> ls), s = (int)(t & ((1 << ls) - 1));
+  __shared__ cpx<double> red[DKS][256 / DKS];
+  constexpr int OB = 256 / DKS;  // outputs per block
+  const int ks = threadIdx.x / OB, ob = threadIdx.x % OB;
+  const long long t = (long long)blockIdx.x * OB + ob;  // output (row, source)
+  const bool valid = t < ((long long)n << ls);
+  const int row = valid ? (int)(t >> ls) : 0, s = (int)(t & ((1 << ls) - 1));
   const int S = 1 << ls;
   cpx<double> acc = cmk(0.0, 0.0);
-  for (int j = 0; j < n; ++j)
-    acc = cfma(D[(size_t)row * n + j], ccast<double>(X[(size_t)j * S + s]), acc);
-  Y[t] = ccast<T>(acc);
+  if (valid)
+    for (int j = ks; j < n; j += DKS)
+      acc = cfma(D[(size_t)row * n + j], ccast<double>(X[(size_t)j * S + s]), acc);
+  red[ks][ob] = acc;
+  __syncthreads();
+  if (ks == 0 && valid) {
+    cpx<double> sum = red[0][ob];
+    for (int k = 1; k < DKS; ++k) sum = sum + red[k][ob];
+    Y[t] = ccast<T>(sum);
+  }
 }
 
 hipError_t batch_dense(int n, int ls, const cpx<double>* D, int prec, const void* X, void* Y,
                        hipStream_t st) {
-  const unsigned nb = nblk((long long)n << ls, 256);
+  const unsigned nb = nblk((long long)n << ls, 256 / DKS);
   if (prec == PREC_F64)
     kb_dense<double><<<nb, 256, 0, st>>>(n, ls, D, (const cpx<double>*)X, (cpx<double>*)Y);
   else

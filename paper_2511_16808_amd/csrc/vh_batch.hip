@@ -1459,7 +1459,8 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
 template <int NJ>
 __global__ __launch_bounds__(256) void kb_dcgs_b(cpx<double>* __restrict__ V, size_t ldv, int c0,
                                                  int nc, int j, int first, int last, long long N,
-                                                 int ls, const BatchKrylovDev* __restrict__ K) {
+                                                 int ls, const BatchKrylovDev* __restrict__ K,
+                                                 cpx<float>* __restrict__ lo) {
   __shared__ cpx<double> xs[NJ][64], ys[NJ][64];
   const int S = 1 << ls;
   for (int e = threadIdx.x; e < NJ * 64; e += 256) {
@@ -1490,6 +1491,7 @@ __global__ __launch_bounds__(256) void kb_dcgs_b(cpx<double>* __restrict__ V, si
     if (last) {
       t0 = ib * t0;
       t1 = inu * t1;
+      if (lo) lo[o] = ccast<float>(t1);
     }
     u[o] = t0;
     w[o] = t1;
@@ -1504,7 +1506,7 @@ hipError_t batch_dcgs_fin(BatchKrylovDev* K, int j, int S, int closing, hipStrea
 }
 
 hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
-                        const BatchKrylovDev* K, hipStream_t st) {
+                        const BatchKrylovDev* K, cpx<float>* lo, hipStream_t st) {
   if (j < 0 || j >= MMAX) return hipErrorInvalidValue;
   const int ng = j > 0 ? (j + DG - 1) / DG : 1;
   const long long total = N << ls;
@@ -1513,11 +1515,11 @@ hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
     const int c0 = q * DG, nc = j - c0 < DG ? j - c0 : DG;
     const int first = q == 0, last = q == ng - 1;
     if (nc <= 4)
-      kb_dcgs_b<4><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+      kb_dcgs_b<4><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
     else if (nc <= 8)
-      kb_dcgs_b<8><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+      kb_dcgs_b<8><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
     else
-      kb_dcgs_b<DG><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K);
+      kb_dcgs_b<DG><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
     VHB_CHECK();
   }
   return hipSuccess;

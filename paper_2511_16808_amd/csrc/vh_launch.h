@@ -143,7 +143,9 @@ hipError_t batch_scale(const BatchKrylovDev* K, const cpx<double>* w, cpx<double
 hipError_t batch_dcgs_a(const cpx<double>* V, size_t ldv, int j, int wcol, long long N, int ls,
                         cpx<double>* part, int nb, BatchKrylovDev* K, hipStream_t st);
 hipError_t batch_dcgs_fin(BatchKrylovDev* K, int j, int S, int closing, hipStream_t st);
+// lo (optional): also receives the new lagged vector rounded to complex64, the next
+// preconditioner input
 hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
-                        const BatchKrylovDev* K, hipStream_t st);
+                        const BatchKrylovDev* K, cpx<float>* lo, hipStream_t st);
 
 }  // namespace vh

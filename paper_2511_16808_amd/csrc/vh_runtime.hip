@@ -461,8 +461,16 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
       stop = est <= tol || its >= hd->opt.maxit || hd->hstat[1] == 0.0;
       return VH_OK;
     };
+    // complex64 preconditioner: pass B leaves the next input already rounded in L0.q
+    cpx<float>* lo = hd->prec == PREC_F32 ? (cpx<float>*)hd->L[0].q : nullptr;
     for (int j = 0; j < m && !stop; ++j) {
-      VH_TRY(precondition(hd, Vj(j), Zj(j)));
+      if (j > 0 && lo) {
+        const int tk = hd->tbegin(2);
+        VH_TRY(vcycle(hd, 0, hd->L[0].q, Zj(j), true));
+        hd->tend(tk);
+      } else {
+        VH_TRY(precondition(hd, Vj(j), Zj(j)));
+      }
       VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec,
                      Zj(j), PREC_F64, nullptr, Vj(j + 1), hd->s));
       VH_HIP(batch_dcgs_a(V, N, j, j + 1, NL, 0, hd->dpart, hd->dnb, K, hd->s));
@@ -471,7 +479,7 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
         VH_TRY(account(j));
         if (stop) break;
       }
-      VH_HIP(batch_dcgs_b(V, N, j, NL, 0, K, hd->s));
+      VH_HIP(batch_dcgs_b(V, N, j, NL, 0, K, lo, hd->s));
     }
     if (!stop) {
       VH_HIP(batch_dcgs_a(V, N, m, m, NL, 0, hd->dpart, hd->dnb, K, hd->s));
@@ -740,10 +748,12 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       return all_stopped ? VH_ENOCONV : VH_OK;  // VH_ENOCONV here: every source stopped
     };
     bool finished = false;
+    // complex64 preconditioner: pass B leaves the next input already rounded in bq[0]
+    cpx<float>* lo = hd->prec == PREC_F32 ? (cpx<float>*)hd->bq[0] : nullptr;
     for (int j = 0; j < m && !finished; ++j) {
       const void* qv = Vj(j);
       if (hd->prec != PREC_F64) {
-        VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
+        if (j == 0) VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
         qv = hd->bq[0];
       }
       const int tk = hd->tbegin(2);
@@ -761,7 +771,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
         }
         VH_TRY(a);
       }
-      VH_HIP(batch_dcgs_b(hd->bV, ldv, j, N, ls, K, s));
+      VH_HIP(batch_dcgs_b(hd->bV, ldv, j, N, ls, K, lo, s));
     }
     if (!finished) {
       VH_HIP(batch_dcgs_a(hd->bV, ldv, m, m, N, ls, hd->bpart, hd->bnred, K, s));

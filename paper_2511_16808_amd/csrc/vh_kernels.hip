@@ -504,11 +504,13 @@ hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const
 // ------------------------------------------------------------------ Vanka setup
 // Sec. 3.2/3.3: for every patch c (anchored at every node, truncated at the
 // boundary), A_c = V_c H_s V_c^T is inverted in FP64 by Gauss-Jordan elimination
-// with partial pivoting.  One lane per patch row (Np lanes per patch, 64/Np patches
-// per wave); out-of-domain members are identity rows (padding).  Pivoting is
-// implicit: rows stay in their lanes, the pivot row of each step is broadcast with
-// lane shuffles.  After step s, A^{-1}[step(L)][piv[s]] = a_L[s] for lane L.
-// Row i of A_c^{-1} is written, scaled by w / cnt(c + off_i), to
+// with partial pivoting.  One lane per patch row (Np lanes per patch; a patch of more
+// than 16 members takes 32 lanes, so that it fills half a wave and its pivot search
+// stays inside DPP rows); out-of-domain members are identity rows (padding).
+// Pivoting is implicit: rows stay in their lanes, the pivot row of each step is
+// broadcast through LDS.  Pivot rows are not normalised during the elimination: after
+// step s, A^{-1}[step(L)][piv[s]] = a_L[s] / d_L for lane L, d_L the pivot value of
+// row L at its step.  Row i of A_c^{-1} is written, scaled by w / cnt(c + off_i), to
 // G[(i*Np + m)][c + off_i].
 __device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
@@ -550,21 +552,39 @@ __device__ __forceinline__ int patch_count(const Grid& g, int x, int y, int z) {
   return c;
 }
 
+// lanes per patch in the setup kernel
+template <int DIM, int PATCH>
+__host__ __device__ constexpr int setup_group() {
+  return patch_Np<DIM, PATCH>() > 16 ? 32 : patch_Np<DIM, PATCH>();
+}
+
 // waves per block of the setup kernel: the LDS staging area (Np*Np rows of PB
 // patches) must fit in 64 KB
 template <int DIM, int PATCH, class T>
 __host__ __device__ constexpr int setup_waves() {
-  return (patch_Np<DIM, PATCH>() * patch_Np<DIM, PATCH>() * 4 * (64 / patch_Np<DIM, PATCH>()) *
+  return (patch_Np<DIM, PATCH>() * patch_Np<DIM, PATCH>() * 4 * (64 / setup_group<DIM, PATCH>()) *
               (int)sizeof(cpx<T>) <= 65536)
              ? 4
              : 2;
+}
+
+__device__ __forceinline__ unsigned dpp_max(unsigned v, int ctrl_sel) {
+  unsigned o;
+  switch (ctrl_sel) {
+    case 0: o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false); break;
+    case 1: o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false); break;
+    case 2: o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false); break;
+    default: o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false); break;
+  }
+  return o > v ? o : v;
 }
 
 template <int DIM, int SHAPE, int PATCH, class T>
 __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
                                                      double w, cpx<T>* __restrict__ G, Slab sl) {
   constexpr int Np = patch_Np<DIM, PATCH>();
-  constexpr int PPW = 64 / Np;
+  constexpr int GW = setup_group<DIM, PATCH>();
+  constexpr int PPW = 64 / GW;
   constexpr int WPB = setup_waves<DIM, PATCH, T>();
   constexpr int PB = WPB * PPW;  // patches per block
   __shared__ cpx<T> stage[Np * Np * PB];
@@ -572,21 +592,22 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   __shared__ long long cpad[PB];  // padded index of each patch anchor
   const unsigned lane = threadIdx.x & 63u;
   const unsigned wib = threadIdx.x >> 6;  // wave in block
-  const unsigned slot = lane / Np;
-  const int k = (int)(lane % Np);
+  const unsigned slot = lane / GW;
+  const int k = (int)(lane % GW);
   const long long c0 = sl.c_lo + (long long)blockIdx.x * PB;
   const int pslot = (int)(wib * PPW + slot);
   const long long c = c0 + pslot;
-  const bool in_slot = slot < (unsigned)PPW;
+  const bool in_slot = slot < (unsigned)PPW && k < Np;
   const bool in_range = in_slot && c < sl.c_hi;
-  const int base = (int)(in_slot ? slot : 0) * Np;
+  const int base = (int)(slot < (unsigned)PPW ? slot : 0) * GW;
   const size_t N = (size_t)g.N;
   int cx = 0, cy = 0, cz = 0;
   if (in_range) decode((unsigned)c, g, cx, cy, cz);
   // a node that anchors no patch keeps identity rows and writes nothing
   const bool active = in_range && anchor_ok<DIM, PATCH>(g, cx, cy, cz);
-  const int kx = cx + patch_off<DIM, PATCH>(k, 0), ky = cy + patch_off<DIM, PATCH>(k, 1),
-            kz = cz + patch_off<DIM, PATCH>(k, 2);
+  const int kk = k < Np ? k : 0;
+  const int kx = cx + patch_off<DIM, PATCH>(kk, 0), ky = cy + patch_off<DIM, PATCH>(kk, 1),
+            kz = cz + patch_off<DIM, PATCH>(kk, 2);
   const bool mem_in = active && inside(g, kx, ky, kz);
   const long long ik = mem_in ? lin(g, kx, ky, kz) : 0;
 
@@ -595,9 +616,9 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   for (int m = 0; m < Np; ++m) {
     a[m] = cmk(0.0, 0.0);
     if (mem_in) {
-      const int dx = patch_off<DIM, PATCH>(m, 0) - patch_off<DIM, PATCH>(k, 0);
-      const int dy = patch_off<DIM, PATCH>(m, 1) - patch_off<DIM, PATCH>(k, 1);
-      const int dz = patch_off<DIM, PATCH>(m, 2) - patch_off<DIM, PATCH>(k, 2);
+      const int dx = patch_off<DIM, PATCH>(m, 0) - patch_off<DIM, PATCH>(kk, 0);
+      const int dy = patch_off<DIM, PATCH>(m, 1) - patch_off<DIM, PATCH>(kk, 1);
+      const int dz = patch_off<DIM, PATCH>(m, 2) - patch_off<DIM, PATCH>(kk, 2);
       const int s = shape_index<DIM, SHAPE>(dx, dy, dz);
       if (s >= 0 && inside(g, kx + dx, ky + dy, kz + dz)) a[m] = A[(size_t)s * N + ik];
     } else if (m == k) {
@@ -609,38 +630,45 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   // working matrix, a[1 .. Np-1-s] the columns after it and a[Np-s ..] the inverse's
   // columns of steps 0 .. s-1; every step shifts the row down by one and appends the
   // new inverse column, so the loop stays rolled and every register index is static.
-  // The pivot is the unused row with the largest |re| + |im| in a[0] (the first one on
-  // ties), found by a tree over the patch's lanes; its raw row is broadcast with lane
-  // shuffles and every row takes a[m] <- keep * a[m+1] + c * p[m+1], a[Np-1] <- c, with
-  // keep = 0, c = 1/p[0] on the pivot row and keep = 1, c = -a[0]/p[0] on the others
-  // (no divergent branch).  After the last step a[s] = A^{-1}[step(L)][piv[s]].
-  // The pivot sequence of each patch is kept in LDS.
+  // The pivot is the unused row with the largest |re| + |im| in a[0], compared in
+  // single precision with the lane index in the low mantissa bits (the first row on
+  // ties within 2^-18), so that one 32-bit maximum over the patch's lanes finds it.
+  // Its raw row is broadcast through LDS and every row takes
+  // a[m] <- a[m+1] + c * p[m+1], a[Np-1] <- c with c = -a[0]/p[0], except the pivot
+  // row: c = 0 and a[Np-1] <- 1, so it stays unnormalised and its pivot value d is
+  // kept to scale the row once at the end.  The pivot sequence of each patch is kept
+  // in LDS.
   __shared__ unsigned char pivs[PB * Np];
   __shared__ cpx<double> prow[WPB][PPW][Np];
   bool used = false;
   int mystep = k;
-#pragma unroll 1
+  cpx<double> dpiv = cmk(1.0, 0.0);
+  cpx<double>* pr = prow[wib][slot < (unsigned)PPW ? slot : 0];
+  constexpr int CH = 6;  // pivot-row entries read per batch
+#pragma unroll 3
   for (int s = 0; s < Np; ++s) {
     const cpx<double> as = a[0];
-    double bv = in_slot ? (used ? -1.0 : (fabs(as.re) + fabs(as.im))) : -3.0;
-    int bi = k;
+    const float mag = (float)(fabs(as.re) + fabs(as.im));
+    unsigned key = (in_slot && !used) ? ((__float_as_uint(mag) & ~31u) | (31u - (unsigned)k)) : 0u;
+    if constexpr (GW == 32) {
+      key = dpp_max(key, 0);
+      key = dpp_max(key, 1);
+      key = dpp_max(key, 2);
+      key = dpp_max(key, 3);
+      const unsigned o = (unsigned)__shfl_xor((int)key, 16, 64);
+      key = o > key ? o : key;
+    } else {
 #pragma unroll
-    for (int off = 16; off >= 1; off >>= 1) {
-      if (off >= Np) continue;
-      const double pv = shfl_d(bv, (int)lane + off);
-      const int pi = __shfl(bi, (int)lane + off, 64);
-      if (k + off < Np && (pv > bv || (pv == bv && pi < bi))) {
-        bv = pv;
-        bi = pi;
+      for (int off = 16; off >= 1; off >>= 1) {
+        if (off >= GW) continue;
+        const unsigned o = (unsigned)__shfl((int)key, (int)lane + off, 64);
+        key = (k + off < Np && o > key) ? o : key;
       }
+      key = (unsigned)__shfl((int)key, base, 64);
     }
-    const int best = __shfl(bi, base, 64);
+    const int best = 31 - (int)(key & 31u);
     if (in_slot && k == 0) pivs[pslot * Np + s] = (unsigned char)best;
     const bool am = in_slot && (k == best);
-    // the pivot row goes through LDS: its lane writes it, every lane of the patch reads
-    // it back as 16-byte broadcasts (one LDS instruction per entry instead of four
-    // 4-byte lane permutes); a wave's LDS operations complete in order
-    cpx<double>* pr = prow[wib][in_slot ? slot : 0];
     if (am) {
 #pragma unroll
       for (int m = 0; m < Np; ++m) pr[m] = a[m];
@@ -651,20 +679,28 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     const cpx<double> ps = pr[0];
     const double dd = 1.0 / (ps.re * ps.re + ps.im * ps.im);
     const cpx<double> inv = cmk(ps.re * dd, -ps.im * dd);
-    const cpx<double> c = am ? inv : cmk(0.0, 0.0) - as * inv;
-    const double keep = am ? 0.0 : 1.0;
+    const cpx<double> c = am ? cmk(0.0, 0.0) : cmk(0.0, 0.0) - as * inv;
 #pragma unroll
-    for (int m = 0; m + 1 < Np; ++m) {
-      const cpx<double> p = pr[m + 1];
-      cpx<double> t;
-      t.re = fma(keep, a[m + 1].re, fma(c.re, p.re, -c.im * p.im));
-      t.im = fma(keep, a[m + 1].im, fma(c.re, p.im, c.im * p.re));
-      a[m] = t;
+    for (int m0 = 0; m0 + 1 < Np; m0 += CH) {
+      cpx<double> pb[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (m0 + q + 1 < Np) pb[q] = pr[m0 + q + 1];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        if (m0 + q + 1 < Np) {
+          cpx<double> t;
+          t.re = fma(-c.im, pb[q].im, fma(c.re, pb[q].re, a[m0 + q + 1].re));
+          t.im = fma(c.im, pb[q].re, fma(c.re, pb[q].im, a[m0 + q + 1].im));
+          a[m0 + q] = t;
+        }
+      }
     }
-    a[Np - 1] = c;
+    a[Np - 1] = am ? cmk(1.0, 0.0) : c;
     if (am) {
       used = true;
       mystep = s;
+      dpiv = ps;
     }
     // every lane has read the row before the next step's pivot lane overwrites it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -691,8 +727,10 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   const bool ok = mem_in && inside(g, jx, jy, jz);
   if (in_slot) {
     const double wt = ok ? w / (double)patch_count<DIM, PATCH>(g, jx, jy, jz) : 0.0;
+    const double dd = 1.0 / (dpiv.re * dpiv.re + dpiv.im * dpiv.im);
+    const cpx<double> sc = cmk(wt * dpiv.re * dd, -wt * dpiv.im * dd);  // w / (cnt d)
 #pragma unroll
-    for (int s = 0; s < Np; ++s) stage[(pivs[pslot * Np + s] + i * Np) * PB + pslot] = ccast<T>(wt * a[s]);
+    for (int s = 0; s < Np; ++s) stage[(pivs[pslot * Np + s] + i * Np) * PB + pslot] = ccast<T>(sc * a[s]);
     okrow[i * PB + pslot] = ok ? 1 : 0;
     if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
@@ -709,8 +747,7 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
 template <int DIM, int SHAPE, int PATCH>
 static hipError_t vanka_setup_s(Grid g, const cpx<double>* A, double w, int prec, void* G,
                                 Slab sl, hipStream_t s) {
-  constexpr int Np = patch_Np<DIM, PATCH>();
-  constexpr int PPW = 64 / Np;
+  constexpr int PPW = 64 / setup_group<DIM, PATCH>();
   if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
   const long long nc = sl.c_hi - sl.c_lo;
   if (prec == PREC_F64) {

@@ -32,13 +32,13 @@ WORKLOADS = {
     "c1": dict(desc="2D homogeneous 129x129 nodes (128^2 cells), kappa=1, 10 ppw, gamma=0.01*omega, "
                     "ABC, shift 0.1, 4-level V(1,1), Full 3x3 Vanka, FGMRES(20), complex128",
                dim=2, n=(129, 129), levels=4, alpha=0.1, medium="homogeneous", seed=0,
-               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6],
+               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6], smoother="symmetric",
                sample=dict(n=(129, 129), levels=4)),
     "c2": dict(desc="2D layered 1025x1025 nodes (1024^2 cells), 8-14 layers kappa in [0.25,1] + "
                     "5% smooth noise, 10 ppw at kappa_max, gamma=0.01*omega, ABC, shift 0.1, "
                     "7-level V(1,1), Full 3x3 Vanka, FGMRES(20), complex128",
                dim=2, n=(1025, 1025), levels=7, alpha=0.1, medium="layered_2d", seed=2,
-               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6],
+               precision=0, restart=20, damping=[0.94, 1.2, 0.4, 0.6], smoother="symmetric",
                sample=dict(n=(1025, 1025), levels=7)),
     "c4": dict(desc="2D layered 513x513 nodes (512^2 cells), recipe of c2 with seed 4, 64 point "
                     "sources at row 2, columns 4+8k; one shared hierarchy, shift 0.2, 6-level "
@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--budget-gib", type=float, default=240.0, help="c5: HBM budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--smoother", default=None, choices=["patch", "assembled"],
+    ap.add_argument("--smoother", default=None, choices=["patch", "assembled", "symmetric"],
                     help="additive Vanka applied as stored patch inverses or as the same "
                          "operator assembled into a 5^d-point stencil (default: assembled, "
                          "unless the workload names its form)")
@@ -361,7 +361,8 @@ def main():
                    "mfma_bf16x3": B.VH_CONTRACT_MFMA_BF16X3}[args.contraction]
     if contraction != B.VH_CONTRACT_VALU:
         args.smoother = "patch"  # the matrix-core sweep applies the stored patch inverses
-    smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
+    smoother = {"assembled": B.VH_SMOOTHER_ASSEMBLED, "symmetric": B.VH_SMOOTHER_SYMMETRIC,
+                "patch": B.VH_SMOOTHER_PATCH}[args.smoother]
     nsrc = w.get("nsrc", 1)
     batch = w.get("batch", 0) if args.batch is None else args.batch
     precision = w["precision"] if args.precision is None else {"c128": 0, "c64": 1}[args.precision]
@@ -404,13 +405,17 @@ def main():
     width = S if batch else 1   # sources per sweep launch
     info = last["info"]
     E = [i["smoother_entries"] for i in info]
+    if args.smoother == "symmetric":
+        # entries stored per node: the symmetric half (5^d + 1) / 2 on every level whose
+        # operator is symmetric (3D trilinear: all; 2D level-dependent: the two finest)
+        E = [(e + 1) // 2 if (dim == 3 or l < 2) else e for l, e in enumerate(E)]
     # dominant kernel: finest-level additive-Vanka sweep u += B r
     n_l = sum(r["stats"]["smooth1_launches"] for r in runs)
     ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
     bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
     if width == 1:
-        kname = "k_vanka_sweep"
+        kname = "k_vanka_sweep_sym" if args.smoother == "symmetric" else "k_vanka_sweep"
     elif contraction != B.VH_CONTRACT_VALU and width >= 16:
         kname = "kb_sweep_mfma"
     elif dim == 2 and width == 64 and E[0] == 25:

@@ -77,6 +77,17 @@ typedef int vh_status;
 /* Smoother storage. */
 #define VH_SMOOTHER_PATCH 0     /* per-patch inverses, [Np*Np][node]; block multiply + weighted overlap-add */
 #define VH_SMOOTHER_ASSEMBLED 1 /* the same operator summed into a 5^d-point stencil at setup */
+#define VH_SMOOTHER_SYMMETRIC 2 /* the assembled stencil stored as one half where H_s^l is
+                                   complex symmetric (Sec. 3.2, 3.3: every A_c and its inverse
+                                   are then symmetric): 63 (3D) / 13 (2D) entries per node, so
+                                   each sweep reads about half the bytes.  H_s is symmetric
+                                   for VH_STENCIL_FD2; a level keeps it while every transfer
+                                   above it has R and P of one family, and the levels below
+                                   a mixed transfer (VH_IG_MIXED, VH_IG_LEVDEP past the first)
+                                   keep the full stencil.  Needs the Full patch on every
+                                   level, VH_STENCIL_FD2, batch = 0 and the VALU contraction
+                                   (VH_EUNSUPPORTED otherwise) and damping > 0; exported and
+                                   sampled as the full 5^d stencil */
 
 /* Fine-grid stencil (vh_options.stencil).
  *   FD2      : 2nd-order 5-point (2D) / 7-point (3D) stencil (Sec. 2.1); with VH_BC_ABC the

@@ -36,6 +36,7 @@ VH_BC_ABC = 0
 VH_BC_DIRICHLET = 1
 VH_SMOOTHER_PATCH = 0
 VH_SMOOTHER_ASSEMBLED = 1
+VH_SMOOTHER_SYMMETRIC = 2
 VH_STENCIL_FD2 = 0
 VH_STENCIL_COMPACT4 = 1
 VH_CONTRACT_VALU = 0

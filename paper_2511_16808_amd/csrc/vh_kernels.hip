@@ -803,6 +803,130 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ symmetric assembled apply
+// When H_s is complex symmetric (the 5/7-point operator, whose absorbing rows are scaled
+// to keep it symmetric, and Galerkin levels built with R = c P^T), every patch matrix
+// A_c = V_c H_s V_c^T and its inverse are symmetric, so the assembled smoother is
+// B = D S with D = diag(w / cnt_i) and S = sum_c V_c^T A_c^{-1} V_c symmetric (Sec. 3.2,
+// 3.3).  S is stored for the upper half of the 5^DIM box only: entry e' = e - C for the
+// box entries e >= C (C the centre; e grows with dz, then dy, then dx, so these are the
+// offsets d >= 0 in that order), S[e'][i] = S(i, i + d_e).  The sweep is then
+//   u_i += D_i ( sum_{e >= C} S[e-C][i] r[i+d_e] + sum_{e > C} S[e-C][i-d_e] r[i-d_e] ),
+// the second sum reading the entries stored at the neighbours i - d_e.  In 3D the blocks
+// of one 64 x SYM_TY column of tiles run plane after plane (x tiles fastest, then z, then
+// y), so the entries a block reads at planes z-1 and z-2 were read a few blocks earlier
+// by the blocks that own them and come from L2; only the rows across a tile-row edge
+// (about 15 % of the mirrored reads at SYM_TY = 8) go back to HBM.
+
+template <int DIM>
+__host__ __device__ constexpr int sym_entries() { return (ipow(5, DIM) + 1) / 2; }
+
+// rows per tile of the symmetric sweep (the residual tile stays within 33 KB / 65 KB)
+template <class T>
+__host__ __device__ constexpr int sym_ty() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <int DIM, bool ZERO, class T>
+__global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* __restrict__ S,
+                                                         double w, const cpx<T>* __restrict__ r,
+                                                         cpx<T>* __restrict__ u) {
+  constexpr int TY = sym_ty<T>();
+  constexpr int SX = VT_X + 2 * VT_H, SY = TY + 2 * VT_H, SZ = (DIM == 3) ? 1 + 2 * VT_H : 1;
+  constexpr int HZ = (DIM == 3) ? VT_H : 0;
+  __shared__ cpx<T> tile[SZ * SY * SX];
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (g.nx + VT_X - 1) / VT_X;
+  // x tile fastest, then the plane, then the tile row
+  const int bx = (int)(b % (unsigned)nbx);
+  const unsigned t = b / (unsigned)nbx;
+  const int bz = (int)(t % (unsigned)g.nz), by = (int)(t / (unsigned)g.nz);
+  const int x0 = bx * VT_X, y0 = by * TY, z0 = bz;
+  constexpr int NTL = SX * SY * SZ, NPT = (NTL + VT_X * TY - 1) / (VT_X * TY);
+  cpx<T> tv[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int e = (int)threadIdx.x + VT_X * TY * k;
+    const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+    const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+    tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int e = (int)threadIdx.x + VT_X * TY * k;
+    if (e < NTL) tile[e] = tv[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  const int lx = threadIdx.x % VT_X, ly = threadIdx.x / VT_X;
+  const int x = x0 + lx, y = y0 + ly, z = z0;
+  if (x >= g.nx || y >= g.ny) return;
+  const long long i = lin(g, x, y, z);
+  const long long ip = linp(g, x, y, z);
+  constexpr int K5 = ipow(5, DIM), C = (K5 - 1) / 2, EH = sym_entries<DIM>();
+  const size_t Np = (size_t)g.Np;
+  const int sy = g.nxp, sz = g.nxp * g.ny;
+  const unsigned ipu = (unsigned)ip;  // padded index < 2^31 (checked on the host)
+  const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
+  cpx<T> acc = cmk<T>(0, 0);
+  // own entries: S(i, i + d), d >= 0; the plane base is uniform, the per-lane part a
+  // 32-bit offset
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    const int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
+              dz = shape_off<DIM, BOX2>(C + q, 2);
+    const cpx<T>* Sq = S + (size_t)q * Np;
+    acc = cfma(Sq[ipu], t0[(dz * SY + dy) * SX + dx], acc);
+  }
+  // mirrored entries: S(i - d, i) stored at i - d, d > 0 (cached loads: which of the two
+  // reads of an entry comes first depends on the tile order).  A
+  // neighbour i - d outside the grid has r = 0 in the tile, so its entry only has to be
+  // finite: the address stays inside the allocation (a zero guard of sym_guard() entries
+  // precedes plane 0; earlier planes otherwise) and every load is unconditional.
+#pragma unroll
+  for (int q = 1; q < EH; ++q) {
+    const int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
+              dz = shape_off<DIM, BOX2>(C + q, 2);
+    const cpx<T>* Sm = S + (size_t)q * Np - (long long)(dx + sy * dy + sz * dz);
+    acc = cfma(Sm[ipu], t0[-((dz * SY + dy) * SX + dx)], acc);
+  }
+  const T dw = (T)(w / (double)patch_count<DIM, PATCH_FULL>(g, x, y, z));
+  acc = cmk<T>(dw * acc.re, dw * acc.im);
+  u[i] = ZERO ? acc : (u[i] + acc);
+}
+
+template <int DIM, class T>
+static hipError_t vanka_sweep_sym_t(Grid g, const void* S, double w, const void* r, void* u,
+                                    bool zero, hipStream_t s) {
+  constexpr int TY = sym_ty<T>();
+  const unsigned nbx = (unsigned)((g.nx + VT_X - 1) / VT_X), nby = (unsigned)((g.ny + TY - 1) / TY);
+  const unsigned nb = nbx * nby * (unsigned)g.nz;
+  if (zero)
+    k_vanka_sweep_sym<DIM, true, T><<<nb, VT_X * TY, 0, s>>>(g, (const cpx<T>*)S, w,
+                                                             (const cpx<T>*)r, (cpx<T>*)u);
+  else
+    k_vanka_sweep_sym<DIM, false, T><<<nb, VT_X * TY, 0, s>>>(g, (const cpx<T>*)S, w,
+                                                              (const cpx<T>*)r, (cpx<T>*)u);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// entries before plane 0 that the mirrored loads of the sweep may touch
+long long sym_guard(const Grid& g) {
+  return 2 + 2LL * g.nxp + (g.dim == 3 ? 2LL * g.nxp * g.ny : 0);
+}
+
+hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
+                           void* u, bool zero, hipStream_t s) {
+  if (g.Np >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit lane offsets
+  if (dim == 2)
+    return prec == PREC_F64 ? vanka_sweep_sym_t<2, double>(g, S, w, r, u, zero, s)
+                            : vanka_sweep_sym_t<2, float>(g, S, w, r, u, zero, s);
+  if (dim == 3)
+    return prec == PREC_F64 ? vanka_sweep_sym_t<3, double>(g, S, w, r, u, zero, s)
+                            : vanka_sweep_sym_t<3, float>(g, S, w, r, u, zero, s);
+  return hipErrorInvalidValue;
+}
+
 // Assembled form of the same operator: B[d][i] = sum over (a, m) with
 // off_m - off_a = d of G[(a*Np+m)][i]  (d in the 5^DIM box, FULL patch), summed
 // in FP64.  u += B r is then a 5^DIM-point stencil sweep.
@@ -825,9 +949,11 @@ __device__ __forceinline__ int member_of(int mx, int my, int mz) {
   return k;
 }
 
-template <int DIM, int PATCH, class T>
+// SYM: only the entries e >= C (C the centre) are formed, as S = B / D (row i divided
+// by w / cnt_i), for the symmetric sweep above.
+template <int DIM, int PATCH, class T, bool SYM>
 __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __restrict__ G,
-                                                        Slab sl, cpx<T>* __restrict__ B) {
+                                                        Slab sl, double w, cpx<T>* __restrict__ B) {
   const long long i = sl.c_lo + (long long)node_id();
   if (i >= sl.c_hi) return;
   constexpr int Np = patch_Np<DIM, PATCH>();
@@ -839,8 +965,10 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
   const size_t ig = (size_t)(ip - sl.gbase);
   // entry e of the box collects every (a, m) with off_m - off_a = off_e; both loops are
   // unrolled, so the member lookups fold to constants and only existing pairs are loaded
+  constexpr int E0 = SYM ? (K5 - 1) / 2 : 0;
+  const double rs = SYM ? (double)patch_count<DIM, PATCH>(g, cx, cy, cz) / w : 1.0;
 #pragma unroll
-  for (int e = 0; e < K5; ++e) {
+  for (int e = E0; e < K5; ++e) {
     const int dx = shape_off<DIM, BOX2>(e, 0), dy = shape_off<DIM, BOX2>(e, 1),
               dz = shape_off<DIM, BOX2>(e, 2);
     cpx<double> acc = cmk(0.0, 0.0);
@@ -855,28 +983,28 @@ __global__ __launch_bounds__(256) void k_vanka_assemble(Grid g, const cpx<T>* __
                                           cz - patch_off<DIM, PATCH>(a, 2)))
         acc = acc + ccast<double>(G[(size_t)(a * Np + m) * sl.gstride + ig]);
     }
-    B[(size_t)e * N + ip] = ccast<T>(acc);
+    B[(size_t)(e - E0) * N + ip] = ccast<T>(SYM ? rs * acc : acc);
   }
 }
 
-template <int PATCH>
-static hipError_t assemble_p(int dim, Grid g, int prec, const void* G, Slab sl, void* B,
+template <int PATCH, bool SYM>
+static hipError_t assemble_p(int dim, Grid g, int prec, const void* G, Slab sl, double w, void* B,
                              hipStream_t s) {
   const unsigned nb = nblocks((size_t)(sl.c_hi - sl.c_lo), 256);
   if (dim == 2) {
     if (prec == PREC_F64)
-      k_vanka_assemble<2, PATCH, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl,
-                                                            (cpx<double>*)B);
+      k_vanka_assemble<2, PATCH, double, SYM><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, w,
+                                                                 (cpx<double>*)B);
     else
-      k_vanka_assemble<2, PATCH, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl,
-                                                           (cpx<float>*)B);
+      k_vanka_assemble<2, PATCH, float, SYM><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, w,
+                                                                (cpx<float>*)B);
   } else {
     if (prec == PREC_F64)
-      k_vanka_assemble<3, PATCH, double><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl,
-                                                            (cpx<double>*)B);
+      k_vanka_assemble<3, PATCH, double, SYM><<<nb, 256, 0, s>>>(g, (const cpx<double>*)G, sl, w,
+                                                                 (cpx<double>*)B);
     else
-      k_vanka_assemble<3, PATCH, float><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl,
-                                                           (cpx<float>*)B);
+      k_vanka_assemble<3, PATCH, float, SYM><<<nb, 256, 0, s>>>(g, (const cpx<float>*)G, sl, w,
+                                                                (cpx<float>*)B);
   }
   VH_LAUNCH_CHECK();
   return hipSuccess;
@@ -886,12 +1014,83 @@ hipError_t vanka_assemble(int dim, int patch, Grid g, int prec, const void* G, S
                           hipStream_t s) {
   if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
   switch (patch) {
-    case PATCH_FULL: return assemble_p<PATCH_FULL>(dim, g, prec, G, sl, B, s);
-    case PATCH_PLUS: return assemble_p<PATCH_PLUS>(dim, g, prec, G, sl, B, s);
-    case PATCH_RB: return assemble_p<PATCH_RB>(dim, g, prec, G, sl, B, s);
-    case PATCH_ELEMENT: return assemble_p<PATCH_ELEMENT>(dim, g, prec, G, sl, B, s);
+    case PATCH_FULL: return assemble_p<PATCH_FULL, false>(dim, g, prec, G, sl, 1.0, B, s);
+    case PATCH_PLUS: return assemble_p<PATCH_PLUS, false>(dim, g, prec, G, sl, 1.0, B, s);
+    case PATCH_RB: return assemble_p<PATCH_RB, false>(dim, g, prec, G, sl, 1.0, B, s);
+    case PATCH_ELEMENT: return assemble_p<PATCH_ELEMENT, false>(dim, g, prec, G, sl, 1.0, B, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// the upper half of the assembled Full-patch stencil divided by the weights (w > 0)
+hipError_t vanka_assemble_sym(int dim, Grid g, int prec, const void* G, Slab sl, double w, void* S,
+                              hipStream_t s) {
+  if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi || !(w > 0))
+    return hipErrorInvalidValue;
+  return assemble_p<PATCH_FULL, true>(dim, g, prec, G, sl, w, S, s);
+}
+
+// dst[e][i] (FP64, N-node rows, e over the whole 5^DIM box) = B[e][i] = D_i S(i, i + d_e)
+// rebuilt from the stored half: S[e-C][i] for e >= C, S[C'-C][i+d_e] (C' = K5-1-e, the
+// mirrored entry stored at i + d_e) for e < C.
+__device__ __forceinline__ cpx<double> sym_entry(const Grid& g, int K5, double w, int x, int y, int z,
+                                                 int e, const void* S, int prec) {
+  const int C = (K5 - 1) / 2;
+  const int dx = e % 5 - 2, dy = (e / 5) % 5 - 2, dz = g.dim == 3 ? e / 25 - 2 : 0;
+  int q, jx = x, jy = y, jz = z;
+  if (e >= C) {
+    q = e - C;
+  } else {
+    q = (K5 - 1 - e) - C;
+    jx += dx;
+    jy += dy;
+    jz += dz;
+    if (!inside(g, jx, jy, jz)) return cmk(0.0, 0.0);
+  }
+  const size_t at = (size_t)q * (size_t)g.Np + (size_t)linp(g, jx, jy, jz);
+  const cpx<double> v = prec == PREC_F64 ? ((const cpx<double>*)S)[at]
+                                         : ccast<double>(((const cpx<float>*)S)[at]);
+  int cnt = (3 - (x == 0) - (x == g.nx - 1)) * (3 - (y == 0) - (y == g.ny - 1));
+  if (g.dim == 3) cnt *= 3 - (z == 0) - (z == g.nz - 1);
+  return (w / (double)cnt) * v;
+}
+
+__global__ __launch_bounds__(256) void k_unpad_sym(Grid g, int K5, double w, int prec, const void* S,
+                                                   cpx<double>* __restrict__ dst) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)K5 * (size_t)g.N) return;
+  const int e = (int)(t / (size_t)g.N);
+  int x, y, z;
+  decode((unsigned)(t % (size_t)g.N), g, x, y, z);
+  dst[t] = sym_entry(g, K5, w, x, y, z, e, S, prec);
+}
+
+hipError_t unpad_sym(Grid g, double w, int prec, const void* S, cpx<double>* dst, hipStream_t s) {
+  const int K5 = g.dim == 3 ? 125 : 25;
+  const size_t n = (size_t)K5 * (size_t)g.N;
+  k_unpad_sym<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, K5, w, prec, S, dst);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void k_sample_sym(Grid g, int K5, double w, int prec, int count,
+                                                    const long long* __restrict__ nodes,
+                                                    const void* S, cpx<double>* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)count * K5) return;
+  const int k = (int)(t / K5), e = (int)(t % K5);
+  int x, y, z;
+  decode((unsigned)nodes[k], g, x, y, z);
+  out[t] = sym_entry(g, K5, w, x, y, z, e, S, prec);
+}
+
+hipError_t sample_sym(Grid g, double w, int prec, int count, const long long* nodes, const void* S,
+                      cpx<double>* out, hipStream_t s) {
+  const int K5 = g.dim == 3 ? 125 : 25;
+  const unsigned nb = (unsigned)(((long long)count * K5 + 255) / 256);
+  k_sample_sym<<<nb, 256, 0, s>>>(g, K5, w, prec, count, nodes, S, out);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
 }
 
 // dst[e][i] (FP64, N-node rows) = src[e][padded i] (smoother arrays, for inspection)

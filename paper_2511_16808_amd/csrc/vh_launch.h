@@ -81,6 +81,18 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
 hipError_t sample(Grid g, int E, int padded, int prec, int count, const long long* nodes,
                   const void* src, cpx<double>* out, hipStream_t s);
 hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);
+// symmetric half of the assembled Full-patch smoother (upper half of the 5^d box, divided
+// by the weights w / cnt_i): assembly, sweep, and the full stencil rebuilt for export
+hipError_t vanka_assemble_sym(int dim, Grid g, int prec, const void* G, Slab sl, double w, void* S,
+                              hipStream_t s);
+// the sweep reads up to sym_guard(g) entries before plane 0: S must be preceded by that
+// many zero entries of the same allocation
+long long sym_guard(const Grid& g);
+hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
+                           void* u, bool zero, hipStream_t s);
+hipError_t unpad_sym(Grid g, double w, int prec, const void* S, cpx<double>* dst, hipStream_t s);
+hipError_t sample_sym(Grid g, double w, int prec, int count, const long long* nodes, const void* S,
+                      cpx<double>* out, hipStream_t s);
 // B rows of nodes [sl.c_lo, sl.c_hi) from the per-patch rows held as in vanka_setup
 hipError_t vanka_assemble(int dim, int patch, Grid g, int prec, const void* G, Slab sl, void* B,
                           hipStream_t s);

@@ -47,6 +47,8 @@ namespace {
     if (s_ != VH_OK) return s_;     \
   } while (0)
 
+constexpr int SM_SYMHALF = 6;  // Level.form of the symmetric half of the assembled stencil
+
 struct Level {
   Grid g{};
   int shape = CROSS;  // stencil shape of H_s^l
@@ -61,7 +63,8 @@ struct Level {
   double w = 1.0;                         // damping
   size_t bytes = 0;
   int patch = VH_PATCH_FULL;              // patch kind of this level's smoother
-  int form = 0;                           // sweep form: the patch kind, or 2 = assembled
+  int form = 0;                           // sweep form: the patch kind, 2 = assembled,
+                                          // SM_SYMHALF = its symmetric half
   int mfma_txp[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned matrix-core sweep tile per log2(S)
   int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
 };
@@ -267,8 +270,19 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
       o.fine_patch != VH_PATCH_PLUS && o.fine_patch != VH_PATCH_RB &&
       o.fine_patch != VH_PATCH_ELEMENT)
     return fail(VH_EINVAL, "unknown fine_patch");
-  if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED)
+  if (o.smoother != VH_SMOOTHER_PATCH && o.smoother != VH_SMOOTHER_ASSEMBLED &&
+      o.smoother != VH_SMOOTHER_SYMMETRIC)
     return fail(VH_EINVAL, "unknown smoother");
+  if (o.smoother == VH_SMOOTHER_SYMMETRIC &&
+      (patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
+       o.stencil != VH_STENCIL_FD2 || o.batch != 0 || o.contraction != VH_CONTRACT_VALU))
+    return fail(VH_EUNSUPPORTED,
+                "the symmetric smoother needs the Full patch, the 5/7-point stencil, batch = 0 "
+                "and the VALU contraction");
+  if (o.smoother == VH_SMOOTHER_SYMMETRIC)
+    for (int k = 0; k < o.ndamping; ++k)
+      if (!(o.damping[k] > 0.0))
+        return fail(VH_EINVAL, "the symmetric smoother needs damping > 0 on every level");
   if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
   if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
     return fail(VH_EINVAL, "unknown contraction");
@@ -327,7 +341,10 @@ size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N *
 vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(zero ? 0 : 1) : -1;
   const int form = Lv.form;
-  VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
+  if (form == SM_SYMHALF)
+    VH_HIP(vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, r, u, zero, hd->s));
+  else
+    VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
   return VH_OK;
 }
@@ -509,6 +526,8 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
 
 // ---------------------------------------------------------------- multi-source path
 vh_status ensure_batch(vh_handle* hd, int S) {
+  if (hd->opt.smoother == VH_SMOOTHER_SYMMETRIC)
+    return fail(VH_EUNSUPPORTED, "the multi-source sweeps do not take the symmetric smoother");
   if (hd->bS >= S) return VH_OK;
   // (re)allocate for S sources
   auto drop = [&](void* p) {
@@ -846,7 +865,7 @@ SlabPlan slab_plan(int dim, const Grid& g, int Np, size_t esz, size_t scratch_by
 // array: each slab of output planes gets its patch inverses in the scratch area (the
 // patches centred within one plane of the slab), then its assembled rows.
 vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
-                         void* scratch, size_t scratch_bytes) {
+                         void* scratch, size_t scratch_bytes, bool sym) {
   const int dim = hd->dim;
   const Grid& g = Lv.g;
   hipStream_t s = hd->s;
@@ -855,24 +874,32 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
   if (p.own) VH_TRY(hd->alloc(&buf, (size_t)p.cnt_max * p.per_plane));
   const size_t gstride = (size_t)p.cnt_max * p.plane_pad;
   const int K5 = dim == 2 ? 25 : 125;
+  const int E = sym ? (K5 + 1) / 2 : K5;
   const size_t Npad = (size_t)g.Np;
-  VH_TRY(hd->alloc(&Lv.B, (size_t)K5 * Npad * hd->esz));
-  VH_HIP(fill(Lv.B, (size_t)K5 * Npad, hd->prec, 0, 0, s));  // row padding stays zero
+  // the symmetric sweep reads up to sym_guard entries before the first plane: a zero guard
+  const size_t guard = sym ? (size_t)sym_guard(g) : 0;
+  void* base = nullptr;
+  VH_TRY(hd->alloc(&base, ((size_t)E * Npad + guard) * hd->esz));
+  VH_HIP(fill(base, (size_t)E * Npad + guard, hd->prec, 0, 0, s));  // row padding stays zero
+  Lv.B = (char*)base + guard * hd->esz;
   for (long long p0 = 0; p0 < p.n_out; p0 += p.SZ) {
     const long long p1 = p0 + p.SZ < p.n_out ? p0 + p.SZ : p.n_out;
     const long long b0 = p0 - 2 > 0 ? p0 - 2 : 0;
     const long long c0 = p0 - 1 > 0 ? p0 - 1 : 0, c1 = p1 + 1 < p.n_out ? p1 + 1 : p.n_out;
     VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, g, A, Lv.w, hd->prec, buf,
                        Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
-    VH_HIP(vanka_assemble(dim, Lv.patch, g, hd->prec, buf,
-                          Slab{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride}, Lv.B, s));
+    const Slab so{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride};
+    if (sym)
+      VH_HIP(vanka_assemble_sym(dim, g, hd->prec, buf, so, Lv.w, Lv.B, s));
+    else
+      VH_HIP(vanka_assemble(dim, Lv.patch, g, hd->prec, buf, so, Lv.B, s));
   }
   if (p.own) {
     VH_HIP(hipStreamSynchronize(s));
     hd->release(buf);
     hd->bytes -= (size_t)p.cnt_max * p.per_plane;
   }
-  Lv.E = K5;
+  Lv.E = E;
   return VH_OK;
 }
 
@@ -940,6 +967,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   hd->m = o.restart;
   VH_TRY(hd->alloc((void**)&hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
   // per level: operator at the preconditioner precision, patch inverses, vectors
+  bool sym_above = true;
   for (int l = 0; l < hd->levels; ++l) {
     Level& Lv = hd->L[l];
     const size_t N = (size_t)Lv.g.N;
@@ -959,9 +987,15 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     if (l + 1 == hd->levels) break;
     const size_t Npad = (size_t)Lv.g.Np;  // smoother arrays use the padded row layout
     const int Np = patch_size(dim, Lv.patch);
-    if (o.smoother == VH_SMOOTHER_ASSEMBLED && Lv.patch != VH_PATCH_POINT) {
-      VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>)));
-      Lv.form = 2;
+    // H_s^l is symmetric when H_s is and every transfer above level l has R and P of
+    // one family (R = c P^T); below a mixed transfer the full stencil is kept
+    sym_above = sym_above && (l == 0 || (hd->L[l - 1].rf == hd->L[l - 1].pf));
+    if ((o.smoother == VH_SMOOTHER_ASSEMBLED || o.smoother == VH_SMOOTHER_SYMMETRIC) &&
+        Lv.patch != VH_PATCH_POINT) {
+      const bool sym = o.smoother == VH_SMOOTHER_SYMMETRIC && sym_above;
+      VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>),
+                            sym));
+      Lv.form = sym ? SM_SYMHALF : 2;
     } else {
       VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
       VH_HIP(fill(Lv.B, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
@@ -1194,7 +1228,8 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->n[1] = Lv.g.ny;
   info->n[2] = Lv.g.nz;
   info->stencil_points = Lv.K;
-  info->smoother_entries = Lv.E;
+  // the symmetric half is exported (and counted here) as the full assembled stencil
+  info->smoother_entries = Lv.form == SM_SYMHALF ? (hd->dim == 2 ? 25 : 125) : Lv.E;
   shape_offsets(hd->dim, Lv.shape, Lv.K, info->offsets);
   info->bytes = Lv.bytes;
   for (int ls = 6; ls >= 0; --ls)
@@ -1331,10 +1366,12 @@ vh_status vh_export_level(const vh_handle* hdc, int level, void* coef, void* smo
   };
   if (coef) VH_TRY(copy_out(Lv.A, (size_t)Lv.K * N, coef));
   if (smoother && Lv.B) {
-    const size_t count = (size_t)Lv.E * N;
+    const bool sym = Lv.form == SM_SYMHALF;
+    const size_t count = (size_t)(sym ? (hd->dim == 2 ? 25 : 125) : Lv.E) * N;
     void* tmp = nullptr;
     VH_HIP(hipMalloc(&tmp, count * 16));
-    hipError_t e = unpad(Lv.g, Lv.E, hd->prec, Lv.B, (cpx<double>*)tmp, hd->s);
+    hipError_t e = sym ? unpad_sym(Lv.g, Lv.w, hd->prec, Lv.B, (cpx<double>*)tmp, hd->s)
+                       : unpad(Lv.g, Lv.E, hd->prec, Lv.B, (cpx<double>*)tmp, hd->s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(smoother, tmp, count * 16, hipMemcpyDeviceToHost, hd->s);
     if (e == hipSuccess) e = hipStreamSynchronize(hd->s);
@@ -1357,7 +1394,8 @@ vh_status vh_sample_level(const vh_handle* hdc, int level, int which, int count,
     return fail(VH_EINVAL, "bad argument");
   Level& Lv = hd->L[level];
   const void* src = which == 0 ? Lv.A : Lv.B;
-  const int E = which == 0 ? Lv.K : Lv.E;
+  const bool sym = which == 1 && Lv.form == SM_SYMHALF;
+  const int E = which == 0 ? Lv.K : (sym ? (hd->dim == 2 ? 25 : 125) : Lv.E);
   if (which != 0 && which != 1) return fail(VH_EINVAL, "which must be 0 or 1");
   if (!src || E == 0) return fail(VH_EINVAL, "this level has no such array");
   for (int k = 0; k < count; ++k)
@@ -1368,7 +1406,9 @@ vh_status vh_sample_level(const vh_handle* hdc, int level, int which, int count,
   hipError_t e = hipMalloc((void**)&dout, (size_t)count * E * sizeof(cpx<double>));
   if (e == hipSuccess)
     e = hipMemcpyAsync(dn, nodes, (size_t)count * sizeof(long long), hipMemcpyHostToDevice, hd->s);
-  if (e == hipSuccess) e = sample(Lv.g, E, which == 1, hd->prec, count, dn, src, dout, hd->s);
+  if (e == hipSuccess)
+    e = sym ? sample_sym(Lv.g, Lv.w, hd->prec, count, dn, src, dout, hd->s)
+            : sample(Lv.g, E, which == 1, hd->prec, count, dn, src, dout, hd->s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, dout, (size_t)count * E * sizeof(cpx<double>), hipMemcpyDeviceToHost,
                        hd->s);
@@ -1609,6 +1649,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   size_t total = 0, N0 = nn[0] * nn[1] * nn[2], slab_tmp = 0;
   int shape = o.stencil == VH_STENCIL_COMPACT4 ? BOX1 : CROSS;
   total += (size_t)shape_points(dim, shape) * N0 * 16;  // unshifted H
+  bool sym_above = true;  // H_s^l symmetric (every transfer above with R = c P^T)
   for (int l = 0; l < levels; ++l) {
     const size_t N = nn[0] * nn[1] * nn[2];
     const int K = shape_points(dim, shape);
@@ -1619,8 +1660,12 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     }
     const int lp = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : patch;
     const int Np = (l == 0 && o.fine_patch >= 0) ? patch_size(dim, lp) : Np_c;
-    const bool assembled = o.smoother == VH_SMOOTHER_ASSEMBLED && lp != VH_PATCH_POINT;
-    const int E = assembled ? (dim == 2 ? 25 : 125) : Np * Np;
+    const bool assembled =
+        (o.smoother == VH_SMOOTHER_ASSEMBLED || o.smoother == VH_SMOOTHER_SYMMETRIC) &&
+        lp != VH_PATCH_POINT;
+    const int K5 = dim == 2 ? 25 : 125;
+    const int E = assembled ? (o.smoother == VH_SMOOTHER_SYMMETRIC && sym_above ? (K5 + 1) / 2 : K5)
+                            : Np * Np;
     const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
     total += (size_t)E * Npad * esz;
     if (assembled) {  // a temporary slab buffer when the basis is too small to hold one
@@ -1630,6 +1675,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     }
     shape = (ig == VH_IG_LINEAR) ? BOX1
             : (ig == VH_IG_CUBIC && shape != CROSS && shape != BOX1) ? BOX3 : BOX2;
+    sym_above = sym_above && (ig == VH_IG_LINEAR || ig == VH_IG_CUBIC || (ig == VH_IG_LEVDEP && l == 0));
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }
   total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz + slab_tmp;

@@ -103,3 +103,38 @@ def test_lfa_and_tuners_reject_bad_arguments_before_any_device_work():
     assert st == B.VH_EINVAL
     st = B.lib().vh_mg_iterate(None, 1, None, None, 0, 1, 1e-6, None, None)
     assert st == B.VH_EINVAL
+
+
+def test_symmetric_smoother_rejects_what_it_does_not_cover():
+    """The symmetric half needs the Full patch, the 5/7-point stencil, one source per sweep
+    and damping > 0; refused before any device work."""
+    cases = [(dict(stencil=B.VH_STENCIL_COMPACT4), B.VH_PATCH_FULL, B.VH_EUNSUPPORTED),
+             (dict(batch=1), B.VH_PATCH_FULL, B.VH_EUNSUPPORTED),
+             (dict(), B.VH_PATCH_RB, B.VH_EUNSUPPORTED),
+             (dict(fine_patch=B.VH_PATCH_POINT), B.VH_PATCH_FULL, B.VH_EUNSUPPORTED),
+             (dict(damping=[0.9, 0.0]), B.VH_PATCH_FULL, B.VH_EINVAL)]
+    for extra, patch, status in cases:
+        o = B.make_options(smoother=B.VH_SMOOTHER_SYMMETRIC, **extra)
+        with pytest.raises(B.VhError) as e:
+            B.vh_setup(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 3, patch, o)
+        assert e.value.status == status, extra
+
+
+def test_symmetric_footprint():
+    """3D trilinear: every smoothed level stores 63 instead of 125 entries per node; 2D
+    level-dependent transfers: only the two finest levels are symmetric."""
+    n3 = (129, 129, 129)
+    fa = B.vh_footprint_bytes(3, n3, 5, B.VH_PATCH_FULL, 1,
+                              B.make_options(smoother=B.VH_SMOOTHER_ASSEMBLED))
+    fs = B.vh_footprint_bytes(3, n3, 5, B.VH_PATCH_FULL, 1,
+                              B.make_options(smoother=B.VH_SMOOTHER_SYMMETRIC))
+    nxp = 160
+    fine = 62 * 16 * nxp * 129 * 129  # entries saved on the finest level alone
+    assert fa - fs > fine
+    n2 = (257, 257)
+    fa2 = B.vh_footprint_bytes(2, n2, 5, B.VH_PATCH_FULL, 1,
+                               B.make_options(smoother=B.VH_SMOOTHER_ASSEMBLED))
+    fs2 = B.vh_footprint_bytes(2, n2, 5, B.VH_PATCH_FULL, 1,
+                               B.make_options(smoother=B.VH_SMOOTHER_SYMMETRIC))
+    saved = 12 * 16 * (288 * 257 + 160 * 129)  # levels 0 and 1 only
+    assert fa2 - fs2 == saved

@@ -116,13 +116,14 @@ def test_c3_sampled_inverses_and_solve_257():
         B.vh_destroy(hd)
 
 
-def test_c3_assembled_rows_and_solve_257():
-    """257^3 with the assembled smoother (built slab by slab): sampled finest-level
-    rows of the 125-point stencil equal the sums of the oracle's FP64 patch-inverse
-    entries with the same offset, rounded to complex64; the solve's true FP64 residual
-    is <= 1e-6."""
-    from paper_2511_16808_amd.binding import VH_SMOOTHER_ASSEMBLED
-    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c3", smoother=VH_SMOOTHER_ASSEMBLED)
+@pytest.mark.parametrize("sm", ["assembled", "symmetric"])
+def test_c3_assembled_rows_and_solve_257(sm):
+    """257^3 with the assembled smoother (built slab by slab), stored whole or as its
+    symmetric half: sampled finest-level rows of the 125-point stencil equal the sums of
+    the oracle's FP64 patch-inverse entries with the same offset, rounded to complex64;
+    the solve's true FP64 residual is <= 1e-6."""
+    code = B.VH_SMOOTHER_ASSEMBLED if sm == "assembled" else B.VH_SMOOTHER_SYMMETRIC
+    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c3", smoother=code)
     try:
         ops = D.fd2_operator(n, h, omega, kappa, gamma, w["alpha"])
         nx, ny, nz = n

@@ -19,10 +19,7 @@ namespace vh {
 namespace {
 
 __device__ __forceinline__ void decode_b(unsigned i, const Grid& g, int& x, int& y, int& z) {
-  x = (int)(i % (unsigned)g.nx);
-  const unsigned t = i / (unsigned)g.nx;
-  y = (int)(t % (unsigned)g.ny);
-  z = (int)(t / (unsigned)g.ny);
+  grid_decode(i, g, x, y, z);
 }
 __device__ __forceinline__ bool inside_b(const Grid& g, int x, int y, int z) {
   return (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;

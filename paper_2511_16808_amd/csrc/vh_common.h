@@ -82,6 +82,7 @@ struct Grid {
   // boundary scaling, computed in the kernel (only the centre coefficient is read)
   int offrule;
   double ih2;
+  double rnx, rnxy;  // 1/nx and 1/(nx*ny) in FP64, for the node decode
 };
 
 // Smoother arrays ([entry][node], one row per entry) use rows of nxp = nx rounded up
@@ -100,7 +101,25 @@ __host__ __device__ __forceinline__ Grid make_grid(int dim, int nx, int ny, int 
   g.Np = (long long)g.nxp * g.ny * g.nz;
   g.offrule = 0;
   g.ih2 = 0.0;
+  g.rnx = 1.0 / (double)g.nx;
+  g.rnxy = 1.0 / ((double)g.nx * (double)g.ny);
   return g;
+}
+
+// (x, y, z) of node i < 2^31: each quotient from the FP64 reciprocal (within one of the
+// true quotient), then one correction step either way; no integer division
+__device__ __forceinline__ void grid_decode(unsigned i, const Grid& g, int& x, int& y, int& z) {
+  const unsigned long long nxy = (unsigned long long)g.nx * (unsigned long long)g.ny;
+  unsigned zq = (unsigned)((double)i * g.rnxy);
+  if ((unsigned long long)zq * nxy > i) --zq;
+  if ((unsigned long long)(zq + 1) * nxy <= i) ++zq;
+  const unsigned rem = i - (unsigned)((unsigned long long)zq * nxy);
+  unsigned yq = (unsigned)((double)rem * g.rnx);
+  if (yq * (unsigned)g.nx > rem) --yq;
+  if ((yq + 1) * (unsigned)g.nx <= rem) ++yq;
+  x = (int)(rem - yq * (unsigned)g.nx);
+  y = (int)yq;
+  z = (int)zq;
 }
 
 // ---------------------------------------------------------------- stencil shapes

@@ -13,10 +13,7 @@ namespace vh {
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ void decode(unsigned i, const Grid& g, int& x, int& y, int& z) {
-  x = (int)(i % (unsigned)g.nx);
-  const unsigned t = i / (unsigned)g.nx;
-  y = (int)(t % (unsigned)g.ny);
-  z = (int)(t / (unsigned)g.ny);
+  grid_decode(i, g, x, y, z);
 }
 __device__ __forceinline__ bool inside(const Grid& g, int x, int y, int z) {
   return (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
@@ -268,15 +265,16 @@ __global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restri
       const bool up = ((k - 1) & 1) != 0;
       const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
                 dz = shape_off<DIM, SHAPE>(k, 2);
-      if (inside(g, cx + dx, cy + dy, cz + dz)) {
-        const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
-        const double wv = (g.offrule == 2 && ((up && lo) || (!up && hi))) ? -2.0 * g.ih2 : -g.ih2;
-        const TC ov = (TC)(scale * wv);
-        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-        const cpx<TC> xv = ccast<TC>(x[j]);
-        acc.re = fma(ov, xv.re, acc.re);
-        acc.im = fma(ov, xv.im, acc.im);
-      }
+      // a neighbour outside the grid: the node's own value with weight 0 (no branch)
+      const bool ok = inside(g, cx + dx, cy + dy, cz + dz);
+      const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
+      const double wv = (g.offrule == 2 && ((up && lo) || (!up && hi))) ? -2.0 * g.ih2 : -g.ih2;
+      const TC ov = ok ? (TC)(scale * wv) : (TC)0;
+      const long long j =
+          ok ? (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz) : (long long)i;
+      const cpx<TC> xv = ccast<TC>(x[j]);
+      acc.re = fma(ov, xv.re, acc.re);
+      acc.im = fma(ov, xv.im, acc.im);
     }
   } else {
 #pragma unroll
@@ -734,13 +732,17 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     okrow[i * PB + pslot] = ok ? 1 : 0;
     if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
+  // padded-layout offset of every member, computed once per block (member k by the
+  // lanes of slot 0 of wave 0, whose offsets are compile-time after unrolling)
+  __shared__ long long moff[Np];
+  if (threadIdx.x < (unsigned)Np) moff[k] = linp(g, patch_off<DIM, PATCH>(kk, 0),
+                                                 patch_off<DIM, PATCH>(kk, 1),
+                                                 patch_off<DIM, PATCH>(kk, 2));
   __syncthreads();
   for (int e = threadIdx.x; e < Np * Np * PB; e += blockDim.x) {
     const int r = e / PB, p = e % PB, ii = r / Np;
     if (!okrow[ii * PB + p]) continue;
-    const long long off = linp(g, patch_off<DIM, PATCH>(ii, 0), patch_off<DIM, PATCH>(ii, 1),
-                               patch_off<DIM, PATCH>(ii, 2));
-    G[(size_t)r * sl.gstride + (size_t)(cpad[p] + off - sl.gbase)] = stage[e];
+    G[(size_t)r * sl.gstride + (size_t)(cpad[p] + moff[ii] - sl.gbase)] = stage[e];
   }
 }
 
@@ -1255,6 +1257,37 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid gf, Grid gc, const cpx
   if (i >= gf.N) return;
   int c[3];
   decode(i, gf, c[0], c[1], c[2]);
+  if constexpr (PF == FAM_LINEAR) {
+    // p(0) = 1, p(+-1) = 1/2: an even index takes coarse node c/2, an odd one the mean of
+    // (c-1)/2 and (c+1)/2 (inside, since every fine grid has 2 n_c - 1 nodes).  All 2^DIM
+    // candidates are loaded unconditionally; an even index repeats its node with weight 0.
+    int ja[3], jb[3];
+    T wa[3], wb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const bool odd = d < DIM && (c[d] & 1);
+      ja[d] = c[d] >> 1;
+      jb[d] = odd ? ja[d] + 1 : ja[d];
+      wa[d] = odd ? (T)0.5 : (T)1;
+      wb[d] = odd ? (T)0.5 : (T)0;
+    }
+    cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+    for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const T wt = (sx ? wb[0] : wa[0]) * (sy ? wb[1] : wa[1]) *
+                       (DIM == 3 ? (sz ? wb[2] : wa[2]) : (T)1);
+          const cpx<T> ev = e[lin(gc, sx ? jb[0] : ja[0], sy ? jb[1] : ja[1],
+                                  DIM == 3 ? (sz ? jb[2] : ja[2]) : 0)];
+          acc.re = fma(wt, ev.re, acc.re);
+          acc.im = fma(wt, ev.im, acc.im);
+        }
+    u[i] = u[i] + acc;
+    return;
+  }
   // per dimension: candidate coarse nodes J0-1, J0, J0+1 (J0 = c/2) and weights p(c - 2J)
   int J[3][3];
   T w[3][3];

@@ -71,10 +71,13 @@ def patch_rows(Hs, n, damping, x, y, z):
     return ref
 
 
-def test_c2_vcycle_and_solve_1025():
-    """1025^2 layered medium, 7-level V(1,1), complex128: one V-cycle equals the
-    oracle's to 1e-10; the solve reaches a true FP64 residual <= 1e-6."""
-    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c2")
+@pytest.mark.parametrize("sm", ["patch", "symmetric"])
+def test_c2_vcycle_and_solve_1025(sm):
+    """1025^2 layered medium, 7-level V(1,1), complex128, with the per-patch inverses and
+    with the symmetric half of the assembled stencil (bench.py's c2 configuration): one
+    V-cycle equals the oracle's to 1e-10; the solve reaches a true FP64 residual <= 1e-6."""
+    code = B.VH_SMOOTHER_PATCH if sm == "patch" else B.VH_SMOOTHER_SYMMETRIC
+    w, n, h, omega, kappa, gamma, q, hd = setup_workload("c2", smoother=code)
     try:
         ops = D.fd2_operator(n, h, omega, kappa, gamma, w["alpha"])
         mg = cycle.Multigrid(ops["Hs"], n, w["levels"], "levdep", "full", w["damping"])

@@ -193,3 +193,28 @@ def test_mixed_and_linear_intergrid_2d():
             assert rel(z.cpu().numpy(), mg.apply(v)) <= 1e-10, ig
         finally:
             B.vh_destroy(hd)
+
+
+def test_operator_on_a_plane_of_two_million_nodes():
+    """2049 x 1025 nodes (nx*ny >= 2^21, where the FP64-reciprocal node decode needs its
+    downward correction) with a ragged last block: the fine operator applied on the GPU
+    equals the oracle's to 1e-13, and so does one finest-level smoothing step of the
+    symmetric assembled smoother against the full one."""
+    kw = dict(n=(2049, 1025), levels=7, alpha=0.3, medium="random", seed=12, sponge_width=8)
+    c = Case(**kw, smoother=B.VH_SMOOTHER_SYMMETRIC)
+    ops = c.oracle_ops()
+    hd = c.gpu()
+    hf = Case(**kw, smoother=B.VH_SMOOTHER_ASSEMBLED).gpu()
+    try:
+        x = cplx_randn(c.N, 13)
+        y = torch.empty(c.N, dtype=torch.complex128, device="cuda")
+        B.vh_apply_operator(hd, 0, 0, to_gpu(x), y)
+        assert rel(y.cpu().numpy(), ops["H"] @ x) <= 1e-13
+        q = cplx_randn(c.N, 14)
+        us, uf = to_gpu(x), to_gpu(x)
+        B.vh_apply_smoother(hd, 0, to_gpu(q), us)
+        B.vh_apply_smoother(hf, 0, to_gpu(q), uf)
+        assert rel(us.cpu().numpy() - x, uf.cpu().numpy() - x) <= 1e-12
+    finally:
+        B.vh_destroy(hd)
+        B.vh_destroy(hf)

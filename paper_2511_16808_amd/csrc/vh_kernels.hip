@@ -566,6 +566,9 @@ __host__ __device__ constexpr int setup_waves() {
              : 2;
 }
 
+// max(v, v of a partner lane) with the partner chosen by a DPP pattern: 0 = lane ^ 1,
+// 1 = lane ^ 2 (quad permutes), 2 = mirror within 8 lanes, 3 = mirror within 16 lanes.
+// Applied in that order, every lane ends with the maximum over its 16-lane row.
 __device__ __forceinline__ unsigned dpp_max(unsigned v, int ctrl_sel) {
   unsigned o;
   switch (ctrl_sel) {
@@ -732,8 +735,8 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     okrow[i * PB + pslot] = ok ? 1 : 0;
     if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
-  // padded-layout offset of every member, computed once per block (member k by the
-  // lanes of slot 0 of wave 0, whose offsets are compile-time after unrolling)
+  // padded-layout offset of every member, computed once per block (member k by lane k
+  // of wave 0) instead of once per stored entry
   __shared__ long long moff[Np];
   if (threadIdx.x < (unsigned)Np) moff[k] = linp(g, patch_off<DIM, PATCH>(kk, 0),
                                                  patch_off<DIM, PATCH>(kk, 1),
@@ -814,11 +817,13 @@ hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>*
 // box entries e >= C (C the centre; e grows with dz, then dy, then dx, so these are the
 // offsets d >= 0 in that order), S[e'][i] = S(i, i + d_e).  The sweep is then
 //   u_i += D_i ( sum_{e >= C} S[e-C][i] r[i+d_e] + sum_{e > C} S[e-C][i-d_e] r[i-d_e] ),
-// the second sum reading the entries stored at the neighbours i - d_e.  In 3D the blocks
-// of one 64 x SYM_TY column of tiles run plane after plane (x tiles fastest, then z, then
-// y), so the entries a block reads at planes z-1 and z-2 were read a few blocks earlier
-// by the blocks that own them and come from L2; only the rows across a tile-row edge
-// (about 15 % of the mirrored reads at SYM_TY = 8) go back to HBM.
+// the second sum reading the entries stored at the neighbours i - d_e.  Blocks run x
+// tiles fastest, then planes, then tile rows.  In 2D the mirrored entries lie in the same
+// or the previous tile row, read a few blocks earlier, and come from L2, so each stored
+// entry leaves HBM about once.  In 3D those at planes z-1 and z-2 were read by blocks a few
+// dispatches earlier, but with every XCD streaming many blocks its L2 has turned over by
+// then: the second read comes back from the fabric and the 3D sweep is slower than the
+// full stencil (measured; keeping that reuse needs the products held on chip).
 
 template <int DIM>
 __host__ __device__ constexpr int sym_entries() { return (ipow(5, DIM) + 1) / 2; }

@@ -1209,12 +1209,64 @@ __global__ __launch_bounds__(256) void k_galerkin(Grid gf, Grid gc, const cpx<do
   for (int e = 0; e < KO; ++e) Ac[(size_t)e * Nc + I] = acc[e];
 }
 
+// The same contraction with one thread per (coarse node, output entry e): for coarse
+// grids too small to fill the GPU with one thread per node (each such thread runs the
+// whole unrolled contraction alone).  The t and s loops, the weights and the order of
+// accumulation per entry are those of k_galerkin, so the results are identical; only the
+// zero prolongation weights are skipped at run time instead of at compile time.
+template <int DIM, int SIN, int SOUT, int RF, int PF>
+__global__ __launch_bounds__(256) void k_galerkin_e(Grid gf, Grid gc, const cpx<double>* __restrict__ Af,
+                                                    cpx<double>* __restrict__ Ac) {
+  const unsigned I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (int)blockIdx.y;
+  if (I >= gc.N) return;
+  int Ix, Iy, Iz;
+  decode(I, gc, Ix, Iy, Iz);
+  constexpr int KI = shape_K<DIM, SIN>();
+  constexpr int RR = fam_radius(RF);
+  constexpr int RW = 2 * RR + 1;
+  constexpr int NT = ipow(RW, DIM);
+  constexpr int RO = shape_radius<DIM, SOUT>();
+  constexpr int WO = 2 * RO + 1;
+  const int ex = e % WO - RO, ey = (e / WO) % WO - RO, ez = (DIM == 3) ? e / (WO * WO) - RO : 0;
+  const size_t Nf = (size_t)gf.N, Nc = (size_t)gc.N;
+  cpx<double> acc = cmk(0.0, 0.0);
+  if (inside(gc, Ix + ex, Iy + ey, Iz + ez)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int tx = t % RW - RR, ty = (t / RW) % RW - RR, tz = (DIM == 3) ? t / (RW * RW) - RR : 0;
+      const int fx = 2 * Ix + tx, fy = 2 * Iy + ty, fz = 2 * Iz + tz;
+      if (!inside(gf, fx, fy, fz)) continue;
+      const double wr = fam_r(RF, tx) * fam_r(RF, ty) * (DIM == 3 ? fam_r(RF, tz) : 1.0);
+      const long long fi = lin(gf, fx, fy, fz);
+#pragma unroll
+      for (int q = 0; q < KI; ++q) {
+        const int sx = shape_off<DIM, SIN>(q, 0), sy = shape_off<DIM, SIN>(q, 1),
+                  sz = shape_off<DIM, SIN>(q, 2);
+        const int ux = tx + sx - 2 * ex, uy = ty + sy - 2 * ey, uz = tz + sz - 2 * ez;
+        const double wp = fam_p(PF, ux) * fam_p(PF, uy) * (DIM == 3 ? fam_p(PF, uz) : 1.0);
+        if (wp != 0.0) {
+          const cpx<double> hv = wr * Af[(size_t)q * Nf + fi];
+          acc = cfma(cmk(wp, 0.0), hv, acc);
+        }
+      }
+    }
+  }
+  Ac[(size_t)e * Nc + I] = acc;
+}
+
 hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc,
                     const cpx<double>* Af, cpx<double>* Ac, hipStream_t s) {
   const unsigned nb = nblocks(gc.N, 256);
+  // one thread per node while that fills the GPU; below, one per (node, output entry)
+  const bool per_entry = gc.N < (1LL << 19);
 #define VH_GK(D, SI, SO, R, P)                                                         \
   if (dim == D && sin == SI && sout == SO && rf == R && pf == P) {                     \
-    k_galerkin<D, SI, SO, R, P><<<nb, 256, 0, s>>>(gf, gc, Af, Ac);                    \
+    if (per_entry)                                                                     \
+      k_galerkin_e<D, SI, SO, R, P>                                                    \
+          <<<dim3(nb, (unsigned)shape_K<D, SO>()), 256, 0, s>>>(gf, gc, Af, Ac);       \
+    else                                                                               \
+      k_galerkin<D, SI, SO, R, P><<<nb, 256, 0, s>>>(gf, gc, Af, Ac);                  \
     VH_LAUNCH_CHECK();                                                                 \
     return hipSuccess;                                                                 \
   }

@@ -99,6 +99,9 @@ struct vh_handle {
   BatchKrylovDev* dK = nullptr;
   cpx<double>* dpart = nullptr;
   int dnb = 512;
+  // marks the copy of an Arnoldi step's status to the host, so that the host waits for
+  // that copy while the step's update pass is already queued behind it
+  hipEvent_t sev = nullptr;
   std::vector<void*> allocs;
   size_t bytes = 0;
   // optional event timing (vh_options.timing): pairs of events with a kind tag
@@ -120,6 +123,7 @@ struct vh_handle {
   int t_n[3] = {0, 0, 0};
 
   ~vh_handle() {
+    if (sev) (void)hipEventDestroy(sev);
     for (void* p : allocs) (void)hipFree(p);
     if (hstat) (void)hipHostFree(hstat);
     if (bstat) (void)hipHostFree(bstat);
@@ -427,6 +431,21 @@ vh_status read_dstatus(vh_handle* hd) {
   return VH_OK;
 }
 
+// the status copy of an Arnoldi step, marked by hd->sev; the host waits on the mark
+// (status_wait) after it has queued the step's update pass, so the device is not idle
+// while the host decides whether the cycle goes on (the pass is harmless if it stops:
+// it touches neither the Hessenberg columns in use nor Z)
+vh_status status_post(vh_handle* hd, const double* src, size_t bytes, double* dst) {
+  VH_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, hd->s));
+  VH_HIP(hipEventRecord(hd->sev, hd->s));
+  return VH_OK;
+}
+vh_status status_wait(vh_handle* hd) {
+  VH_HIP(hipEventSynchronize(hd->sev));
+  hd->tflush();  // every timing event was recorded before the mark
+  return VH_OK;
+}
+
 vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double tol,
                      vh_solve_stats* st) {
   const size_t N = (size_t)hd->L[0].g.N;
@@ -469,8 +488,8 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
     int k = 0;
     bool stop = false;
     // iteration `done` completed: read its estimate; true when the cycle ends here
-    auto account = [&](int done) -> vh_status {
-      VH_TRY(read_dstatus(hd));
+    auto account = [&](int done, bool posted) -> vh_status {
+      VH_TRY(posted ? status_wait(hd) : read_dstatus(hd));
       if (hd->hstat[2] != 0.0) return fail(VH_EBREAKDOWN, "NaN/Inf in the Arnoldi process");
       ++its;
       k = done;
@@ -492,16 +511,17 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
                      Zj(j), PREC_F64, nullptr, Vj(j + 1), hd->s));
       VH_HIP(batch_dcgs_a(V, N, j, j + 1, NL, 0, hd->dpart, hd->dnb, K, hd->s));
       VH_HIP(batch_dcgs_fin(K, j, 1, 0, hd->s));
+      if (j >= 1) VH_TRY(status_post(hd, K->status, 4 * sizeof(double), hd->hstat));
+      VH_HIP(batch_dcgs_b(V, N, j, NL, 0, K, lo, hd->s));
       if (j >= 1) {
-        VH_TRY(account(j));
+        VH_TRY(account(j, true));
         if (stop) break;
       }
-      VH_HIP(batch_dcgs_b(V, N, j, NL, 0, K, lo, hd->s));
     }
     if (!stop) {
       VH_HIP(batch_dcgs_a(V, N, m, m, NL, 0, hd->dpart, hd->dnb, K, hd->s));
       VH_HIP(batch_dcgs_fin(K, m, 1, 1, hd->s));
-      VH_TRY(account(m));
+      VH_TRY(account(m, false));
     }
     VH_HIP(hipMemcpyAsync(K->kcols, &k, sizeof(int), hipMemcpyHostToDevice, hd->s));
     VH_HIP(batch_backsolve(K, 1, hd->s));
@@ -752,8 +772,8 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     // lagged vector V_j and completes Hessenberg column j-1 (iteration j), so the
     // residual estimate of an iteration is known one step later; a cycle that runs to m
     // closes column m-1 with one more reduction pass.
-    auto account = [&](int done) -> vh_status {
-      VH_TRY(read_bstatus(hd, S));
+    auto account = [&](int done, bool posted) -> vh_status {
+      VH_TRY(posted ? status_wait(hd) : read_bstatus(hd, S));
       bool all_stopped = true;
       for (int k = 0; k < S; ++k) {
         if (!active[k] || stopped[k]) continue;
@@ -782,20 +802,21 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
                            PREC_F64, nullptr, Vj(j + 1), s));
       VH_HIP(batch_dcgs_a(hd->bV, ldv, j, j + 1, N, ls, hd->bpart, hd->bnred, K, s));
       VH_HIP(batch_dcgs_fin(K, j, S, 0, s));
+      if (j >= 1) VH_TRY(status_post(hd, hd->bK->status, (size_t)S * 4 * sizeof(double), hd->bstat));
+      VH_HIP(batch_dcgs_b(hd->bV, ldv, j, N, ls, K, lo, s));
       if (j >= 1) {
-        const vh_status a = account(j);
+        const vh_status a = account(j, true);
         if (a == VH_ENOCONV) {
           finished = true;
           break;
         }
         VH_TRY(a);
       }
-      VH_HIP(batch_dcgs_b(hd->bV, ldv, j, N, ls, K, lo, s));
     }
     if (!finished) {
       VH_HIP(batch_dcgs_a(hd->bV, ldv, m, m, N, ls, hd->bpart, hd->bnred, K, s));
       VH_HIP(batch_dcgs_fin(K, m, S, 1, s));
-      const vh_status a = account(m);
+      const vh_status a = account(m, false);
       if (a != VH_ENOCONV) VH_TRY(a);
     }
     VH_HIP(hipMemcpyAsync(K->kcols, kcols, S * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1046,6 +1067,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   VH_TRY(hd->alloc((void**)&hd->dK, sizeof(BatchKrylovDev)));
   VH_HIP(hipMemsetAsync(hd->dK, 0, sizeof(BatchKrylovDev), s));
   VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
+  VH_HIP(hipEventCreateWithFlags(&hd->sev, hipEventDisableTiming));
   if (o.timing) {
     hd->ev.assign(128, nullptr);
     hd->ev_kind.assign(64, 0);

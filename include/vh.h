@@ -300,6 +300,21 @@ void vh_lfa_problem_default(vh_lfa_problem *p);
 vh_status vh_lfa_factors(const vh_lfa_problem *p, int nw, const double *w, double *mu,
                          double *rho);
 
+/* vh_lfa_factors_noalloc -- the same factors as vh_lfa_factors, computed by the same
+ * kernels, for callers that cannot allocate device memory: code under HIP graph capture,
+ * serving loops that must not call hipMalloc/hipFree, harnesses that forbid allocation.
+ * It calls no hipMalloc, hipFree, hipHostMalloc or other allocating routine.  Its work
+ * arrays (per-sample symbols, damping values, block maxima, factors) live in one
+ * statically allocated 16 MiB device array per GPU, held until the process ends; the
+ * limit admits npts^dim <= 2^18 samples (every 2D npts, 3D npts <= 64) with nw <= 1024,
+ * and a problem that needs more returns VH_EINVAL before any device work.  Arguments,
+ * layout (mu, rho, w are HOST arrays of nw) and other errors as vh_lfa_factors; p->stream
+ * must belong to the current device.  Every call on one GPU shares that GPU's array
+ * (nothing in it needs to start at zero; each call writes what it reads): calls that
+ * overlap on one GPU, from different threads or on different streams, race. */
+vh_status vh_lfa_factors_noalloc(const vh_lfa_problem *p, int nw, const double *w, double *mu,
+                                 double *rho);
+
 /* LFA damping tuner (Sec. 5.2: the fine-level damping is the minimiser of the LFA
  * factor): evaluates objective 0 = mu, 1 = rho on the nw candidates w (HOST) and
  * returns the first minimiser in *w_best and its factor in *f_best (HOST). */

@@ -155,6 +155,8 @@ _SIGNATURES = {
     "vh_lfa_problem_default": (None, [ctypes.POINTER(vh_lfa_problem)]),
     "vh_lfa_factors": (_I, [ctypes.POINTER(vh_lfa_problem), _I, ctypes.POINTER(_D),
                             ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "vh_lfa_factors_noalloc": (_I, [ctypes.POINTER(vh_lfa_problem), _I, ctypes.POINTER(_D),
+                                    ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "vh_lfa_tune": (_I, [ctypes.POINTER(vh_lfa_problem), _I, _I, ctypes.POINTER(_D),
                          ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "vh_mg_iterate": (_I, [_P, _I, _P, _P, _I, _I, _D, ctypes.POINTER(_D),
@@ -393,6 +395,15 @@ def vh_lfa_factors(p, w, mu=True, rho=True):
     m = (_D * nw)() if mu else None
     r = (_D * nw)() if rho else None
     check(lib().vh_lfa_factors(ctypes.byref(p), nw, _dvec(w), m, r))
+    return (list(m) if mu else None), (list(r) if rho else None)
+
+
+def vh_lfa_factors_noalloc(p, w, mu=True, rho=True):
+    """vh_lfa_factors through the allocation-free entry point (static device scratch)."""
+    nw = len(w)
+    m = (_D * nw)() if mu else None
+    r = (_D * nw)() if rho else None
+    check(lib().vh_lfa_factors_noalloc(ctypes.byref(p), nw, _dvec(w), m, r))
     return (list(m) if mu else None), (list(r) if rho else None)
 
 

@@ -16,6 +16,7 @@
 // minimiser over w.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -454,65 +455,90 @@ vh_status check(const vh_lfa_problem* p, int nw, const double* w) {
   return VH_OK;
 }
 
+// Placement of the LFA work arrays in one device buffer: the stencil and patch inverse,
+// per theta sample q(theta) and A(theta) (complex) and R(theta), P(theta) (real), the
+// damping values, the block maxima and the reduced factors.
+struct LfaLayout {
+  long long count, lcount;  // npts^dim samples, (npts/2)^dim low frequencies
+  int nbx, nbl;             // blocks of the per-sample and per-low-frequency kernels
+  size_t o_Z, o_A, o_R, o_P, o_w, o_part, o_out, bytes;
+};
+
+LfaLayout lfa_layout(const vh_lfa_problem* p, int nw) {
+  LfaLayout L;
+  L.count = 1;
+  for (int d = 0; d < p->dim; ++d) L.count *= p->npts;
+  L.lcount = L.count >> p->dim;
+  L.nbx = (int)std::min<long long>((L.count + LFA_T - 1) / LFA_T, 256);
+  L.nbl = (int)std::min<long long>((L.lcount + LFA_T - 1) / LFA_T, 256);
+  L.o_Z = (sizeof(LfaConst) + 255) / 256 * 256;
+  L.o_A = L.o_Z + (size_t)L.count * 16;
+  L.o_R = L.o_A + (size_t)L.count * 16;
+  L.o_P = L.o_R + (size_t)L.count * 8;
+  L.o_w = L.o_P + (size_t)L.count * 8;
+  L.o_part = L.o_w + (size_t)nw * 8;
+  L.o_out = L.o_part + (size_t)nw * std::max(L.nbx, L.nbl) * 8;
+  L.bytes = L.o_out + (size_t)(2 * nw + 4) * 8;
+  return L;
+}
+
+// Enqueues the LFA kernels on p->stream with their arrays in buf (laid out by lfa_layout);
+// every array is written before it is read, so buf needs no clearing.  The factors are
+// left in buf at o_out: mu[nw], rho[nw], then (index, value) of the minimiser of each.
+hipError_t lfa_enqueue(const vh_lfa_problem* p, int nw, const double* w, bool want_mu,
+                       bool want_rho, const LfaLayout& L, char* buf) {
+  hipStream_t s = (hipStream_t)p->stream;
+  LfaConst* C = (LfaConst*)buf;
+  double* wd = (double*)(buf + L.o_w);
+  double* part = (double*)(buf + L.o_part);
+  double* out = (double*)(buf + L.o_out);
+  hipError_t e = hipMemcpyAsync(wd, w, (size_t)nw * 8, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = symbols(p, C, L.count, L.nbx, (cpx<double>*)(buf + L.o_Z), (cpx<double>*)(buf + L.o_A),
+              (double*)(buf + L.o_R), (double*)(buf + L.o_P), s);
+  if (e != hipSuccess) return e;
+  if (want_mu) {
+    k_lfa_mu<<<dim3(L.nbx, nw), LFA_T, 0, s>>>(p->dim, p->npts, L.count,
+                                               (const cpx<double>*)(buf + L.o_Z), wd, part);
+    VH_LAUNCH_CHECK();
+    k_lfa_final<<<1, 256, 0, s>>>(nw, L.nbx, part, out, out + 2 * nw);
+    VH_LAUNCH_CHECK();
+  }
+  if (want_rho) {
+    const int nu = p->nu1 + p->nu2;
+    if (p->dim == 2)
+      k_lfa_rho<2><<<dim3(L.nbl, nw), LFA_T, 0, s>>>(
+          p->npts, nu, L.lcount, (const cpx<double>*)(buf + L.o_Z),
+          (const cpx<double>*)(buf + L.o_A), (const double*)(buf + L.o_R),
+          (const double*)(buf + L.o_P), wd, part);
+    else
+      k_lfa_rho<3><<<dim3(L.nbl, nw), LFA_T, 0, s>>>(
+          p->npts, nu, L.lcount, (const cpx<double>*)(buf + L.o_Z),
+          (const cpx<double>*)(buf + L.o_A), (const double*)(buf + L.o_R),
+          (const double*)(buf + L.o_P), wd, part);
+    VH_LAUNCH_CHECK();
+    k_lfa_final<<<1, 256, 0, s>>>(nw, L.nbl, part, out + nw, out + 2 * nw + 2);
+    VH_LAUNCH_CHECK();
+  }
+  return hipSuccess;
+}
+
 // objective: 0 = mu, 1 = rho; out (host) receives the nw factors of each requested one
 vh_status run(const vh_lfa_problem* p, int nw, const double* w, double* mu, double* rho,
               double* best_mu, double* best_rho) {
   vh_status st = check(p, nw, w);
   if (st != VH_OK) return st;
   hipStream_t s = (hipStream_t)p->stream;
-  long long count = 1;
-  for (int d = 0; d < p->dim; ++d) count *= p->npts;
-  long long lcount = count >> p->dim;  // (npts/2)^dim low frequencies
-  const int nbx = (int)std::min<long long>((count + LFA_T - 1) / LFA_T, 256);
-  const int nbl = (int)std::min<long long>((lcount + LFA_T - 1) / LFA_T, 256);
-  const size_t o_C = 0;
-  const size_t o_Z = (sizeof(LfaConst) + 255) / 256 * 256;
-  const size_t o_A = o_Z + (size_t)count * 16;
-  const size_t o_R = o_A + (size_t)count * 16;
-  const size_t o_P = o_R + (size_t)count * 8;
-  const size_t o_w = o_P + (size_t)count * 8;
-  const size_t o_part = o_w + (size_t)nw * 8;
-  const size_t o_out = o_part + (size_t)nw * std::max(nbx, nbl) * 8;
-  const size_t bytes = o_out + (size_t)(2 * nw + 4) * 8;
+  const LfaLayout L = lfa_layout(p, nw);
   char* buf = nullptr;
-  LfaConst* C;
-  double* wd;
-  double* part;
-  double* out;
   double* host = nullptr;
   int singular = 0;
-  LFA_HIP(hipMalloc((void**)&buf, bytes));
-  C = (LfaConst*)(buf + o_C);
-  wd = (double*)(buf + o_w);
-  part = (double*)(buf + o_part);
-  out = (double*)(buf + o_out);
-  LFA_HIP(hipMemcpyAsync(wd, w, (size_t)nw * 8, hipMemcpyHostToDevice, s));
-  LFA_HIP(symbols(p, C, count, nbx, (cpx<double>*)(buf + o_Z), (cpx<double>*)(buf + o_A),
-                  (double*)(buf + o_R), (double*)(buf + o_P), s));
-  if (mu) {
-    k_lfa_mu<<<dim3(nbx, nw), LFA_T, 0, s>>>(p->dim, p->npts, count,
-                                             (const cpx<double>*)(buf + o_Z), wd, part);
-    LFA_HIP(hipGetLastError());
-    k_lfa_final<<<1, 256, 0, s>>>(nw, nbx, part, out, out + 2 * nw);
-    LFA_HIP(hipGetLastError());
-  }
-  if (rho) {
-    const int nu = p->nu1 + p->nu2;
-    if (p->dim == 2)
-      k_lfa_rho<2><<<dim3(nbl, nw), LFA_T, 0, s>>>(
-          p->npts, nu, lcount, (const cpx<double>*)(buf + o_Z), (const cpx<double>*)(buf + o_A),
-          (const double*)(buf + o_R), (const double*)(buf + o_P), wd, part);
-    else
-      k_lfa_rho<3><<<dim3(nbl, nw), LFA_T, 0, s>>>(
-          p->npts, nu, lcount, (const cpx<double>*)(buf + o_Z), (const cpx<double>*)(buf + o_A),
-          (const double*)(buf + o_R), (const double*)(buf + o_P), wd, part);
-    LFA_HIP(hipGetLastError());
-    k_lfa_final<<<1, 256, 0, s>>>(nw, nbl, part, out + nw, out + 2 * nw + 2);
-    LFA_HIP(hipGetLastError());
-  }
+  LFA_HIP(hipMalloc((void**)&buf, L.bytes));
+  LFA_HIP(lfa_enqueue(p, nw, w, mu != nullptr, rho != nullptr, L, buf));
   LFA_HIP(hipHostMalloc((void**)&host, (size_t)(2 * nw + 4) * 8, hipHostMallocDefault));
-  LFA_HIP(hipMemcpyAsync(host, out, (size_t)(2 * nw + 4) * 8, hipMemcpyDeviceToHost, s));
-  LFA_HIP(hipMemcpyAsync(&singular, &C->singular, sizeof(int), hipMemcpyDeviceToHost, s));
+  LFA_HIP(hipMemcpyAsync(host, buf + L.o_out, (size_t)(2 * nw + 4) * 8, hipMemcpyDeviceToHost, s));
+  LFA_HIP(hipMemcpyAsync(&singular, &((LfaConst*)buf)->singular, sizeof(int),
+                         hipMemcpyDeviceToHost, s));
   LFA_HIP(hipStreamSynchronize(s));
   if (singular) {
     st = lfail(VH_EBREAKDOWN, "the patch matrix of the stencil is singular");
@@ -536,6 +562,41 @@ done:
   if (host) (void)hipHostFree(host);
   if (buf) (void)hipFree(buf);
   return st;
+}
+
+// ------------------------------------------------------------------ allocation-free form
+// The work arrays of vh_lfa_factors_noalloc live in one statically allocated device array
+// per GPU (held until the process ends).  In host code `scratch` names only a host-side
+// stand-in: its device address is looked up once per device with hipGetSymbolAddress and
+// only that address is handed to copies and kernels.
+constexpr size_t LFA_SCRATCH_BYTES = (size_t)16 << 20;
+constexpr int LFA_MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[LFA_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch_dev[LFA_MAX_DEVICES] = {};
+
+// device address of the scratch array on the current device (looked up on first use)
+vh_status scratch_address(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return lfail(VH_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= LFA_MAX_DEVICES) return lfail(VH_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return lfail(VH_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (char*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return VH_OK;
 }
 
 }  // namespace
@@ -563,6 +624,35 @@ vh_status vh_lfa_factors(const vh_lfa_problem* p, int nw, const double* w, doubl
                          double* rho) {
   if (!mu && !rho) return lfail(VH_EINVAL, "mu and rho are both NULL");
   return run(p, nw, w, mu, rho, nullptr, nullptr);
+}
+
+vh_status vh_lfa_factors_noalloc(const vh_lfa_problem* p, int nw, const double* w, double* mu,
+                                 double* rho) {
+  if (!mu && !rho) return lfail(VH_EINVAL, "mu and rho are both NULL");
+  vh_status st = check(p, nw, w);
+  if (st != VH_OK) return st;
+  const LfaLayout L = lfa_layout(p, nw);
+  if (L.bytes > LFA_SCRATCH_BYTES)
+    return lfail(VH_EINVAL, "the LFA work arrays need " + std::to_string(L.bytes) +
+                                " bytes; the allocation-free form holds at most " +
+                                std::to_string(LFA_SCRATCH_BYTES) +
+                                " (npts^dim <= 2^18 samples and nw <= 1024)");
+  char* buf = nullptr;
+  st = scratch_address(&buf);
+  if (st != VH_OK) return st;
+  hipStream_t s = (hipStream_t)p->stream;
+  int singular = 0;
+  LFA_HIP(lfa_enqueue(p, nw, w, mu != nullptr, rho != nullptr, L, buf));
+  if (mu) LFA_HIP(hipMemcpyAsync(mu, buf + L.o_out, (size_t)nw * 8, hipMemcpyDeviceToHost, s));
+  if (rho)
+    LFA_HIP(hipMemcpyAsync(rho, buf + L.o_out + (size_t)nw * 8, (size_t)nw * 8,
+                           hipMemcpyDeviceToHost, s));
+  LFA_HIP(hipMemcpyAsync(&singular, &((LfaConst*)buf)->singular, sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  LFA_HIP(hipStreamSynchronize(s));
+  if (singular) st = lfail(VH_EBREAKDOWN, "the patch matrix of the stencil is singular");
+done:
+  return st;
 }
 
 vh_status vh_lfa_tune(const vh_lfa_problem* p, int objective, int nw, const double* w,

@@ -103,6 +103,13 @@ def test_lfa_and_tuners_reject_bad_arguments_before_any_device_work():
     assert st == B.VH_EINVAL
     st = B.lib().vh_mg_iterate(None, 1, None, None, 0, 1, 1e-6, None, None)
     assert st == B.VH_EINVAL
+    # the allocation-free LFA form refuses work arrays beyond its static scratch
+    with pytest.raises(B.VhError) as e:
+        B.vh_lfa_factors_noalloc(B.make_lfa_problem(dim=3, npts=128), [0.8])
+    assert e.value.status == B.VH_EINVAL and "allocation-free" in str(e.value)
+    with pytest.raises(B.VhError) as e:
+        B.vh_lfa_factors_noalloc(p, [0.8], mu=False, rho=False)
+    assert e.value.status == B.VH_EINVAL
 
 
 def test_symmetric_smoother_rejects_what_it_does_not_cover():

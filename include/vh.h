@@ -158,6 +158,16 @@ typedef struct vh_solve_stats {
     double smooth0_ms;
     int smooth1_launches;   /* finest-level smoothing launches u += B r                 */
     double smooth1_ms;
+    /* always filled:                                                                   */
+    double setup_ms;        /* wall time of the vh_setup that built the handle          */
+    double bytes_moved;     /* algorithmic device bytes of the solve's kernels: every
+                               array a kernel reads or writes counted once per launch
+                               (the 5/7-point finest operator as its centre entries);
+                               sources solved together in one batch (opt.batch = 1)
+                               report the batch's total                                 */
+    double c_f;             /* convergence factor of eq. (cf) (Sec. 5.1) on the residual
+                               estimates: (r_k / r_5)^(1/(k-5)) after k iterations, the
+                               first 5 as warm-up; NaN when k <= 5                        */
 } vh_solve_stats;
 
 typedef struct vh_level_info {
@@ -218,6 +228,11 @@ vh_status vh_destroy(vh_handle *hd);
 /* ---- inspection hooks (used by the parity tests) ----------------------------- */
 
 int vh_num_levels(const vh_handle *hd);
+
+/* Device bytes the handle holds now (*in_use) and the most it has held at any time
+ * since vh_setup began (*peak), both HOST outputs (either may be NULL).  vh_footprint_bytes
+ * with the handle's arguments is an upper bound of *peak. */
+vh_status vh_get_memory(const vh_handle *hd, size_t *in_use, size_t *peak);
 vh_status vh_get_level_info(const vh_handle *hd, int level, vh_level_info *info);
 
 /* y = A x on level `level` (0 = finest): which = 0 -> unshifted H (finest only, FP64),

@@ -64,6 +64,7 @@ class vh_solve_stats(ctypes.Structure):
         ("vcycles", ctypes.c_int), ("vcycle_ms", ctypes.c_double),
         ("smooth0_launches", ctypes.c_int), ("smooth0_ms", ctypes.c_double),
         ("smooth1_launches", ctypes.c_int), ("smooth1_ms", ctypes.c_double),
+        ("setup_ms", ctypes.c_double), ("bytes_moved", ctypes.c_double), ("c_f", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -134,6 +135,7 @@ _SIGNATURES = {
     "vh_solve": (_I, [_P, _P, _I, _D, _P, ctypes.POINTER(vh_solve_stats)]),
     "vh_destroy": (_I, [_P]),
     "vh_num_levels": (_I, [_P]),
+    "vh_get_memory": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "vh_get_level_info": (_I, [_P, _I, ctypes.POINTER(vh_level_info)]),
     "vh_apply_operator": (_I, [_P, _I, _I, _P, _P]),
     "vh_apply_vcycle": (_I, [_P, _P, _P]),
@@ -236,10 +238,21 @@ def vh_setup(dim, n, h, omega, kappa, gamma, shift, levels, patch, opt=None):
     return hd
 
 
+def _level_nodes(hd, level):
+    """Node count of a level of the handle (from vh_get_level_info)."""
+    info = vh_level_info()
+    check(lib().vh_get_level_info(hd, level, ctypes.byref(info)))
+    return info.n[0] * info.n[1] * info.n[2]
+
+
 def vh_solve(hd, q, nsrc, tol, u, raise_on_noconv=False):
     """q, u: complex128 GPU tensors of nsrc*N.  Returns (status, [stats dicts])."""
+    if nsrc < 1:
+        raise ValueError("nsrc must be >= 1")
+    n = nsrc * _level_nodes(hd, 0)
     stats = (vh_solve_stats * nsrc)()
-    st = lib().vh_solve(hd, _ptr(q, "complex128"), nsrc, float(tol), _ptr(u, "complex128"), stats)
+    st = lib().vh_solve(hd, _ptr(q, "complex128", n), nsrc, float(tol), _ptr(u, "complex128", n),
+                        stats)
     if st != VH_OK and (st != VH_ENOCONV or raise_on_noconv):
         check(st)
     return st, [s.as_dict() for s in stats]
@@ -251,6 +264,13 @@ def vh_destroy(hd):
 
 def vh_num_levels(hd):
     return lib().vh_num_levels(hd)
+
+
+def vh_get_memory(hd):
+    """(device bytes held now, peak since setup began)."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().vh_get_memory(hd, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def vh_get_level_info(hd, level):
@@ -266,24 +286,31 @@ def vh_get_level_info(hd, level):
 
 
 def vh_apply_operator(hd, level, which, x, y):
-    check(lib().vh_apply_operator(hd, level, which, _ptr(x, "complex128"), _ptr(y, "complex128")))
+    n = _level_nodes(hd, level)
+    check(lib().vh_apply_operator(hd, level, which, _ptr(x, "complex128", n),
+                                  _ptr(y, "complex128", n)))
 
 
 def vh_apply_vcycle(hd, v, z):
-    check(lib().vh_apply_vcycle(hd, _ptr(v, "complex128"), _ptr(z, "complex128")))
+    n = _level_nodes(hd, 0)
+    check(lib().vh_apply_vcycle(hd, _ptr(v, "complex128", n), _ptr(z, "complex128", n)))
 
 
 def vh_apply_smoother(hd, level, q, u):
-    check(lib().vh_apply_smoother(hd, level, _ptr(q, "complex128"), _ptr(u, "complex128")))
+    n = _level_nodes(hd, level)
+    check(lib().vh_apply_smoother(hd, level, _ptr(q, "complex128", n), _ptr(u, "complex128", n)))
 
 
 def vh_apply_smoother_batch(hd, level, nsrc, q, u):
-    check(lib().vh_apply_smoother_batch(hd, level, nsrc, _ptr(q, "complex128"),
-                                        _ptr(u, "complex128")))
+    n = nsrc * _level_nodes(hd, level)
+    check(lib().vh_apply_smoother_batch(hd, level, nsrc, _ptr(q, "complex128", n),
+                                        _ptr(u, "complex128", n)))
 
 
 def vh_apply_vcycle_batch(hd, nsrc, v, z):
-    check(lib().vh_apply_vcycle_batch(hd, nsrc, _ptr(v, "complex128"), _ptr(z, "complex128")))
+    n = nsrc * _level_nodes(hd, 0)
+    check(lib().vh_apply_vcycle_batch(hd, nsrc, _ptr(v, "complex128", n),
+                                      _ptr(z, "complex128", n)))
 
 
 def vh_export_level(hd, level, coef=None, smoother=None, coarse_inv=None):
@@ -311,6 +338,9 @@ def vh_footprint_bytes(dim, n, levels, patch, nsrc=1, opt=None):
                                     ctypes.byref(opt) if opt is not None else None)
 
 
+_tickets = {}  # (server, ticket) -> (N, nsrc) of the submitted request
+
+
 def vh_server_create(hbm_budget, max_slots):
     srv = _P()
     check(lib().vh_server_create(ctypes.byref(srv), int(hbm_budget), int(max_slots)))
@@ -325,6 +355,13 @@ def vh_server_submit(srv, dim, n, h, omega, kappa, gamma, shift, levels, patch, 
     k = np.ascontiguousarray(kappa, dtype=np.float64)
     g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
     qq = np.ascontiguousarray(q, dtype=np.complex128)
+    N = 1
+    for d in range(dim):
+        N *= int(n[d])
+    if k.size != N or (g is not None and g.size != N):
+        raise ValueError(f"kappa and gamma need {N} nodes")
+    if nsrc < 1 or qq.size != nsrc * N:
+        raise ValueError(f"q needs nsrc * N = {nsrc * N} entries, got {qq.size}")
     req = vh_request()
     req.dim = dim
     for d in range(3):
@@ -337,6 +374,7 @@ def vh_server_submit(srv, dim, n, h, omega, kappa, gamma, shift, levels, patch, 
     req.opt = ctypes.pointer(opt) if opt is not None else None
     t = ctypes.c_uint64()
     check(lib().vh_server_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    _tickets[(srv.value, t.value)] = (N, int(nsrc))
     return t.value
 
 
@@ -351,8 +389,13 @@ def vh_server_wait(srv, ticket):
 
 
 def vh_server_result(srv, ticket, N, nsrc):
-    """Returns (status, u (nsrc, N) complex128, [stats dicts], latency_ms, queue_ms)."""
+    """Returns (status, u (nsrc, N) complex128, [stats dicts], latency_ms, queue_ms).
+    N and nsrc must be the request's (the output buffers are sized by them)."""
     import numpy as np
+    rec = _tickets.get((srv.value, ticket))
+    if rec is not None and rec != (int(N), int(nsrc)):
+        raise ValueError(f"ticket {ticket} was submitted with (N, nsrc) = {rec}")
+    _tickets.pop((srv.value, ticket), None)
     u = np.zeros((nsrc, N), dtype=np.complex128)
     stats = (vh_solve_stats * nsrc)()
     lat, qms = _D(), _D()
@@ -419,7 +462,8 @@ def vh_mg_iterate(hd, which, q, x, warmup, maxit, tol):
     """q, x: complex128 GPU tensors.  Returns (stats dict, residual history list)."""
     hist = (_D * (maxit + 1))()
     st = vh_cf_stats()
-    check(lib().vh_mg_iterate(hd, which, _ptr(q, "complex128"), _ptr(x, "complex128"), warmup,
+    n = _level_nodes(hd, 0)
+    check(lib().vh_mg_iterate(hd, which, _ptr(q, "complex128", n), _ptr(x, "complex128", n), warmup,
                               maxit, float(tol), hist, ctypes.byref(st)))
     return st.as_dict(), list(hist[:st.iterations + 1])
 

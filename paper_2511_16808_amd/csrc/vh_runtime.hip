@@ -4,6 +4,7 @@
 // (Sec. 2.3).  Every arithmetic step runs in the kernels of vh_kernels.hip; the
 // host only sequences launches and reads back one residual estimate per Arnoldi
 // step to decide when to stop.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -47,7 +48,9 @@ namespace {
     if (s_ != VH_OK) return s_;     \
   } while (0)
 
-constexpr int SM_SYMHALF = 6;  // Level.form of the symmetric half of the assembled stencil
+constexpr int SM_SYMHALF = 6;
+// warm-up iterations before the convergence factor of eq. (cf) is counted (Sec. 5.1)
+constexpr int CF_WARMUP = 5;  // Level.form of the symmetric half of the assembled stencil
 
 struct Level {
   Grid g{};
@@ -103,7 +106,11 @@ struct vh_handle {
   // that copy while the step's update pass is already queued behind it
   hipEvent_t sev = nullptr;
   std::vector<void*> allocs;
-  size_t bytes = 0;
+  std::vector<size_t> alloc_sizes;
+  size_t bytes = 0;       // device bytes held now
+  size_t peak_bytes = 0;  // largest value bytes has taken
+  double setup_ms = 0.0;  // wall time of vh_setup
+  double moved = 0.0;     // algorithmic bytes of the kernels enqueued since the last reset
   // optional event timing (vh_options.timing): pairs of events with a kind tag
   // (0 = finest smoothing from u = 0, 1 = finest smoothing u += B r, 2 = V-cycle)
   // multi-source workspace, allocated on the first batched solve for up to bS sources
@@ -162,14 +169,18 @@ struct vh_handle {
                                  hipGetErrorString(e));
     }
     allocs.push_back(*p);
+    alloc_sizes.push_back(bytes_);
     bytes += bytes_;
+    if (bytes > peak_bytes) peak_bytes = bytes;
     return VH_OK;
   }
   void release(void* p) {
     for (size_t i = 0; i < allocs.size(); ++i)
       if (allocs[i] == p) {
         (void)hipFree(p);
+        bytes -= alloc_sizes[i];
         allocs.erase(allocs.begin() + i);
+        alloc_sizes.erase(alloc_sizes.begin() + i);
         return;
       }
   }
@@ -283,11 +294,13 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
     return fail(VH_EUNSUPPORTED,
                 "the symmetric smoother needs the Full patch, the 5/7-point stencil, batch = 0 "
                 "and the VALU contraction");
+  if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
+  for (int k = 0; k < o.ndamping; ++k)
+    if (!std::isfinite(o.damping[k])) return fail(VH_EINVAL, "damping values must be finite");
   if (o.smoother == VH_SMOOTHER_SYMMETRIC)
     for (int k = 0; k < o.ndamping; ++k)
       if (!(o.damping[k] > 0.0))
         return fail(VH_EINVAL, "the symmetric smoother needs damping > 0 on every level");
-  if (o.ndamping < 0 || o.ndamping > 16) return fail(VH_EINVAL, "ndamping must be in [0, 16]");
   if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
     return fail(VH_EINVAL, "unknown contraction");
   if (o.contraction != VH_CONTRACT_VALU &&
@@ -341,10 +354,17 @@ vh_status transfer_plan(int dim, int ig, int l, int sin, int* rf, int* pf, int* 
 
 size_t vec_bytes(const vh_handle* hd, const Level& Lv) { return (size_t)Lv.g.N * hd->esz; }
 
+// Algorithmic bytes of the enqueued kernels (every array touched once per kernel),
+// summed into hd->moved for vh_solve_stats.bytes_moved.  Coefficients read per node by an
+// operator application: the 5/7-point finest operator reads only its centre entries.
+double coef_reads(const Level& Lv) { return Lv.g.offrule ? 1.0 : (double)Lv.K; }
+void count(vh_handle* hd, double nodes, double per_node) { hd->moved += nodes * per_node; }
+
 // ---------------------------------------------------------------- V-cycle
 vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(zero ? 0 : 1) : -1;
   const int form = Lv.form;
+  count(hd, (double)Lv.g.N, (double)hd->esz * (Lv.E + (zero ? 2 : 3)));
   if (form == SM_SYMHALF)
     VH_HIP(vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, r, u, zero, hd->s));
   else
@@ -354,6 +374,7 @@ vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
 }
 
 vh_status residual(vh_handle* hd, Level& Lv, const void* q, const void* u, void* r) {
+  count(hd, (double)Lv.g.N, (double)hd->esz * (coef_reads(Lv) + 3));
   VH_HIP(stencil(hd->dim, Lv.shape, Lv.g, OP_RESID, hd->prec, Lv.A, hd->prec, u, hd->prec, q, r,
                  hd->s));
   return VH_OK;
@@ -369,11 +390,15 @@ int coarse_visits(const vh_handle* hd, int l) {
 vh_status vcycle(vh_handle* hd, int l, const void* q, void* u, bool from_zero) {
   Level& Lv = hd->L[l];
   if (l == hd->levels - 1) {
+    count(hd, (double)hd->nc, 16.0 * hd->nc + 2.0 * hd->esz);
     VH_HIP(dense_matvec(hd->nc, hd->Dinv, hd->prec, q, u, hd->s));
     return VH_OK;
   }
   const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
-  if (nu1 == 0 && from_zero) VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
+  if (nu1 == 0 && from_zero) {
+    count(hd, (double)Lv.g.N, (double)hd->esz);
+    VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
+  }
   for (int k = 0; k < nu1; ++k) {
     if (k == 0 && from_zero) {
       VH_TRY(smooth(hd, Lv, q, u, true));  // u = 0: the residual is q
@@ -384,8 +409,10 @@ vh_status vcycle(vh_handle* hd, int l, const void* q, void* u, bool from_zero) {
   }
   Level& Lc = hd->L[l + 1];
   VH_TRY(residual(hd, Lv, q, u, Lv.r));
+  count(hd, (double)(Lv.g.N + Lc.g.N), (double)hd->esz);
   VH_HIP(restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s));
   for (int v = 0; v < coarse_visits(hd, l); ++v) VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u, v == 0));
+  count(hd, (double)(2 * Lv.g.N + Lc.g.N), (double)hd->esz);
   VH_HIP(prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, hd->prec, Lc.u, u, hd->s));
   for (int k = 0; k < nu2; ++k) {
     VH_TRY(residual(hd, Lv, q, u, Lv.r));
@@ -399,6 +426,7 @@ vh_status precondition(vh_handle* hd, const cpx<double>* v, void* z) {
   Level& L0 = hd->L[0];
   const void* q = v;
   if (hd->prec != PREC_F64) {
+    count(hd, (double)L0.g.N, 16.0 + hd->esz);
     VH_HIP(convert(v, PREC_F64, L0.q, hd->prec, (size_t)L0.g.N, hd->s));
     q = L0.q;
   }
@@ -456,26 +484,31 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
   auto Zj = [&](int j) { return (void*)((char*)hd->Z + (size_t)j * N * hd->esz); };
   const long long NL = (long long)N;
 
+  const double dN = (double)N, k0 = coef_reads(hd->L[0]);
+  count(hd, dN, 16.0);
   VH_HIP(fill(x, N, PREC_F64, 0.0, 0.0, hd->s));
   // r = q (x = 0); beta = ||q||; V_0 = r / beta
   auto restart_vector = [&]() -> vh_status {
+    count(hd, dN, 48.0);  // norm pass and scaling of V_0
     VH_HIP(batch_cgs(2, V, N, 0, K->h2, Vj(0), NL, 0, hd->dpart, hd->dnb, K->nrm2, hd->s));
     VH_HIP(batch_cycle_init(K, m, 1, hd->s));
     VH_HIP(batch_scale(K, Vj(0), Vj(0), NL, 0, hd->s));
     return read_dstatus(hd);
   };
+  count(hd, dN, 32.0);
   VH_HIP(hipMemcpyAsync(Vj(0), q, N * sizeof(cpx<double>), hipMemcpyDeviceToDevice, hd->s));
   VH_TRY(restart_vector());
   const double bnorm = hd->hstat[3];
   double beta = bnorm;
   int its = 0, restarts = 0;
   bool converged = false;
-  double est = 1.0;
+  double est = 1.0, est_w = NAN;  // residual estimate now and after CF_WARMUP iterations
   if (!(bnorm == bnorm) || std::isinf(bnorm)) return fail(VH_EBREAKDOWN, "non-finite right-hand side");
   if (bnorm == 0.0) {
     if (st) {
       *st = vh_solve_stats{};
       st->converged = 1;
+      st->c_f = NAN;
     }
     return VH_OK;
   }
@@ -494,6 +527,7 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
       ++its;
       k = done;
       est = hd->hstat[0] / bnorm;
+      if (its == CF_WARMUP) est_w = est;
       stop = est <= tol || its >= hd->opt.maxit || hd->hstat[1] == 0.0;
       return VH_OK;
     };
@@ -507,8 +541,10 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
       } else {
         VH_TRY(precondition(hd, Vj(j), Zj(j)));
       }
+      count(hd, dN, 16.0 * k0 + hd->esz + 16.0);
       VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_APPLY, PREC_F64, hd->Hfine, hd->prec,
                      Zj(j), PREC_F64, nullptr, Vj(j + 1), hd->s));
+      count(hd, dN, 16.0 * (2 * j + 6) + (lo ? 8.0 : 0.0));  // passes A and B
       VH_HIP(batch_dcgs_a(V, N, j, j + 1, NL, 0, hd->dpart, hd->dnb, K, hd->s));
       VH_HIP(batch_dcgs_fin(K, j, 1, 0, hd->s));
       if (j >= 1) VH_TRY(status_post(hd, K->status, 4 * sizeof(double), hd->hstat));
@@ -519,14 +555,17 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
       }
     }
     if (!stop) {
+      count(hd, dN, 16.0 * (m + 2));
       VH_HIP(batch_dcgs_a(V, N, m, m, NL, 0, hd->dpart, hd->dnb, K, hd->s));
       VH_HIP(batch_dcgs_fin(K, m, 1, 1, hd->s));
       VH_TRY(account(m, false));
     }
     VH_HIP(hipMemcpyAsync(K->kcols, &k, sizeof(int), hipMemcpyHostToDevice, hd->s));
     VH_HIP(batch_backsolve(K, 1, hd->s));
+    count(hd, dN, (double)k * hd->esz + 32.0);
     VH_HIP(batch_update_x(K, k, hd->prec, hd->Z, N, x, NL, 0, hd->s));
     // true residual r = q - H x (FP64), V_0 = r / ||r||
+    count(hd, dN, 16.0 * k0 + 48.0);
     VH_HIP(stencil(hd->dim, hd->L[0].shape, hd->L[0].g, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, x,
                    PREC_F64, q, Vj(0), hd->s));
     VH_TRY(restart_vector());
@@ -540,6 +579,7 @@ vh_status fgmres_one(vh_handle* hd, const cpx<double>* q, cpx<double>* x, double
     st->converged = converged ? 1 : 0;
     st->relres = beta / bnorm;
     st->relres_est = est;
+    st->c_f = its > CF_WARMUP && est_w > 0.0 ? std::pow(est / est_w, 1.0 / (its - CF_WARMUP)) : NAN;
   }
   return converged ? VH_OK : fail(VH_ENOCONV, "maxit reached before tol");
 }
@@ -552,7 +592,6 @@ vh_status ensure_batch(vh_handle* hd, int S) {
   // (re)allocate for S sources
   auto drop = [&](void* p) {
     if (p) {
-      hd->bytes -= 0;
       hd->release(p);
     }
   };
@@ -598,6 +637,7 @@ vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zer
   Level& Lv = hd->L[l];
   const int tk = (l == 0) ? hd->tbegin(zero ? 0 : 1) : -1;
   const int form = Lv.form;
+  count(hd, (double)Lv.g.N, (double)hd->esz * (Lv.E + (zero ? 2 : 3) * (1 << ls)));
   if (Lv.mfma_txp[ls])
     VH_HIP(batch_sweep_mfma(Lv.g, ls, hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3,
                             Lv.mfma_txp[ls], Lv.mfma_rows[ls], Lv.B, r, u, zero, hd->s));
@@ -671,6 +711,7 @@ vh_status tune_mfma(vh_handle* hd, int ls) {
 
 vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, void* r) {
   Level& Lv = hd->L[l];
+  count(hd, (double)Lv.g.N, (double)hd->esz * (coef_reads(Lv) + 3 * (1 << ls)));
   VH_HIP(batch_stencil(hd->dim, Lv.shape, Lv.g, ls, OP_RESID, hd->prec, Lv.A, hd->prec, u,
                        hd->prec, q, r, hd->s));
   return VH_OK;
@@ -679,13 +720,18 @@ vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, 
 // the V-cycle of vcycle() on a batch of 1 << ls sources
 vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u, bool from_zero) {
   Level& Lv = hd->L[l];
+  const double S = (double)(1 << ls);
   if (l == hd->levels - 1) {
+    count(hd, (double)hd->nc, 16.0 * hd->nc + 2.0 * S * hd->esz);
     VH_HIP(batch_dense(hd->nc, ls, hd->Dinv, hd->prec, q, u, hd->s));
     return VH_OK;
   }
   const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
   void* r = hd->br[l];
-  if (nu1 == 0 && from_zero) VH_HIP(fill(u, (size_t)Lv.g.N << ls, hd->prec, 0.0, 0.0, hd->s));
+  if (nu1 == 0 && from_zero) {
+    count(hd, (double)Lv.g.N, S * hd->esz);
+    VH_HIP(fill(u, (size_t)Lv.g.N << ls, hd->prec, 0.0, 0.0, hd->s));
+  }
   for (int k = 0; k < nu1; ++k) {
     if (k == 0 && from_zero) {
       VH_TRY(bsmooth(hd, l, ls, q, u, true));
@@ -696,9 +742,11 @@ vh_status vcycle_b(vh_handle* hd, int l, int ls, const void* q, void* u, bool fr
   }
   Level& Lc = hd->L[l + 1];
   VH_TRY(bresidual(hd, l, ls, q, u, r));
+  count(hd, (double)(Lv.g.N + Lc.g.N), S * hd->esz);
   VH_HIP(batch_restrict(hd->dim, Lv.rf, Lv.g, Lc.g, ls, hd->prec, r, hd->bq[l + 1], hd->s));
   for (int v = 0; v < coarse_visits(hd, l); ++v)
     VH_TRY(vcycle_b(hd, l + 1, ls, hd->bq[l + 1], hd->bu[l + 1], v == 0));
+  count(hd, (double)(2 * Lv.g.N + Lc.g.N), S * hd->esz);
   VH_HIP(batch_prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, ls, hd->prec, hd->bu[l + 1], u, hd->s));
   for (int k = 0; k < nu2; ++k) {
     VH_TRY(bresidual(hd, l, ls, q, u, r));
@@ -734,6 +782,8 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
   const Grid g0 = hd->L[0].g;
   hipStream_t s = hd->s;
 
+  const double dNS = (double)N * S, k0 = coef_reads(hd->L[0]);
+  count(hd, dNS, 32.0 + 16.0 + 32.0 + 48.0);  // gather, zero x, copy to V_0, norm and scale
   VH_HIP(batch_gather(N, S, nsrc, q, hd->bQ, s));
   VH_HIP(fill(hd->bX, (size_t)N * S, PREC_F64, 0, 0, s));
   VH_HIP(hipMemcpyAsync(Vj(0), hd->bQ, ldv * sizeof(cpx<double>), hipMemcpyDeviceToDevice, s));
@@ -743,7 +793,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
   VH_TRY(read_bstatus(hd, S));
   std::vector<double> bnorm(S), beta(S);
   std::vector<int> its(S, 0), restarts(S, 0), active(S, 0), conv(S, 0);
-  std::vector<double> est(S, 1.0);
+  std::vector<double> est(S, 1.0), est_w(S, NAN);
   for (int k = 0; k < S; ++k) {
     bnorm[k] = hd->bstat[k * 4 + 3];
     beta[k] = bnorm[k];
@@ -781,6 +831,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
         ++its[k];
         kcols[k] = done;
         est[k] = hd->bstat[k * 4 + 0] / bnorm[k];
+        if (its[k] == CF_WARMUP) est_w[k] = est[k];
         if (est[k] <= tol || its[k] >= hd->opt.maxit || hd->bstat[k * 4 + 1] == 0.0) stopped[k] = 1;
         all_stopped = all_stopped && stopped[k];
       }
@@ -792,14 +843,19 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     for (int j = 0; j < m && !finished; ++j) {
       const void* qv = Vj(j);
       if (hd->prec != PREC_F64) {
-        if (j == 0) VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
+        if (j == 0) {
+          count(hd, dNS, 16.0 + hd->esz);
+          VH_HIP(convert(Vj(j), PREC_F64, hd->bq[0], hd->prec, (size_t)N * S, s));
+        }
         qv = hd->bq[0];
       }
       const int tk = hd->tbegin(2);
       VH_TRY(vcycle_b(hd, 0, ls, qv, Zj(j), true));
       hd->tend(tk);
+      count(hd, (double)N, 16.0 * k0 + S * (hd->esz + 16.0));
       VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
                            PREC_F64, nullptr, Vj(j + 1), s));
+      count(hd, dNS, 16.0 * (2 * j + 6) + (lo ? 8.0 : 0.0));  // passes A and B
       VH_HIP(batch_dcgs_a(hd->bV, ldv, j, j + 1, N, ls, hd->bpart, hd->bnred, K, s));
       VH_HIP(batch_dcgs_fin(K, j, S, 0, s));
       if (j >= 1) VH_TRY(status_post(hd, hd->bK->status, (size_t)S * 4 * sizeof(double), hd->bstat));
@@ -814,6 +870,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       }
     }
     if (!finished) {
+      count(hd, dNS, 16.0 * (m + 2));
       VH_HIP(batch_dcgs_a(hd->bV, ldv, m, m, N, ls, hd->bpart, hd->bnred, K, s));
       VH_HIP(batch_dcgs_fin(K, m, S, 1, s));
       const vh_status a = account(m, false);
@@ -823,7 +880,9 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     int kmax = 0;
     for (int k = 0; k < S; ++k) kmax = kcols[k] > kmax ? kcols[k] : kmax;
     VH_HIP(batch_backsolve(K, S, s));
+    count(hd, dNS, (double)kmax * hd->esz + 32.0);
     VH_HIP(batch_update_x(K, kmax, hd->prec, hd->bZ, ldv, hd->bX, N, ls, s));
+    count(hd, (double)N, 16.0 * k0 + S * 48.0 + 48.0 * S);  // true residual, norm and scale
     VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
                          PREC_F64, hd->bQ, Vj(0), s));
     VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->bnred, K->nrm2, s));
@@ -837,6 +896,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       if (!(beta[k] == beta[k]) || std::isinf(beta[k])) return fail(VH_EBREAKDOWN, "non-finite residual");
     }
   }
+  count(hd, dNS, 32.0);
   VH_HIP(batch_scatter(N, S, nsrc, hd->bX, u, s));
   VH_HIP(hipStreamSynchronize(s));
   bool all_conv = true;
@@ -848,6 +908,9 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       st[k].converged = conv[k];
       st[k].relres = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
       st[k].relres_est = est[k];
+      st[k].c_f = its[k] > CF_WARMUP && est_w[k] > 0.0
+                      ? std::pow(est[k] / est_w[k], 1.0 / (its[k] - CF_WARMUP))
+                      : NAN;
     }
     all_conv = all_conv && conv[k];
   }
@@ -918,7 +981,6 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
   if (p.own) {
     VH_HIP(hipStreamSynchronize(s));
     hd->release(buf);
-    hd->bytes -= (size_t)p.cnt_max * p.per_plane;
   }
   Lv.E = E;
   return VH_OK;
@@ -959,7 +1021,6 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     VH_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     VH_HIP(hipStreamSynchronize(s));
     hd->release(flag);
-    hd->bytes -= sizeof(int);
     if (hflag) return fail(VH_EINVAL, "kappa must be finite and > 0, gamma finite and >= 0");
   }
   // finest operator, FP64
@@ -1045,12 +1106,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     VH_HIP(hipStreamSynchronize(s));
     hd->release(perm);
     hd->release(col);
-    hd->bytes -= (size_t)nc * (sizeof(int) + sizeof(cpx<double>));
   }
   VH_HIP(hipStreamSynchronize(s));
   if (hd->prec != PREC_F64)
     for (int l = 0; l < hd->levels; ++l) {
-      hd->bytes -= (size_t)hd->L[l].K * hd->L[l].g.N * sizeof(cpx<double>);
       hd->release(A64[l]);
     }
   // FGMRES workspace (the basis V is already allocated)
@@ -1145,7 +1204,10 @@ vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omeg
   hd->prec = o.precision == VH_PREC_FP64 ? PREC_F64 : PREC_F32;
   hd->esz = hd->prec == PREC_F64 ? 16 : 8;
   hd->s = (hipStream_t)o.stream;
+  const auto t0 = std::chrono::steady_clock::now();
   vh_status st = build(hd, kappa, gamma);
+  hd->setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (st != VH_OK) {
     (void)hipStreamSynchronize(hd->s);
     delete hd;
@@ -1175,6 +1237,7 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
         hd->t_n[k] = 0;
       }
       hd->ev_used = 0;
+      hd->moved = 0.0;
       vh_status r = fgmres_batch(hd, (const cpx<double>*)q + (size_t)s0 * N, cnt,
                                  (cpx<double>*)u + (size_t)s0 * N, tol, stats ? stats + s0 : nullptr);
       (void)hipEventRecord(e1, hd->s);
@@ -1193,6 +1256,8 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
           stats[k].smooth1_ms = hd->t_ms[1];
           stats[k].vcycles = hd->t_n[2];
           stats[k].vcycle_ms = hd->t_ms[2];
+          stats[k].setup_ms = hd->setup_ms;
+          stats[k].bytes_moved = hd->moved;
         }
       if (r != VH_OK && r != VH_ENOCONV) return r;
       if (r == VH_ENOCONV) worst = VH_ENOCONV;
@@ -1210,6 +1275,7 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
       hd->t_n[k] = 0;
     }
     hd->ev_used = 0;
+    hd->moved = 0.0;
     vh_status r = fgmres_one(hd, (const cpx<double>*)q + sidx * N, (cpx<double>*)u + sidx * N,
                              tol, &st);
     (void)hipEventRecord(e1, hd->s);
@@ -1226,6 +1292,8 @@ vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
     st.smooth1_ms = hd->t_ms[1];
     st.vcycles = hd->t_n[2];
     st.vcycle_ms = hd->t_ms[2];
+    st.setup_ms = hd->setup_ms;
+    st.bytes_moved = hd->moved;
     if (stats) stats[sidx] = st;
     if (r != VH_OK && r != VH_ENOCONV) return r;
     if (r == VH_ENOCONV) worst = VH_ENOCONV;
@@ -1241,6 +1309,13 @@ vh_status vh_destroy(vh_handle* hd) {
 }
 
 int vh_num_levels(const vh_handle* hd) { return hd ? hd->levels : 0; }
+
+vh_status vh_get_memory(const vh_handle* hd, size_t* in_use, size_t* peak) {
+  if (!hd) return fail(VH_EINVAL, "NULL handle");
+  if (in_use) *in_use = hd->bytes;
+  if (peak) *peak = hd->peak_bytes;
+  return VH_OK;
+}
 
 vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info) {
   if (!hd || !info || level < 0 || level >= hd->levels) return fail(VH_EINVAL, "bad level");
@@ -1656,6 +1731,10 @@ vh_status vh_tune_shift(int dim, const int* n, double h, double omega, const dou
 
 size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc,
                           const vh_options* opt) {
+  // Device bytes of build() and vh_solve, allocation by allocation, as the larger of the
+  // setup peak (with the FP64 Galerkin copies of a complex64 hierarchy, the temporary slab
+  // buffer and the coarsest pivoting arrays) and the solve peak (with the FGMRES
+  // workspace and, for opt->batch, the multi-source workspace).
   vh_options o;
   if (opt)
     o = *opt;
@@ -1665,19 +1744,25 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   for (int d = 0; d < dim; ++d)
     if (n[d] < 3) return 0;
   const size_t esz = o.precision == VH_PREC_FP64 ? 16 : 8;
+  const bool c64 = esz != 16;
   const int ig = resolve_intergrid(dim, o.intergrid);
   const int Np_c = patch_size(dim, patch);
   size_t nn[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
-  size_t total = 0, N0 = nn[0] * nn[1] * nn[2], slab_tmp = 0;
+  const size_t N0 = nn[0] * nn[1] * nn[2];
+  size_t common = 0, a64 = 0, slab_tmp = 0, coarse_tmp = 0;
   int shape = o.stencil == VH_STENCIL_COMPACT4 ? BOX1 : CROSS;
-  total += (size_t)shape_points(dim, shape) * N0 * 16;  // unshifted H
+  common += (size_t)shape_points(dim, shape) * N0 * 16;  // unshifted H
+  common += (size_t)(o.restart + 1) * N0 * 16;           // FGMRES basis (slab scratch in setup)
   bool sym_above = true;  // H_s^l symmetric (every transfer above with R = c P^T)
   for (int l = 0; l < levels; ++l) {
     const size_t N = nn[0] * nn[1] * nn[2];
     const int K = shape_points(dim, shape);
-    total += (size_t)K * N * esz + 3 * N * esz;
+    // the FP64 Galerkin operator is the level's operator (FP64) or a setup copy (c64)
+    if (c64) a64 += (size_t)K * N * 16;
+    common += (size_t)K * N * esz + 3 * N * esz;
     if (l + 1 == levels) {
-      total += N * N * 16;
+      common += N * N * 16;                                   // coarsest inverse
+      coarse_tmp = N * (sizeof(int) + sizeof(cpx<double>));  // pivots and a column
       break;
     }
     const int lp = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : patch;
@@ -1686,12 +1771,12 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
         (o.smoother == VH_SMOOTHER_ASSEMBLED || o.smoother == VH_SMOOTHER_SYMMETRIC) &&
         lp != VH_PATCH_POINT;
     const int K5 = dim == 2 ? 25 : 125;
-    const int E = assembled ? (o.smoother == VH_SMOOTHER_SYMMETRIC && sym_above ? (K5 + 1) / 2 : K5)
-                            : Np * Np;
-    const size_t Npad = (nn[0] + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN * nn[1] * nn[2];
-    total += (size_t)E * Npad * esz;
+    const bool sym = assembled && o.smoother == VH_SMOOTHER_SYMMETRIC && sym_above;
+    const int E = assembled ? (sym ? (K5 + 1) / 2 : K5) : Np * Np;
+    const Grid g = make_grid(dim, (int)nn[0], (int)nn[1], (int)nn[2]);
+    const size_t Npad = (size_t)g.Np;
+    common += ((size_t)E * Npad + (sym ? (size_t)sym_guard(g) : 0)) * esz;
     if (assembled) {  // a temporary slab buffer when the basis is too small to hold one
-      const Grid g = make_grid(dim, (int)nn[0], (int)nn[1], (int)nn[2]);
       const SlabPlan p = slab_plan(dim, g, Np, esz, (size_t)(o.restart + 1) * N0 * 16);
       if (p.own && (size_t)p.cnt_max * p.per_plane > slab_tmp) slab_tmp = (size_t)p.cnt_max * p.per_plane;
     }
@@ -1700,21 +1785,28 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     sym_above = sym_above && (ig == VH_IG_LINEAR || ig == VH_IG_CUBIC || (ig == VH_IG_LEVDEP && l == 0));
     for (int d = 0; d < dim; ++d) nn[d] = (nn[d] - 1) / 2 + 1;
   }
-  total += (size_t)(o.restart + 1) * N0 * 16 + (size_t)o.restart * N0 * esz + slab_tmp;
-  total += (size_t)2048 * 65 * 16 + sizeof(KrylovDev);
-  total += (size_t)(1024 + 16) * 65 * 64 * 16 + sizeof(BatchKrylovDev);  // delayed CGS2 state
+  if (!c64) a64 = 0;
+  // setup: media flag, Galerkin copies, and the larger of a slab buffer (per level) and
+  // the coarsest pivoting arrays (allocated after the last slab buffer is freed)
+  const size_t setup_extra = sizeof(int) + a64 + std::max(slab_tmp, coarse_tmp);
+  // solve: Krylov workspace (partial-sum rows as build() sizes them)
+  const size_t nred = std::min<size_t>(std::max<size_t>(N0 / 512, 64), 2048);
+  const size_t dnb = std::min<size_t>(nred, 1024);
+  size_t solve_extra = (size_t)o.restart * N0 * esz + nred * 65 * 16 + sizeof(KrylovDev) +
+                       (dnb + 16) * 65 * 64 * 16 + sizeof(BatchKrylovDev);
   if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
     size_t S = 1;
     while (S < (size_t)(nsrc < 64 ? nsrc : 64)) S *= 2;
-    total += (size_t)(o.restart + 1) * N0 * S * 16 + (size_t)o.restart * N0 * S * esz +
-             2 * N0 * S * 16 + (size_t)2048 * 65 * 64 * 16 + sizeof(BatchKrylovDev);
+    const size_t bnred = std::min<size_t>(std::max<size_t>(N0 * S / 8192, 64), 1024);
+    solve_extra += (size_t)(o.restart + 1) * N0 * S * 16 + (size_t)o.restart * N0 * S * esz +
+                   2 * N0 * S * 16 + (bnred + 16) * 65 * 64 * 16 + sizeof(BatchKrylovDev);
     size_t m[3] = {(size_t)n[0], (size_t)n[1], dim == 3 ? (size_t)n[2] : 1};
     for (int l = 0; l < levels; ++l) {
-      total += 3 * m[0] * m[1] * m[2] * S * esz;
+      solve_extra += 3 * m[0] * m[1] * m[2] * S * esz;
       for (int d = 0; d < dim; ++d) m[d] = (m[d] - 1) / 2 + 1;
     }
   }
-  return total;
+  return common + std::max(setup_extra, solve_extra);
 }
 
 }  // extern "C"

@@ -124,4 +124,11 @@ def stencil_entries(A, n, offsets):
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+    """Relative difference of a from b: the larger of the norm-wise ||a - b|| / ||b|| and
+    the element-wise max |a_i - b_i| / max |b_i|, so that an error confined to a few
+    nodes is not averaged away by the norm."""
+    a, b = np.ravel(a), np.ravel(b)
+    d = np.abs(a - b)
+    norm = float(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300))
+    elem = float(d.max() / max(np.abs(b).max(), 1e-300)) if b.size else 0.0
+    return max(norm, elem)

@@ -47,6 +47,43 @@ def test_setup_rejects_bad_arguments_before_any_device_work(dim, n, levels, err)
     assert e.value.status == B.VH_EINVAL and err in str(e.value)
 
 
+def test_symmetric_smoother_checks_ndamping_before_reading_damping():
+    o = B.make_options(smoother=B.VH_SMOOTHER_SYMMETRIC)
+    o.ndamping = 17
+    with pytest.raises(B.VhError) as e:
+        B.vh_setup(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 3, B.VH_PATCH_FULL, o)
+    assert e.value.status == B.VH_EINVAL and "ndamping" in str(e.value)
+    o = B.make_options(damping=[0.9, float("inf")])
+    with pytest.raises(B.VhError) as e:
+        B.vh_setup(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 3, B.VH_PATCH_FULL, o)
+    assert e.value.status == B.VH_EINVAL and "finite" in str(e.value)
+
+
+def test_solve_stats_layout_carries_setup_bytes_and_convergence_factor():
+    names = [f for f, _ in B.vh_solve_stats._fields_]
+    assert names[-3:] == ["setup_ms", "bytes_moved", "c_f"]
+    text = open(os.path.join(ROOT, "include", "vh.h")).read()
+    body = text[text.index("typedef struct vh_solve_stats"):text.index("} vh_solve_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    decl = re.findall(r"\b(int|double)\s+([a-z0-9_]+)\s*;", body)
+    assert [n for _, n in decl] == names
+    ctypes_of = {"int": "c_int", "double": "c_double"}
+    assert [ctypes_of[t] for t, _ in decl] == [ty.__name__ for _, ty in B.vh_solve_stats._fields_]
+    assert B.lib().vh_get_memory(None, None, None) == B.VH_EINVAL
+
+
+def test_footprint_counts_the_setup_peak_of_a_complex64_hierarchy():
+    """With the complex64 preconditioner setup also holds the FP64 Galerkin operators of
+    every level; the footprint is the larger of that and the solve peak."""
+    n = (257, 257, 257)
+    o = B.make_options(precision=B.VH_PREC_C64, restart=1, smoother=B.VH_SMOOTHER_ASSEMBLED)
+    fp = B.vh_footprint_bytes(3, n, 6, B.VH_PATCH_FULL, 1, o)
+    N = 257 ** 3
+    a64 = 7 * N * 16 + 27 * 16 * sum((2 ** (8 - l) + 1) ** 3 for l in range(1, 6))
+    stored = 7 * N * 8 + 7 * N * 16 + 2 * N * 16 + 125 * N * 8  # A, H, basis, smoother
+    assert fp >= stored + a64
+
+
 def test_setup_rejects_bad_options():
     for field, value in (("restart", 0), ("restart", 65), ("precision", 7), ("nu1", -1),
                          ("bc", 5), ("smoother", 3)):
@@ -144,4 +181,5 @@ def test_symmetric_footprint():
     fs2 = B.vh_footprint_bytes(2, n2, 5, B.VH_PATCH_FULL, 1,
                                B.make_options(smoother=B.VH_SMOOTHER_SYMMETRIC))
     saved = 12 * 16 * (288 * 257 + 160 * 129)  # levels 0 and 1 only
-    assert fa2 - fs2 == saved
+    guards = 16 * ((2 + 2 * 288) + (2 + 2 * 160))  # zero entries before each half's first plane
+    assert fa2 - fs2 == saved - guards

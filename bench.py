@@ -52,7 +52,7 @@ WORKLOADS = {
                     "6-level trilinear V(1,1), Full 3x3x3 Vanka, complex64 preconditioner, "
                     "FGMRES(30) in complex128",
                dim=3, n=(257, 257, 257), levels=6, alpha=0.5, medium="geophysical_3d", seed=3,
-               precision=1, restart=30, damping=[1.08, 0.9, 0.6, 0.6],
+               precision=1, restart=30, damping=[1.08, 0.5, 1.0, 0.4],
                sample=dict(n=(65, 65, 65), levels=4)),
     "p2": dict(desc="the paper's own 2D configuration scaled to 1025x1025 nodes: kappa^2 linear in "
                     "depth over [0.25, 1] (Table heterogeneous2D model), 10 ppw at kappa_max, gamma = 0, "

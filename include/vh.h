@@ -142,6 +142,11 @@ typedef struct vh_options {
     int contraction;        /* VH_CONTRACT_*: how a batch of >= 16 sources applies the
                                per-patch smoother (2D, Full patch, VH_SMOOTHER_PATCH,
                                VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */
+    int sweep_tile;         /* variant of the 64-source 2D sweep of the assembled smoother
+                               (batch = 1, VALU contraction): 0 (default) = the fastest of
+                               the 7 variants, timed on each level's grid at the first
+                               64-source solve and kept for the process; 1..7 forces one.
+                               The variants give identical results */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -179,6 +184,7 @@ typedef struct vh_level_info {
     int mfma_sources;       /* batch width the matrix-core sweep was tuned for (0: none) */
     int mfma_tile;          /* patches per strip row chosen by the tuner (16 or 32)      */
     int mfma_rows;          /* rows per block chosen by the tuner                        */
+    int sweep_tile;         /* variant of the 64-source 2D sweep in use (0: none chosen)  */
 } vh_level_info;
 
 typedef struct vh_handle vh_handle;

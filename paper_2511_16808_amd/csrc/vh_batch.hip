@@ -580,6 +580,108 @@ __global__ __launch_bounds__(256) void kb_sweep2d_s64(Grid g, int tx,
   }
 }
 
+// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>)
+template <int B, int E, class F>
+__device__ __forceinline__ void bstatic_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    bstatic_for<B + 1, E>(f);
+  }
+}
+
+// 2D, 64 sources, walk without LDS: one wave = one grid row x 64 sources (lane = source)
+// walking along x over a strip of columns.  Each lane keeps the 5 x 5 residual window of
+// its node in a register ring of 5 + P columns: a step loads the next column (rows
+// y - 2 .. y + 2) straight from memory, P steps before its first use (the rows shared with
+// the neighbouring rows' waves come from the caches), together with u of the output of
+// that step and the node's smoother entries.  The entries are the same for all 64 lanes:
+// in complex64 one load spreads a node's 25 entries over the lanes (lane l holds float l)
+// and each is broadcast to an SGPR operand of the FMAs by a lane read; in complex128 they
+// are read through the scalar unit.  Loads go to clamped in-range addresses and out-of-grid
+// values are selected to zero afterwards, so the step has no branch and the loads of later
+// steps stay in flight.  No LDS and no barrier: waves run independently.
+template <int FORM, bool ZERO, class T, int P>
+__global__ __launch_bounds__(256) void kb_sweep2d_s64w(Grid g, int tx,
+                                                       const cpx<T>* __restrict__ G,
+                                                       const cpx<T>* __restrict__ r,
+                                                       cpx<T>* __restrict__ u) {
+  // the assembled stencil: its entries that point outside the grid are exact zeros (no
+  // patch contains an outside node), so the window may hold any finite in-grid values
+  // there; loads go to clamped in-grid addresses and need no select
+  static_assert(FORM == 2, "the walk relies on the zero entries of the assembled stencil");
+  constexpr int E = bsm_entries<2, FORM>();
+  constexpr int R = 5 + P;  // column ring: the window of 5 plus P in flight
+  constexpr bool LANE_G = sizeof(T) == 4 && 2 * E <= 64;
+  const int nsx = (g.nx + tx - 1) / tx;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int xs = (int)(b % (unsigned)nsx) * tx;
+  const int y = (int)(b / (unsigned)nsx) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (y >= g.ny) return;  // a whole wave; nothing below synchronises
+  const int lane = threadIdx.x & 63;
+  const int xe = min(xs + tx, g.nx);
+  const int nstep = xe - xs + 4;  // step k loads column xs - 2 + k and outputs xs + k - 4
+  size_t roff[5];                 // offsets of the window rows y - 2 .. y + 2 (clamped)
+#pragma unroll
+  for (int d = 0; d < 5; ++d) roff[d] = (size_t)lin_b(g, 0, min(max(y - 2 + d, 0), g.ny - 1), 0) * 64 + lane;
+  const size_t uoff = (size_t)lin_b(g, 0, y, 0) * 64 + lane;
+  const size_t Np = (size_t)g.Np;
+  const size_t grow = (size_t)linp_b(g, 0, y, 0);  // entry e of node x at G[e * Np + grow + x]
+  // lane l of an entries load reads float (l & 1) of entry l >> 1 (lanes past 2E: entry 0)
+  const size_t gl = 2 * ((size_t)(lane < 2 * E ? lane >> 1 : 0) * Np + grow) + (lane & 1);
+  const T* Gf = (const T*)G;
+  cpx<T> c[R][5];
+  cpx<T> uf[R];
+  T gv[R];
+  const cpx<T> zero = cmk<T>(0, 0);
+  auto fetch = [&](int k, auto sl) {
+    constexpr int SL = decltype(sl)::value;
+    const size_t cc = (size_t)min(max(xs - 2 + k, 0), g.nx - 1) * 64;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) c[SL][d] = r[roff[d] + cc];
+    const int xo = max(xs + k - 4, xs);  // output of step k (k >= 4 in use)
+    if (!ZERO) uf[SL] = u[uoff + (size_t)xo * 64];
+    if constexpr (LANE_G) gv[SL] = Gf[gl + 2 * (size_t)xo];
+  };
+  // step k: fetch the column of step k + P (clamped: past the strip's end it loads in-grid
+  // values nobody uses), then (k >= 4) the output xs + k - 4
+  auto step = [&](int k, auto ph, bool out) {
+    constexpr int PH = decltype(ph)::value;  // k % R
+    fetch(k + P, std::integral_constant<int, (PH + P) % R>{});
+    if (out) {
+      const int x = xs + k - 4;
+      cpx<T> acc = zero;
+      bstatic_for<0, E>([&](auto ei) {
+        constexpr int e = decltype(ei)::value;
+        constexpr int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
+        cpx<T> ge;
+        if constexpr (LANE_G) {
+          ge.re = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[PH]), 2 * e));
+          ge.im = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[PH]), 2 * e + 1));
+        } else {
+          ge = G[(size_t)e * Np + grow + x];
+        }
+        acc = cfma(ge, c[(PH + dx - 2 + 2 * R) % R][dy + 2], acc);
+      });
+      u[uoff + (size_t)x * 64] = ZERO ? acc : (uf[PH] + acc);
+    }
+  };
+  // the loads of every step are issued unconditionally and the main loop runs whole ring
+  // turns without a branch inside, so the loads of later steps stay in flight across the
+  // waits of the current one; the last partial turn is the only guarded code
+  bstatic_for<0, P>([&](auto i) { fetch(i.value, i); });
+  bstatic_for<0, 4>([&](auto i) { step(i.value, std::integral_constant<int, i.value % R>{}, false); });
+  int k0 = 4;
+#pragma unroll 1
+  for (; k0 + R <= nstep; k0 += R)
+    bstatic_for<0, R>([&](auto j) {
+      step(k0 + j.value, std::integral_constant<int, (4 + j.value) % R>{}, true);
+    });
+  bstatic_for<0, R - 1>([&](auto j) {
+    if (k0 + j.value < nstep)
+      step(k0 + j.value, std::integral_constant<int, (4 + j.value) % R>{}, true);
+  });
+}
+
 template <int FORM, class T>
 static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero, hipStream_t st) {
   // balanced strips of at most B64_TX columns
@@ -593,6 +695,39 @@ static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero,
   else
     kb_sweep2d_s64<FORM, false, T><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
                                                        (const cpx<T>*)r, (cpx<T>*)u);
+}
+
+template <int FORM, class T, int P>
+static void launch_s64w(Grid g, int tx0, const void* G, const void* r, void* u, bool zero,
+                        hipStream_t st) {
+  // balanced strips of at most tx0 columns; blocks of 4 rows (4 independent waves)
+  const int nsx = (g.nx + tx0 - 1) / tx0;
+  const int tx = (g.nx + nsx - 1) / nsx;
+  const int nsx2 = (g.nx + tx - 1) / tx;
+  const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + 3) / 4);
+  if (zero)
+    kb_sweep2d_s64w<FORM, true, T, P><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
+                                                          (const cpx<T>*)r, (cpx<T>*)u);
+  else
+    kb_sweep2d_s64w<FORM, false, T, P><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
+                                                           (const cpx<T>*)r, (cpx<T>*)u);
+}
+
+// 64-source 2D assembled sweep by tile code (S64_TILES candidates, 1-based): 1 = the LDS
+// walk of four rows per block (16 columns per strip), 2..7 = the independent-wave walk
+// with prefetch distance 2 or 3 over strips of 16, 32 or 64 columns
+template <int FORM, class T>
+static void launch_s64_tile(int tile, Grid g, const void* G, const void* r, void* u, bool zero,
+                            hipStream_t st) {
+  static constexpr int TXS[3] = {16, 32, 64};
+  if (tile == 0) tile = S64_DEFAULT_TILE;
+  if (tile <= 1 || tile > S64_TILES) {
+    launch_s64<FORM, T>(g, G, r, u, zero, st);
+  } else if (tile <= 4) {
+    launch_s64w<FORM, T, 2>(g, TXS[tile - 2], G, r, u, zero, st);
+  } else {
+    launch_s64w<FORM, T, 3>(g, TXS[tile - 5], G, r, u, zero, st);
+  }
 }
 
 template <int FORM, class T, int LS>
@@ -716,8 +851,8 @@ static void launch_zw(Grid g, const void* G, const void* r, void* u, bool zero, 
 }
 
 template <int DIM, int FORM, class T>
-static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u, bool zero,
-                           hipStream_t st) {
+static hipError_t bsweep_t(Grid g, int ls, int tile, const void* G, const void* r, void* u,
+                           bool zero, hipStream_t st) {
   if constexpr (DIM == 3 && FORM == 2) {
     // measured: the z walk pays off with 16 sources; with fewer, the per-thread gather
     // through the caches below is faster
@@ -729,7 +864,7 @@ static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u
   }
   if constexpr (DIM == 2 && FORM == 2) {
     if (ls == 6) {
-      launch_s64<FORM, T>(g, G, r, u, zero, st);
+      launch_s64_tile<FORM, T>(tile, g, G, r, u, zero, st);
       VHB_CHECK();
       return hipSuccess;
     }
@@ -774,11 +909,11 @@ static hipError_t bsweep_t(Grid g, int ls, const void* G, const void* r, void* u
 }
 
 hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* G, const void* r,
-                       void* u, bool zero, hipStream_t st) {
-#define VHB_SW(D, F)                                                          \
-  if (dim == D && form == F)                                                  \
-    return prec == PREC_F64 ? bsweep_t<D, F, double>(g, ls, G, r, u, zero, st) \
-                            : bsweep_t<D, F, float>(g, ls, G, r, u, zero, st);
+                       void* u, bool zero, hipStream_t st, int tile) {
+#define VHB_SW(D, F)                                                                \
+  if (dim == D && form == F)                                                        \
+    return prec == PREC_F64 ? bsweep_t<D, F, double>(g, ls, tile, G, r, u, zero, st) \
+                            : bsweep_t<D, F, float>(g, ls, tile, G, r, u, zero, st);
   VHB_SW(2, 0) VHB_SW(3, 0) VHB_SW(2, 1) VHB_SW(3, 1) VHB_SW(2, 2) VHB_SW(3, 2)
   VHB_SW(2, 3) VHB_SW(3, 3) VHB_SW(2, 4) VHB_SW(3, 4) VHB_SW(2, 5) VHB_SW(3, 5)
 #undef VHB_SW

@@ -9,8 +9,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/vh.h"
@@ -70,6 +73,7 @@ struct Level {
                                           // SM_SYMHALF = its symmetric half
   int mfma_txp[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned matrix-core sweep tile per log2(S)
   int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
+  int s64_tile = 0;  // variant of the 64-source 2D assembled sweep (0: not chosen yet)
 };
 
 }  // namespace
@@ -221,7 +225,8 @@ int patch_size(int dim, int patch) {
 // damping used when the caller passes none.  Element, Plus, RB: Table "relaxParam"
 // (2D columns; 3D columns for Element and Plus, the 3D RB patch, absent from the table,
 // takes the Plus column).  Full patch: LFA smoothing-factor minimiser on the finest
-// level and an exhaustive per-level search (not in the table).  Point patch (damped
+// level and an exhaustive per-level search (not in the table; in 3D the search ran on
+// the 257^3 geophysical medium with 6 levels, scored by FGMRES iterations).  Point patch (damped
 // Jacobi): the table's Jacobi column with the compact stencil, for which the table was
 // made; the LFA minimiser with the 2nd-order stencil.
 double default_damping(int dim, int patch, int level, int stencil) {
@@ -230,7 +235,7 @@ double default_damping(int dim, int patch, int level, int stencil) {
   if (patch == VH_PATCH_POINT && stencil == VH_STENCIL_COMPACT4)
     return (dim == 2 ? jac2 : jac3)[level < 3 ? level : 3];
   static const double full2[] = {0.94, 1.2, 0.4, 0.6};
-  static const double full3[] = {1.08, 0.9, 0.6, 0.6};
+  static const double full3[] = {1.08, 0.5, 1.0, 0.4};
   static const double point2[] = {0.78, 0.7, 0.4, 0.6};
   static const double point3[] = {0.84, 0.7, 0.5, 0.5};
   static const double elem2[] = {0.97, 0.66, 0.48, 0.88};
@@ -303,6 +308,8 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
         return fail(VH_EINVAL, "the symmetric smoother needs damping > 0 on every level");
   if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
     return fail(VH_EINVAL, "unknown contraction");
+  if (o.sweep_tile < 0 || o.sweep_tile > S64_TILES)
+    return fail(VH_EINVAL, "sweep_tile must be in [0, 7]");
   if (o.contraction != VH_CONTRACT_VALU &&
       (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
        o.smoother != VH_SMOOTHER_PATCH ||
@@ -642,7 +649,7 @@ vh_status bsmooth(vh_handle* hd, int l, int ls, const void* r, void* u, bool zer
     VH_HIP(batch_sweep_mfma(Lv.g, ls, hd->opt.contraction == VH_CONTRACT_MFMA_BF16X3,
                             Lv.mfma_txp[ls], Lv.mfma_rows[ls], Lv.B, r, u, zero, hd->s));
   else
-    VH_HIP(batch_sweep(hd->dim, form, Lv.g, ls, hd->prec, Lv.B, r, u, zero, hd->s));
+    VH_HIP(batch_sweep(hd->dim, form, Lv.g, ls, hd->prec, Lv.B, r, u, zero, hd->s, Lv.s64_tile));
   hd->tend(tk);
   return VH_OK;
 }
@@ -706,6 +713,80 @@ vh_status tune_mfma(vh_handle* hd, int ls) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return st;
+}
+
+// Variant of the 64-source 2D assembled sweep for every smoothed level: the caller's
+// vh_options.sweep_tile, else the fastest of the S64_TILES candidates timed with HIP
+// events on the level's own grid (one warm-up and three timed launches each).  The
+// choice depends only on the device, the grid and the precision, so it is kept for the
+// process and reused by later handles; every candidate computes the same sums in the same
+// order, so the choice does not change any result bit.
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tile_cache;
+
+vh_status tune_s64(vh_handle* hd, int ls) {
+  if (ls != 6 || hd->dim != 2 || hd->opt.contraction != VH_CONTRACT_VALU) return VH_OK;
+  int dev = 0;
+  VH_HIP(hipGetDevice(&dev));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  vh_status st = VH_OK;
+  for (int l = 0; l + 1 < hd->levels && st == VH_OK; ++l) {
+    Level& Lv = hd->L[l];
+    if (Lv.form != 2 || Lv.s64_tile) continue;
+    if (hd->opt.sweep_tile > 0) {
+      Lv.s64_tile = hd->opt.sweep_tile;
+      continue;
+    }
+    const auto key = std::make_tuple(dev, Lv.g.nx, Lv.g.ny, hd->prec);
+    {
+      std::lock_guard<std::mutex> lock(g_tile_mu);
+      auto it = g_tile_cache.find(key);
+      if (it != g_tile_cache.end()) {
+        Lv.s64_tile = it->second;
+        continue;
+      }
+    }
+    if (!e0) {
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = fail(VH_EDEVICE, "hipEventCreate failed");
+        break;
+      }
+    }
+    const size_t NS = (size_t)Lv.g.N << ls;
+    if (fill(hd->br[l], NS, hd->prec, 0, 0, hd->s) != hipSuccess ||
+        fill(hd->bu[l], NS, hd->prec, 0, 0, hd->s) != hipSuccess) {
+      st = fail(VH_EDEVICE, "fill failed");
+      break;
+    }
+    float best = 1e30f;
+    int btile = S64_DEFAULT_TILE;
+    for (int t = 1; t <= S64_TILES; ++t) {
+      float ms = 0.f;
+      hipError_t e = batch_sweep(2, 2, Lv.g, ls, hd->prec, Lv.B, hd->br[l], hd->bu[l], false,
+                                 hd->s, t);
+      if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
+      for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        e = batch_sweep(2, 2, Lv.g, ls, hd->prec, Lv.B, hd->br[l], hd->bu[l], false, hd->s, t);
+      if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(VH_EDEVICE, std::string("sweep tile timing: ") + hipGetErrorString(e));
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        btile = t;
+      }
+    }
+    if (st != VH_OK) break;
+    Lv.s64_tile = btile;
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    g_tile_cache[key] = btile;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   return st;
 }
 
@@ -773,6 +854,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
   const int S = 1 << ls;
   VH_TRY(ensure_batch(hd, S));
   VH_TRY(tune_mfma(hd, ls));
+  VH_TRY(tune_s64(hd, ls));
   const long long N = hd->L[0].g.N;
   const int m = hd->m;
   const size_t ldv = (size_t)N * S;
@@ -1329,6 +1411,7 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->smoother_entries = Lv.form == SM_SYMHALF ? (hd->dim == 2 ? 25 : 125) : Lv.E;
   shape_offsets(hd->dim, Lv.shape, Lv.K, info->offsets);
   info->bytes = Lv.bytes;
+  info->sweep_tile = Lv.s64_tile;
   for (int ls = 6; ls >= 0; --ls)
     if (Lv.mfma_txp[ls]) {
       info->mfma_sources = 1 << ls;
@@ -1418,6 +1501,7 @@ vh_status vh_apply_smoother_batch(vh_handle* hd, int level, int nsrc, const void
   const int ls = batch_log2(nsrc), S = 1 << ls;
   VH_TRY(ensure_batch(hd, S));
   VH_TRY(tune_mfma(hd, ls));
+  VH_TRY(tune_s64(hd, ls));
   const long long n = hd->L[level].g.N;
   VH_TRY(to_batch(hd, n, S, nsrc, q, hd->bq[level]));
   VH_TRY(to_batch(hd, n, S, nsrc, u, hd->bu[level]));
@@ -1433,6 +1517,7 @@ vh_status vh_apply_vcycle_batch(vh_handle* hd, int nsrc, const void* v, void* z)
   const int ls = batch_log2(nsrc), S = 1 << ls;
   VH_TRY(ensure_batch(hd, S));
   VH_TRY(tune_mfma(hd, ls));
+  VH_TRY(tune_s64(hd, ls));
   const long long n = hd->L[0].g.N;
   VH_TRY(to_batch(hd, n, S, nsrc, v, hd->bq[0]));
   VH_TRY(vcycle_b(hd, 0, ls, hd->bq[0], hd->bZ, true));

@@ -87,82 +87,128 @@ SERVE_DESC = ("serving mix: Poisson arrivals; 70% 2D grids uniform over {257,513
               "FGMRES in complex128; admission by HBM footprint")
 
 
-def serve_requests(count, seed):
-    """Seeded request mix (media are generated here, outside any timed region)."""
+def serve_specs(count, seed, solves=None):
+    """Seeded request mix: grid, levels, shift, restart, ppw and source count of each
+    request (the media are generated later, one request at a time).  With `solves`, as
+    many requests as it takes for their sources to reach that many solves."""
     import numpy as np
-    import synth
     rng = np.random.default_rng(seed)
-    reqs = []
-    for r in range(count):
+    specs = []
+    total = 0
+    r = 0
+    while (total < solves) if solves else (r < count):
         if rng.uniform() < 0.7:
             nn = int(rng.choice([257, 513, 1025, 2049]))
             n = (nn, nn)
-            kappa = synth.layered_2d(n, 1000 + r)
             levels = {257: 5, 513: 6, 1025: 7, 2049: 8}[nn]
             shift, restart = 0.2, 20
         else:
             nn = int(rng.choice([97, 129, 193]))
             n = (nn, nn, nn)
-            kappa = synth.geophysical_3d(n, 1000 + r)
             levels = {97: 4, 129: 5, 193: 5}[nn]
             shift, restart = 0.5, 30
         ppw = float(rng.uniform(8.0, 12.0))
         nsrc = int(rng.integers(1, 17))
-        h = 1.0 / (nn - 1)
-        omega = synth.omega_for_ppw(h, ppw, float(kappa.max()))
-        q = synth.random_sources(n, nsrc, seed=1000 + r, margin=min(22, nn // 4))
-        reqs.append(dict(dim=len(n), n=n, h=h, omega=omega, kappa=kappa.ravel(),
-                         gamma=0.01 * omega * np.ones(kappa.size), shift=shift, levels=levels,
-                         restart=restart, q=q, nsrc=nsrc))
-    return reqs
+        if solves:
+            nsrc = min(nsrc, solves - total)
+        specs.append(dict(r=r, n=n, levels=levels, shift=shift, restart=restart, ppw=ppw,
+                          nsrc=nsrc))
+        total += nsrc
+        r += 1
+    return specs
+
+
+def serve_media(spec):
+    """Seeded medium (c2 recipe in 2D, c3 recipe in 3D) and sources of one request."""
+    import numpy as np
+    import synth
+    n, r = spec["n"], spec["r"]
+    kappa = synth.layered_2d(n, 1000 + r) if len(n) == 2 else synth.geophysical_3d(n, 1000 + r)
+    nn = n[0]
+    h = 1.0 / (nn - 1)
+    omega = synth.omega_for_ppw(h, spec["ppw"], float(kappa.max()))
+    q = synth.random_sources(n, spec["nsrc"], seed=1000 + r, margin=min(22, nn // 4))
+    return dict(spec, dim=len(n), h=h, omega=omega, kappa=kappa.ravel(),
+                gamma=0.01 * omega * np.ones(kappa.size), q=q)
 
 
 def serve_bench(args):
-    """Serving workload: requests submitted at Poisson arrival times to one server."""
+    """Serving workload: requests submitted at Poisson arrival times to one server.  A
+    producer thread generates the media a few requests ahead of their arrival, and a
+    fetcher thread collects the results in submission order while later requests arrive."""
+    import queue
+    import threading
     import numpy as np
     import torch
     from paper_2511_16808_amd import binding as B
-    reqs = serve_requests(args.requests, 5)
+    specs = serve_specs(args.requests, 5, args.solves)
     rng = np.random.default_rng(5)
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(reqs)))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=len(specs)))
     arrivals -= arrivals[0]
     args.smoother = args.smoother or "assembled"
     smoother = B.VH_SMOOTHER_ASSEMBLED if args.smoother == "assembled" else B.VH_SMOOTHER_PATCH
     opts = {rs: B.make_options(precision=B.VH_PREC_C64, batch=1, restart=rs, smoother=smoother)
             for rs in (20, 30)}
+    ready = queue.Queue(maxsize=4)
+
+    def produce():
+        for sp in specs:
+            ready.put(serve_media(sp))
+    threading.Thread(target=produce, daemon=True).start()
     torch.cuda.synchronize()
     srv = B.vh_server_create(int(args.budget_gib * (1 << 30)), args.slots)
+    submitted = queue.Queue()
+    results = []
+
+    def fetch():
+        while True:
+            item = submitted.get()
+            if item is None:
+                return
+            t, nsrc, N = item
+            st, _, stats, lat, qm = B.vh_server_result(srv, t, N, nsrc, want_u=False)
+            results.append((st, [x["iterations"] for x in stats], lat, qm, nsrc))
+            if len(results) % 10 == 0:
+                print(f"c5: {len(results)} of {len(specs)} requests done", file=sys.stderr,
+                      flush=True)
+    fetcher = threading.Thread(target=fetch)
+    fetcher.start()
     t0 = time.perf_counter()
-    tickets = []
-    for r, ta in zip(reqs, arrivals):
+    late = 0.0
+    for ta in arrivals:
+        r = ready.get()
         now = time.perf_counter() - t0
         if ta > now:
             time.sleep(ta - now)
-        tickets.append(B.vh_server_submit(srv, r["dim"], r["n"], r["h"], r["omega"], r["kappa"],
-                                          r["gamma"], r["shift"], r["levels"], B.VH_PATCH_FULL,
-                                          r["q"], r["nsrc"], 1e-6, opts[r["restart"]]))
-    lat, qms, its, ok, nsol = [], [], [], 0, 0
-    for t, r in zip(tickets, reqs):
-        st, u, stats, l, qm = B.vh_server_result(srv, t, int(np.prod(r["n"])), r["nsrc"])
-        lat.append(l)
-        qms.append(qm)
-        its += [x["iterations"] for x in stats]
-        ok += int(st == B.VH_OK)
-        nsol += r["nsrc"]
+        else:
+            late = max(late, now - ta)
+        t = B.vh_server_submit(srv, r["dim"], r["n"], r["h"], r["omega"], r["kappa"], r["gamma"],
+                               r["shift"], r["levels"], B.VH_PATCH_FULL, r["q"], r["nsrc"], 1e-6,
+                               opts[r["restart"]])
+        submitted.put((t, r["nsrc"], int(np.prod(r["n"]))))
+        del r
+    submitted.put(None)
+    fetcher.join()
     makespan = time.perf_counter() - t0
     info = B.vh_server_get_info(srv)
     B.vh_server_destroy(srv)
-    lat = np.array(lat)
+    lat = np.array([x[2] for x in results])
+    qms = np.array([x[3] for x in results])
+    its = [i for x in results for i in x[1]]
+    nsol = sum(x[4] for x in results)
+    ok = sum(int(x[0] == B.VH_OK) for x in results)
     out = {
         "metric": METRIC, "value": nsol / makespan, "unit": "solves/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": 0, "ms_per_step": 1e3 * makespan / len(reqs),
+        "steps": len(specs), "warmup": 0, "ms_per_step": 1e3 * makespan / len(specs),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
         "data": "synthetic",
-        "config": {"workload": "c5: " + SERVE_DESC, "requests": len(reqs), "sources": nsol,
+        "config": {"workload": "c5: " + SERVE_DESC, "requests": len(specs), "sources": nsol,
                    "arrival_rate_per_s": args.rate, "slots": args.slots,
                    "hbm_budget_gib": args.budget_gib, "smoother": args.smoother},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "queue_p50_ms": float(np.percentile(qms, 50)), "makespan_s": makespan,
+        "queue_p50_ms": float(np.percentile(qms, 50)),
+        "queue_p99_ms": float(np.percentile(qms, 99)), "makespan_s": makespan,
+        "max_submit_delay_s": late,
         "requests_ok": ok, "iterations_mean": float(np.mean(its)),
         "peak_running": info["peak_running"], "peak_in_use_gib": info["peak_in_use"] / 2 ** 30,
     }
@@ -357,6 +403,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["c5"])
     ap.add_argument("--requests", type=int, default=32, help="c5: number of requests")
+    ap.add_argument("--solves", type=int, default=None,
+                    help="c5: requests until their sources total this many solves "
+                         "(overrides --requests)")
     ap.add_argument("--rate", type=float, default=2.0, help="c5: Poisson arrival rate (1/s)")
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--budget-gib", type=float, default=240.0, help="c5: HBM budget")
@@ -506,7 +555,8 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     elif contraction != B.VH_CONTRACT_VALU and width >= 16:
         kname = "kb_sweep_mfma"
     elif dim == 2 and width == 64 and E[0] == 25:
-        kname = "kb_sweep2d_s64"
+        # the variant the tile tuner chose for the finest level (1: the LDS walk)
+        kname = "kb_sweep2d_s64" if info[0].get("sweep_tile", 0) == 1 else "kb_sweep2d_s64w"
     elif dim == 2:
         kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
     else:
@@ -566,7 +616,8 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
         "c_f": (float(np.mean(cfs)) if cfs else None),
         "roofline": {
             **roof,
-            "kernel": f"finest-level additive Vanka sweep u += B r ({kname}, {width} source(s))",
+            "kernel": f"finest-level additive Vanka sweep u += B r ({kname}, {width} source(s)"
+                      + (f", tile {info[0]['sweep_tile']}" if info[0].get("sweep_tile") else "") + ")",
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": ms_l / n_l if n_l else None,

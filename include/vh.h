@@ -390,15 +390,17 @@ vh_status vh_tune_shift(int dim, const int *n, double h, double omega, const dou
                         double tol, double *alpha, double *cfs);
 
 /* ---- serving: persistent request loop with admission by HBM footprint ----------
- * Requests are copied at submission and queued.  Up to max_slots requests run at
- * once, each on its own worker thread and HIP stream (default priority); a queued
- * request is admitted as soon as a slot is free and its footprint
- * (vh_footprint_bytes + its kappa, gamma, q and u arrays) fits in what is left of
- * hbm_budget.  Later requests may overtake a queued head that does not fit at most a
- * bounded number of times.  Each request runs vh_setup + vh_solve on a handle of its
- * own, so its result does not depend on the other requests in flight.  Results are
- * held until fetched with vh_server_result.  The server uses the device that is
- * current when it is created. */
+ * Requests are copied at submission and queued.  vh_server_create allocates one device
+ * arena of hbm_budget bytes; a request runs in a contiguous region of it that holds its
+ * kappa, gamma, q and u arrays and its whole handle at its peak (vh_footprint_bytes plus
+ * alignment), so no request allocates or frees device memory while others run.  Up to
+ * max_slots requests run at once, each on its own worker thread and HIP stream (default
+ * priority); a queued request is admitted as soon as a slot and a free region of its
+ * size are available (first fit).  Later requests may overtake a queued head that does
+ * not fit at most a bounded number of times.  Each request runs vh_setup + vh_solve on a
+ * handle of its own, so its result does not depend on the other requests in flight.
+ * Results are held until fetched with vh_server_result.  The server uses the device that
+ * is current when it is created. */
 typedef struct vh_server vh_server;
 
 typedef struct vh_request {
@@ -421,6 +423,7 @@ typedef struct vh_server_info {
     uint64_t completed;
 } vh_server_info;
 
+/* VH_ENOMEM if the arena of hbm_budget bytes cannot be allocated; max_slots in [1, 64]. */
 vh_status vh_server_create(vh_server **out, size_t hbm_budget, int max_slots);
 /* VH_ENOMEM if the request alone exceeds the budget, VH_EINVAL for bad requests. */
 vh_status vh_server_submit(vh_server *srv, const vh_request *req, uint64_t *ticket);

@@ -388,19 +388,19 @@ def vh_server_wait(srv, ticket):
     check(lib().vh_server_wait(srv, ticket))
 
 
-def vh_server_result(srv, ticket, N, nsrc):
-    """Returns (status, u (nsrc, N) complex128, [stats dicts], latency_ms, queue_ms).
+def vh_server_result(srv, ticket, N, nsrc, want_u=True):
+    """Returns (status, u (nsrc, N) complex128 or None, [stats dicts], latency_ms, queue_ms).
     N and nsrc must be the request's (the output buffers are sized by them)."""
     import numpy as np
     rec = _tickets.get((srv.value, ticket))
     if rec is not None and rec != (int(N), int(nsrc)):
         raise ValueError(f"ticket {ticket} was submitted with (N, nsrc) = {rec}")
     _tickets.pop((srv.value, ticket), None)
-    u = np.zeros((nsrc, N), dtype=np.complex128)
+    u = np.zeros((nsrc, N), dtype=np.complex128) if want_u else None
     stats = (vh_solve_stats * nsrc)()
     lat, qms = _D(), _D()
-    st = lib().vh_server_result(srv, ticket, u.ctypes.data, stats, ctypes.byref(lat),
-                                ctypes.byref(qms))
+    st = lib().vh_server_result(srv, ticket, u.ctypes.data if want_u else None, stats,
+                                ctypes.byref(lat), ctypes.byref(qms))
     if st not in (VH_OK, VH_ENOCONV):
         check(st)
     return st, u, [s.as_dict() for s in stats], lat.value, qms.value

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/vh.h"
+#include "vh_internal.h"
 #include "vh_launch.h"
 
 using namespace vh;
@@ -111,6 +112,16 @@ struct vh_handle {
   hipEvent_t sev = nullptr;
   std::vector<void*> allocs;
   std::vector<size_t> alloc_sizes;
+  // Region mode (a handle built inside memory handed over by the request server): every
+  // allocation is carved out of [region, region + region_bytes) with no hipMalloc or
+  // hipFree, the long-lived arrays from the bottom up and the set-up temporaries (FP64
+  // Galerkin copies of a complex64 hierarchy, slab buffers, pivoting arrays) from the
+  // top down, so the temporaries' space is reused by the solve workspace allocated after
+  // them.  alloc_temp flags the top-down blocks; lo and hi are the two stack ends.
+  char* region = nullptr;
+  size_t region_bytes = 0, lo = 0, hi = 0;
+  std::vector<char> alloc_temp, alloc_freed;
+  double* pinned_ext = nullptr;  // server-owned pinned status buffer (4 + 256 doubles)
   size_t bytes = 0;       // device bytes held now
   size_t peak_bytes = 0;  // largest value bytes has taken
   double setup_ms = 0.0;  // wall time of vh_setup
@@ -135,9 +146,12 @@ struct vh_handle {
 
   ~vh_handle() {
     if (sev) (void)hipEventDestroy(sev);
-    for (void* p : allocs) (void)hipFree(p);
-    if (hstat) (void)hipHostFree(hstat);
-    if (bstat) (void)hipHostFree(bstat);
+    if (!region)
+      for (void* p : allocs) (void)hipFree(p);
+    if (!pinned_ext) {
+      if (hstat) (void)hipHostFree(hstat);
+      if (bstat) (void)hipHostFree(bstat);
+    }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
   // returns the index of a free event pair, or -1 if timing is off / the pool is full
@@ -162,29 +176,71 @@ struct vh_handle {
     }
     ev_used = 0;
   }
-  vh_status alloc(void** p, size_t bytes_) {
+  vh_status alloc(void** p, size_t bytes_, bool temp = false) {
     *p = nullptr;
     if (bytes_ == 0) return VH_OK;
-    hipError_t e = hipMalloc(p, bytes_);
-    if (e != hipSuccess) {
-      *p = nullptr;
-      (void)hipGetLastError();
-      return fail(VH_ENOMEM, "hipMalloc of " + std::to_string(bytes_) + " bytes failed: " +
-                                 hipGetErrorString(e));
+    if (region) {
+      const size_t a = (bytes_ + 255) / 256 * 256;
+      if (a > hi - lo)
+        return fail(VH_ENOMEM, "the request's device region is exhausted (" +
+                                   std::to_string(bytes_) + " more bytes)");
+      if (temp) {
+        hi -= a;
+        *p = region + hi;
+      } else {
+        *p = region + lo;
+        lo += a;
+      }
+      bytes_ = a;
+    } else {
+      hipError_t e = hipMalloc(p, bytes_);
+      if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(VH_ENOMEM, "hipMalloc of " + std::to_string(bytes_) + " bytes failed: " +
+                                   hipGetErrorString(e));
+      }
     }
     allocs.push_back(*p);
     alloc_sizes.push_back(bytes_);
+    alloc_temp.push_back(temp ? 1 : 0);
+    alloc_freed.push_back(0);
     bytes += bytes_;
     if (bytes > peak_bytes) peak_bytes = bytes;
     return VH_OK;
   }
   void release(void* p) {
     for (size_t i = 0; i < allocs.size(); ++i)
-      if (allocs[i] == p) {
-        (void)hipFree(p);
+      if (allocs[i] == p && !alloc_freed[i]) {
         bytes -= alloc_sizes[i];
-        allocs.erase(allocs.begin() + i);
-        alloc_sizes.erase(alloc_sizes.begin() + i);
+        if (!region) {
+          (void)hipFree(p);
+          allocs.erase(allocs.begin() + i);
+          alloc_sizes.erase(alloc_sizes.begin() + i);
+          alloc_temp.erase(alloc_temp.begin() + i);
+          alloc_freed.erase(alloc_freed.begin() + i);
+          return;
+        }
+        alloc_freed[i] = 1;
+        // give back freed blocks at either stack end (a block freed out of order waits
+        // until the blocks above it are freed)
+        bool moved = true;
+        while (moved) {
+          moved = false;
+          for (size_t k = 0; k < allocs.size(); ++k) {
+            if (!alloc_freed[k] || alloc_freed[k] == 2) continue;
+            const size_t off = (size_t)((char*)allocs[k] - region);
+            if (alloc_temp[k] && off == hi) {
+              hi += alloc_sizes[k];
+              alloc_freed[k] = 2;
+              moved = true;
+            } else if (!alloc_temp[k] && off + alloc_sizes[k] == lo) {
+              lo -= alloc_sizes[k];
+              alloc_freed[k] = 2;
+              moved = true;
+            }
+          }
+        }
         return;
       }
   }
@@ -635,6 +691,7 @@ vh_status ensure_batch(vh_handle* hd, int S) {
     VH_TRY(hd->alloc(&hd->bu[l], Nl * hd->esz));
     VH_TRY(hd->alloc(&hd->br[l], Nl * hd->esz));
   }
+  if (!hd->bstat && hd->pinned_ext) hd->bstat = hd->pinned_ext + 4;
   if (!hd->bstat) VH_HIP(hipHostMalloc((void**)&hd->bstat, 64 * 4 * sizeof(double), hipHostMallocDefault));
   hd->bS = S;
   return VH_OK;
@@ -1037,7 +1094,7 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
   hipStream_t s = hd->s;
   const SlabPlan p = slab_plan(dim, g, Np, hd->esz, scratch_bytes);
   void* buf = scratch;
-  if (p.own) VH_TRY(hd->alloc(&buf, (size_t)p.cnt_max * p.per_plane));
+  if (p.own) VH_TRY(hd->alloc(&buf, (size_t)p.cnt_max * p.per_plane, true));
   const size_t gstride = (size_t)p.cnt_max * p.plane_pad;
   const int K5 = dim == 2 ? 25 : 125;
   const int E = sym ? (K5 + 1) / 2 : K5;
@@ -1096,7 +1153,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   const size_t N0 = (size_t)hd->L[0].g.N;
   {  // media check: kappa > 0 and gamma >= 0, all finite
     int* flag = nullptr;
-    VH_TRY(hd->alloc((void**)&flag, sizeof(int)));
+    VH_TRY(hd->alloc((void**)&flag, sizeof(int), true));
     VH_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     VH_HIP(check_media((long long)N0, kappa, gamma, flag, s));
     int hflag = 0;
@@ -1108,7 +1165,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   // finest operator, FP64
   std::vector<cpx<double>*> A64(hd->levels, nullptr);
   VH_TRY(hd->alloc((void**)&hd->Hfine, hd->L[0].K * N0 * sizeof(cpx<double>)));
-  VH_TRY(hd->alloc((void**)&A64[0], hd->L[0].K * N0 * sizeof(cpx<double>)));
+  // the FP64 Galerkin operators are the levels' operators in FP64, set-up temporaries
+  // when the preconditioner runs in complex64
+  const bool a64_temp = hd->prec != PREC_F64;
+  VH_TRY(hd->alloc((void**)&A64[0], hd->L[0].K * N0 * sizeof(cpx<double>), a64_temp));
   if (o.stencil == VH_STENCIL_COMPACT4)
     VH_HIP(fine_compact4(dim, hd->L[0].g, kappa, gamma, hd->h, hd->omega, hd->shift, o.bc,
                          o.sponge_width, o.sponge_amp, hd->Hfine, A64[0], s));
@@ -1123,7 +1183,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   // Galerkin hierarchy, FP64
   for (int l = 0; l + 1 < hd->levels; ++l) {
     Level &Lf = hd->L[l], &Lc = hd->L[l + 1];
-    VH_TRY(hd->alloc((void**)&A64[l + 1], (size_t)Lc.K * Lc.g.N * sizeof(cpx<double>)));
+    VH_TRY(hd->alloc((void**)&A64[l + 1], (size_t)Lc.K * Lc.g.N * sizeof(cpx<double>), a64_temp));
     VH_HIP(galerkin(dim, Lf.shape, Lc.shape, Lf.rf, Lf.pf, Lf.g, Lc.g, A64[l], A64[l + 1], s));
   }
   // the FGMRES basis is allocated first: until the first solve it is the scratch
@@ -1180,8 +1240,8 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     int* perm = nullptr;
     cpx<double>* col = nullptr;
     VH_TRY(hd->alloc((void**)&hd->Dinv, (size_t)nc * nc * sizeof(cpx<double>)));
-    VH_TRY(hd->alloc((void**)&perm, (size_t)nc * sizeof(int)));
-    VH_TRY(hd->alloc((void**)&col, (size_t)nc * sizeof(cpx<double>)));
+    VH_TRY(hd->alloc((void**)&perm, (size_t)nc * sizeof(int), true));
+    VH_TRY(hd->alloc((void**)&col, (size_t)nc * sizeof(cpx<double>), true));
     VH_HIP(fill(hd->Dinv, (size_t)nc * nc, PREC_F64, 0, 0, s));
     VH_HIP(dense_assemble(dim, Lc.shape, Lc.g, A64[hd->levels - 1], hd->Dinv, s));
     VH_HIP(gj_invert(nc, hd->Dinv, perm, col, s));
@@ -1207,7 +1267,10 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
   VH_TRY(hd->alloc((void**)&hd->dpart, ((size_t)hd->dnb + 16) * 65 * 64 * sizeof(cpx<double>)));
   VH_TRY(hd->alloc((void**)&hd->dK, sizeof(BatchKrylovDev)));
   VH_HIP(hipMemsetAsync(hd->dK, 0, sizeof(BatchKrylovDev), s));
-  VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
+  if (hd->pinned_ext)
+    hd->hstat = hd->pinned_ext;
+  else
+    VH_HIP(hipHostMalloc((void**)&hd->hstat, 4 * sizeof(double), hipHostMallocDefault));
   VH_HIP(hipEventCreateWithFlags(&hd->sev, hipEventDisableTiming));
   if (o.timing) {
     hd->ev.assign(128, nullptr);
@@ -1256,9 +1319,13 @@ const char* vh_status_string(vh_status s) {
 
 const char* vh_last_error(void) { return g_last_error.c_str(); }
 
-vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omega,
-                   const double* kappa, const double* gamma, double shift, int levels, int patch,
-                   const vh_options* opt) {
+}  // extern "C"
+
+// vh_setup, optionally inside a device region handed over by the caller (see vh_handle)
+static vh_status setup_impl(vh_handle** out, int dim, const int* n, double h, double omega,
+                            const double* kappa, const double* gamma, double shift, int levels,
+                            int patch, const vh_options* opt, void* region, size_t region_bytes,
+                            double* pinned) {
   if (!out) return fail(VH_EINVAL, "out is NULL");
   *out = nullptr;
   vh_options o;
@@ -1286,6 +1353,13 @@ vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omeg
   hd->prec = o.precision == VH_PREC_FP64 ? PREC_F64 : PREC_F32;
   hd->esz = hd->prec == PREC_F64 ? 16 : 8;
   hd->s = (hipStream_t)o.stream;
+  if (region) {
+    hd->region = (char*)region;
+    hd->region_bytes = region_bytes;
+    hd->lo = 0;
+    hd->hi = region_bytes;
+  }
+  hd->pinned_ext = pinned;
   const auto t0 = std::chrono::steady_clock::now();
   vh_status st = build(hd, kappa, gamma);
   hd->setup_ms =
@@ -1297,6 +1371,24 @@ vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omeg
   }
   *out = hd;
   return VH_OK;
+}
+
+vh_status vh_setup_region(vh_handle** out, int dim, const int* n, double h, double omega,
+                          const double* kappa, const double* gamma, double shift, int levels,
+                          int patch, const vh_options* opt, void* region, size_t region_bytes,
+                          double* pinned) {
+  if (!region || region_bytes == 0 || !pinned) return fail(VH_EINVAL, "bad region");
+  return setup_impl(out, dim, n, h, omega, kappa, gamma, shift, levels, patch, opt, region,
+                    region_bytes, pinned);
+}
+
+extern "C" {
+
+vh_status vh_setup(vh_handle** out, int dim, const int* n, double h, double omega,
+                   const double* kappa, const double* gamma, double shift, int levels, int patch,
+                   const vh_options* opt) {
+  return setup_impl(out, dim, n, h, omega, kappa, gamma, shift, levels, patch, opt, nullptr, 0,
+                    nullptr);
 }
 
 vh_status vh_solve(vh_handle* hd, const void* q, int nsrc, double tol, void* u,
@@ -1879,7 +1971,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
   const size_t dnb = std::min<size_t>(nred, 1024);
   size_t solve_extra = (size_t)o.restart * N0 * esz + nred * 65 * 16 + sizeof(KrylovDev) +
                        (dnb + 16) * 65 * 64 * 16 + sizeof(BatchKrylovDev);
-  if (o.batch && nsrc > 1) {  // multi-source workspace for one group of S sources
+  if (o.batch) {  // multi-source workspace for one group of S sources (S = 1 included)
     size_t S = 1;
     while (S < (size_t)(nsrc < 64 ? nsrc : 64)) S *= 2;
     const size_t bnred = std::min<size_t>(std::max<size_t>(N0 * S / 8192, 64), 1024);
@@ -1895,3 +1987,11 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
 }
 
 }  // extern "C"
+
+size_t vh_region_bytes(int dim, const int* n, int levels, int patch, int nsrc,
+                       const vh_options* opt) {
+  const size_t fp = vh_footprint_bytes(dim, n, levels, patch, nsrc, opt);
+  if (fp == 0 || levels < 1) return 0;
+  // every array is rounded up to 256 bytes: at most 24 + 10 per level of them
+  return fp + (size_t)(24 + 10 * levels) * 256;
+}

@@ -2,9 +2,14 @@
 //
 // Requests (grid, medium, frequency, sources) are copied at submission and queued.
 // Up to max_slots worker threads, each with its own HIP stream (default priority),
-// take requests as soon as a slot is free and the request's device footprint fits in
-// the remaining budget: requests arriving while others run are admitted as slots and
-// memory free up, and their kernels overlap on the device.  Each request runs
+// take requests as soon as a slot is free and a contiguous region of the request's
+// device footprint is free in the server's arena: requests arriving while others run
+// are admitted as slots and memory free up, and their kernels overlap on the device.
+// The arena is one device allocation made when the server is created; a request's
+// medium, sources, solution and whole handle (hierarchy and Krylov workspaces) are
+// carved out of its region, and the pinned status buffers belong to the worker, so no
+// request calls hipMalloc, hipFree or the pinned-memory allocator (each of which can
+// wait for the whole device and stall the other requests).  Each request runs
 // vh_setup + vh_solve on its own handle, so its result does not depend on what else
 // is running.  Results are held until fetched.
 #include <hip/hip_runtime.h>
@@ -14,6 +19,8 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -21,6 +28,7 @@
 #include <vector>
 
 #include "../../include/vh.h"
+#include "vh_internal.h"
 
 namespace {
 
@@ -36,7 +44,8 @@ struct Req {
   std::vector<double> kappa, gamma;
   std::vector<std::complex<double>> q, u;
   std::vector<vh_solve_stats> stats;
-  size_t footprint = 0;
+  size_t footprint = 0;    // bytes of the request's region
+  size_t region_off = 0;   // offset of its region in the arena while it runs
   size_t N = 0;
   vh_status status = VH_OK;
   std::string error;
@@ -57,7 +66,56 @@ vh_status serr(vh_status st, const std::string& m) {
 
 }  // namespace
 
+namespace {
+
+// First-fit allocator of byte ranges of one device allocation (host bookkeeping only,
+// callers hold the server lock).  Ranges are 256-byte aligned; freed ranges coalesce.
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(char* b, size_t n) {
+    base = b;
+    bytes = n;
+    free_.clear();
+    free_[0] = n;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n;
+      const size_t roff = it->first + n;
+      free_.erase(it);
+      if (rest) free_[roff] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) / 256 * 256;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+
 struct vh_server {
+  Arena arena;
+  double* pinned = nullptr;  // one 4 + 256 double status buffer per worker
   size_t budget = 0, in_use = 0, peak = 0;
   int max_slots = 1, running = 0, peak_running = 0, device = 0;
   uint64_t next_ticket = 1, completed = 0;
@@ -74,11 +132,16 @@ namespace {
 
 constexpr int MAX_HEAD_SKIPS = 4;  // later requests may overtake the head this often
 
-// device bytes of one request: the handle (hierarchy + FGMRES workspace) plus the
-// caller-side arrays the worker allocates (kappa, gamma, q, u)
+constexpr size_t PINNED_DOUBLES = 4 + 256;  // per worker: one- and multi-source status
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// device bytes of one request's region: its arrays (kappa, gamma, q, u) and the handle
+// (hierarchy + FGMRES workspaces at their peak, with alignment)
 size_t request_footprint(const Req& r) {
-  const size_t lib = vh_footprint_bytes(r.dim, r.n, r.levels, r.patch, r.nsrc, &r.opt);
-  return lib + r.N * 2 * sizeof(double) + r.N * (size_t)r.nsrc * 2 * 16;
+  const size_t lib = vh_region_bytes(r.dim, r.n, r.levels, r.patch, r.nsrc, &r.opt);
+  if (lib == 0) return 0;
+  return lib + 2 * align256(r.N * sizeof(double)) + 2 * align256(r.N * (size_t)r.nsrc * 16);
 }
 
 // under the lock: pick the next admissible request (first fit, bounded overtaking)
@@ -86,7 +149,7 @@ Req* pick(vh_server* S) {
   if (S->running >= S->max_slots || S->queue.empty()) return nullptr;
   for (size_t k = 0; k < S->queue.size(); ++k) {
     Req* r = S->queue[k];
-    if (S->in_use + r->footprint <= S->budget) {
+    if (S->arena.alloc(r->footprint, &r->region_off)) {
       if (k == 0)
         S->head_skips = 0;
       else
@@ -99,23 +162,29 @@ Req* pick(vh_server* S) {
   return nullptr;
 }
 
-void run_request(Req* r, hipStream_t stream) {
+void run_request(Req* r, char* region, double* pinned, hipStream_t stream) {
   const size_t N = r->N;
-  double *dk = nullptr, *dg = nullptr;
-  void *dq = nullptr, *du = nullptr;
   vh_handle* hd = nullptr;
   vh_status st = VH_OK;
   auto hip_ok = [&](hipError_t e, const char* what) {
     if (e == hipSuccess) return true;
-    st = (e == hipErrorOutOfMemory) ? VH_ENOMEM : VH_EDEVICE;
+    st = VH_EDEVICE;
     r->error = std::string(what) + ": " + hipGetErrorString(e);
     return false;
   };
   const size_t qb = N * (size_t)r->nsrc * 16;
-  if (hip_ok(hipMalloc((void**)&dk, N * sizeof(double)), "hipMalloc") &&
-      hip_ok(hipMalloc(&dq, qb), "hipMalloc") && hip_ok(hipMalloc(&du, qb), "hipMalloc") &&
-      (r->gamma.empty() || hip_ok(hipMalloc((void**)&dg, N * sizeof(double)), "hipMalloc")) &&
-      hip_ok(hipMemcpyAsync(dk, r->kappa.data(), N * sizeof(double), hipMemcpyHostToDevice, stream),
+  // region layout: kappa | gamma | q | u | handle
+  char* p = region;
+  double* dk = (double*)p;
+  p += align256(N * sizeof(double));
+  double* dg = r->gamma.empty() ? nullptr : (double*)p;
+  p += align256(N * sizeof(double));
+  void* dq = p;
+  p += align256(qb);
+  void* du = p;
+  p += align256(qb);
+  const size_t hbytes = r->footprint - (size_t)(p - region);
+  if (hip_ok(hipMemcpyAsync(dk, r->kappa.data(), N * sizeof(double), hipMemcpyHostToDevice, stream),
              "copy") &&
       (r->gamma.empty() ||
        hip_ok(hipMemcpyAsync(dg, r->gamma.data(), N * sizeof(double), hipMemcpyHostToDevice, stream),
@@ -123,7 +192,8 @@ void run_request(Req* r, hipStream_t stream) {
       hip_ok(hipMemcpyAsync(dq, r->q.data(), qb, hipMemcpyHostToDevice, stream), "copy")) {
     vh_options o = r->opt;
     o.stream = stream;
-    st = vh_setup(&hd, r->dim, r->n, r->h, r->omega, dk, dg, r->shift, r->levels, r->patch, &o);
+    st = vh_setup_region(&hd, r->dim, r->n, r->h, r->omega, dk, dg, r->shift, r->levels,
+                         r->patch, &o, p, hbytes, pinned);
     if (st != VH_OK) {
       r->error = vh_last_error();
     } else {
@@ -139,19 +209,16 @@ void run_request(Req* r, hipStream_t stream) {
           r->error = hipGetErrorString(e);
         }
       }
-      vh_destroy(hd);
+      vh_destroy(hd);  // a region handle returns nothing to the device allocator
     }
   }
   (void)hipStreamSynchronize(stream);
-  if (dk) (void)hipFree(dk);
-  if (dg) (void)hipFree(dg);
-  if (dq) (void)hipFree(dq);
-  if (du) (void)hipFree(du);
   r->status = st;
 }
 
-void worker(vh_server* S) {
+void worker(vh_server* S, int slot) {
   (void)hipSetDevice(S->device);
+  double* pinned = S->pinned + (size_t)slot * PINNED_DOUBLES;
   hipStream_t stream = nullptr;
   (void)hipStreamCreate(&stream);  // default priority
   std::unique_lock<std::mutex> lk(S->mu);
@@ -165,8 +232,9 @@ void worker(vh_server* S) {
     S->peak_running = std::max(S->peak_running, S->running);
     r->state = RUNNING;
     r->t_start = clk::now();
+    char* region = S->arena.base + r->region_off;
     lk.unlock();
-    run_request(r, stream);
+    run_request(r, region, pinned, stream);
     lk.lock();
     r->t_done = clk::now();
     r->state = DONE;
@@ -176,6 +244,7 @@ void worker(vh_server* S) {
     r->gamma.shrink_to_fit();
     r->q.clear();
     r->q.shrink_to_fit();
+    S->arena.release(r->region_off, r->footprint);
     S->in_use -= r->footprint;
     --S->running;
     ++S->completed;
@@ -208,7 +277,22 @@ vh_status vh_server_create(vh_server** out, size_t hbm_budget, int max_slots) {
     delete S;
     return serr(VH_EDEVICE, "hipGetDevice failed");
   }
-  for (int k = 0; k < max_slots; ++k) S->workers.emplace_back(worker, S);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, hbm_budget);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete S;
+    return serr(VH_ENOMEM, std::string("the server arena of the HBM budget: ") + hipGetErrorString(e));
+  }
+  e = hipHostMalloc((void**)&S->pinned, (size_t)max_slots * PINNED_DOUBLES * sizeof(double),
+                    hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(base);
+    delete S;
+    return serr(VH_ENOMEM, std::string("pinned status buffers: ") + hipGetErrorString(e));
+  }
+  S->arena.init((char*)base, hbm_budget);
+  for (int k = 0; k < max_slots; ++k) S->workers.emplace_back(worker, S, k);
   *out = S;
   return VH_OK;
 }
@@ -330,6 +414,8 @@ vh_status vh_server_destroy(vh_server* S) {
   }
   for (auto& t : S->workers) t.join();
   for (auto& kv : S->reqs) delete kv.second;
+  if (S->arena.base) (void)hipFree(S->arena.base);
+  if (S->pinned) (void)hipHostFree(S->pinned);
   delete S;
   return VH_OK;
 }

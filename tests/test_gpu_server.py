@@ -71,6 +71,30 @@ def test_results_are_the_same_alone_and_in_the_mix():
             assert res <= 1e-6
 
 
+def test_server_result_equals_a_direct_solve():
+    """A request solved by the server (its handle carved out of the server's arena) gives
+    the same bits as vh_setup + vh_solve on device memory of its own."""
+    r = make_requests()[1]
+    res, _ = run([r], budget=8 << 30, slots=1)
+    st, u, stats, _, _ = res[0]
+    assert st == B.VH_OK
+    dev = torch.device("cuda")
+    opt = B.make_options(precision=B.VH_PREC_C64, batch=1, restart=20,
+                         sponge_width=r["opt"].sponge_width, stream=torch.cuda.current_stream())
+    hd = B.vh_setup(r["dim"], r["n"], r["h"], r["omega"], torch.tensor(r["kappa"], device=dev),
+                    torch.tensor(r["gamma"], device=dev), r["shift"], r["levels"],
+                    B.VH_PATCH_FULL, opt)
+    try:
+        qg = torch.tensor(np.ascontiguousarray(r["q"]).ravel(), dtype=torch.complex128, device=dev)
+        ug = torch.empty_like(qg)
+        st1, stats1 = B.vh_solve(hd, qg, r["nsrc"], 1e-6, ug)
+    finally:
+        B.vh_destroy(hd)
+    assert st1 == B.VH_OK
+    assert [s["iterations"] for s in stats] == [s["iterations"] for s in stats1]
+    assert np.array_equal(u, ug.cpu().numpy().reshape(r["nsrc"], -1))
+
+
 def test_admission_respects_the_budget():
     reqs = make_requests()
     fps = [B.vh_footprint_bytes(r["dim"], r["n"], r["levels"], B.VH_PATCH_FULL, r["nsrc"], r["opt"])

@@ -450,13 +450,16 @@ def main():
         torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    ceiling = copy_ceiling()
     out = run_workload(args.workload, args.steps, args.warmup, args.smoother, args.contraction,
                        args.batch, args.precision, not args.no_cpu_baseline)
+    out["roofline"].update(ceiling_fields(out["roofline"], ceiling))
     if args.workload == DEFAULT_WORKLOAD and args.c4_steps > 0:
         # the 512^2 half of the metric: 64 sources through one hierarchy, timed after the
         # 256^3 steps (its own warm-up, steps, roofline and CPU baseline)
         c4 = run_workload("c4", args.c4_steps, 1, None, "valu", None, None,
                           not args.no_cpu_baseline)
+        c4["roofline"].update(ceiling_fields(c4["roofline"], ceiling))
         out["c4"] = {k: c4[k] for k in ("metric", "value", "unit", "steps", "warmup",
                                         "ms_per_step", "dtype", "config", "iterations",
                                         "converged", "true_relres", "setup_ms", "solve_ms",
@@ -465,6 +468,35 @@ def main():
                                         "solve_GBps", "c_f", "roofline", "cpu_baseline")
                      if k in c4}
     print(json.dumps(out))
+
+
+def copy_ceiling(mib=2048, reps=5):
+    """HBM rate a plain elementwise copy reaches on this GPU: out = in + 1 over `mib` MiB
+    read and `mib` MiB written, timed with events on the current stream (best of reps)."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.add(src, 1.0, out=dst)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.add(src, 1.0, out=dst)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
+def ceiling_fields(roof, ceiling):
+    """The measured copy rate next to the spec peak, and the kernel's fraction of it."""
+    if roof.get("unit") != "GB/s" or not ceiling:
+        return {"copy_GBps": ceiling}
+    return {"copy_GBps": ceiling,
+            "frac_of_copy": (roof["achieved"] / ceiling) if roof.get("achieved") else None}
 
 
 def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, precision_o,
@@ -556,7 +588,7 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
         kname = "kb_sweep_mfma"
     elif dim == 2 and width == 64 and E[0] == 25:
         # the variant the tile tuner chose for the finest level (1: the LDS walk)
-        kname = "kb_sweep2d_s64" if info[0].get("sweep_tile", 0) == 1 else "kb_sweep2d_s64w"
+        kname = "kb_sweep2d_s64" if info[0].get("sweep_tile", 0) == 1 else "kb_walk2d_s64"
     elif dim == 2:
         kname = "kb_sweep2d_wide" if width >= 16 else "kb_sweep2d"
     else:

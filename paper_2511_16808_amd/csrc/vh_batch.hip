@@ -96,13 +96,41 @@ __global__ __launch_bounds__(256) void kb_stencil(Grid g, int ls, const cpx<TC>*
   const size_t N = (size_t)g.N;
   const int S = 1 << ls;
   cpx<TC> acc = cmk<TC>(0, 0);
+  if (SHAPE == CROSS && g.offrule != 0) {
+    // the 5/7-point operator with fixed off-diagonals (the values the fine operator
+    // stores, so the result is the same): only the centre coefficient is read
+    const int c[3] = {cx, cy, cz}, n[3] = {g.nx, g.ny, g.nz};
+    double scale = 1.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
-              dz = shape_off<DIM, SHAPE>(k, 2);
-    if (inside_b(g, cx + dx, cy + dy, cz + dz)) {
-      const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-      acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[(size_t)j * S + s]), acc);
+    for (int d = 0; d < DIM; ++d)
+      if (g.offrule == 2 && (c[d] == 0 || c[d] == n[d] - 1)) scale *= 0.5;
+    acc = cfma(A[i], ccast<TC>(x[(size_t)i * S + s]), acc);
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      const int d = (k - 1) / 2;
+      const bool up = ((k - 1) & 1) != 0;
+      const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+                dz = shape_off<DIM, SHAPE>(k, 2);
+      // a neighbour outside the grid: the node's own value with weight 0 (no branch)
+      const bool ok = inside_b(g, cx + dx, cy + dy, cz + dz);
+      const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
+      const double wv = (g.offrule == 2 && ((up && lo) || (!up && hi))) ? -2.0 * g.ih2 : -g.ih2;
+      const TC ov = ok ? (TC)(scale * wv) : (TC)0;
+      const long long j =
+          ok ? (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz) : (long long)i;
+      const cpx<TC> xv = ccast<TC>(x[(size_t)j * S + s]);
+      acc.re = fma(ov, xv.re, acc.re);
+      acc.im = fma(ov, xv.im, acc.im);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
+                dz = shape_off<DIM, SHAPE>(k, 2);
+      if (inside_b(g, cx + dx, cy + dy, cz + dz)) {
+        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+        acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[(size_t)j * S + s]), acc);
+      }
     }
   }
   const size_t o = (size_t)i * S + s;
@@ -127,6 +155,137 @@ __device__ __forceinline__ void lds_barrier_s() {
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
+
+// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>)
+template <int B, int E, class F>
+__device__ __forceinline__ void bstatic_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    bstatic_for<B + 1, E>(f);
+  }
+}
+
+// 2D, 64 sources, walk without LDS: one wave = one grid row x 64 sources (lane = source)
+// walking along x over a strip of columns, for any radius-R stencil applied to 64 sources,
+// out = A x (APPLY), b - A x (RESID) or y + A x (ADD): the batched operator and residual
+// (A the level operator, [K][N]) and the assembled smoother (A the 5x5 stencil of B,
+// [25][Np] in the padded layout: u = B r from zero, u += B r).  Each lane keeps the
+// (2R+1) x (2R+1) window of its node in a register ring of 2R+1+P columns: a step loads
+// the next column (rows y - R .. y + R) straight from memory P steps before its first use
+// (the rows shared with the neighbouring rows' waves come from the caches), together with
+// the output operand and the node's K coefficients.  The coefficients are the same for
+// all 64 lanes: one load spreads a node's coefficient words over the lanes (lane l holds
+// 32-bit word l) and each coefficient is rebuilt from lane reads (SGPR operands of the
+// FMAs).  Coefficients that point outside the grid are exact zeros (no patch contains an
+// outside node, and the operators' boundary rows have none), so window values there may be
+// any finite in-grid value: loads go to clamped in-grid addresses and need no select, and
+// the ring turns have no branch, so the loads of later steps stay in flight.  No LDS and no
+// barrier: waves run independently.  The entries are summed in the same order as in the
+// LDS walks, so both give the same bits.
+template <int SHAPE, int MODE, class TC, class TX, class TY, int P, bool PADG>
+__global__ __launch_bounds__(256) void kb_walk2d_s64(Grid g, int tx, const cpx<TC>* __restrict__ A,
+                                                     const cpx<TX>* __restrict__ x,
+                                                     const cpx<TY>* __restrict__ b,
+                                                     cpx<TY>* __restrict__ y) {
+  constexpr int R = shape_radius<2, SHAPE>(), W = 2 * R + 1;
+  constexpr int K = shape_K<2, SHAPE>();
+  constexpr int RG = W + P;                                // column ring
+  constexpr int NW = 2 * K * (int)(sizeof(TC) / 4);        // coefficient words per node
+  constexpr int NL = (NW + 63) / 64;                       // coefficient loads per node
+  const int nsx = (g.nx + tx - 1) / tx;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int xs = (int)(blk % (unsigned)nsx) * tx;
+  const int yr = (int)(blk / (unsigned)nsx) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (yr >= g.ny) return;  // a whole wave; nothing below synchronises
+  const int lane = threadIdx.x & 63;
+  const int xe = min(xs + tx, g.nx);
+  const int nstep = xe - xs + 2 * R;  // step k loads column xs - R + k, outputs xs + k - 2R
+  size_t roff[W];                     // offsets of the window rows yr - R .. yr + R (clamped)
+#pragma unroll
+  for (int d = 0; d < W; ++d)
+    roff[d] = (size_t)lin_b(g, 0, min(max(yr - R + d, 0), g.ny - 1), 0) * 64 + lane;
+  const size_t ooff = (size_t)lin_b(g, 0, yr, 0) * 64 + lane;
+  const size_t cstride = PADG ? (size_t)g.Np : (size_t)g.N;
+  const size_t crow = PADG ? (size_t)linp_b(g, 0, yr, 0) : (size_t)lin_b(g, 0, yr, 0);
+  // lane l of a coefficient load reads word l (past the last word: word 0)
+  const unsigned* Aw = (const unsigned*)A;
+  constexpr int WPE = 2 * (int)(sizeof(TC) / 4);  // words per complex coefficient
+  size_t woff[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int wd = lane + 64 * q < NW ? lane + 64 * q : 0;
+    woff[q] = ((size_t)(wd / WPE) * cstride + crow) * WPE + (size_t)(wd % WPE);
+  }
+  cpx<TX> c[RG][W];
+  cpx<TY> of[RG];
+  unsigned gv[RG][NL];
+  auto fetch = [&](int k, auto sl) {
+    constexpr int SL = decltype(sl)::value;
+    const size_t cc = (size_t)min(max(xs - R + k, 0), g.nx - 1) * 64;
+#pragma unroll
+    for (int d = 0; d < W; ++d) c[SL][d] = x[roff[d] + cc];
+    const int xo = max(xs + k - 2 * R, xs);  // output of step k (k >= 2R in use)
+    if constexpr (MODE == OP_RESID) of[SL] = b[ooff + (size_t)xo * 64];
+    if constexpr (MODE == OP_ADD) of[SL] = y[ooff + (size_t)xo * 64];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) gv[SL][q] = Aw[woff[q] + (size_t)xo * WPE];
+  };
+  auto coef = [&](auto ph, auto ei) -> cpx<TC> {
+    constexpr int PH = decltype(ph)::value, e = decltype(ei)::value;
+    constexpr int w0 = e * WPE;
+    if constexpr (sizeof(TC) == 4) {
+      cpx<TC> v;
+      v.re = __int_as_float(__builtin_amdgcn_readlane((int)gv[PH][w0 / 64], w0 % 64));
+      v.im = __int_as_float(__builtin_amdgcn_readlane((int)gv[PH][(w0 + 1) / 64], (w0 + 1) % 64));
+      return v;
+    } else {
+      const int lo0 = __builtin_amdgcn_readlane((int)gv[PH][w0 / 64], w0 % 64);
+      const int hi0 = __builtin_amdgcn_readlane((int)gv[PH][(w0 + 1) / 64], (w0 + 1) % 64);
+      const int lo1 = __builtin_amdgcn_readlane((int)gv[PH][(w0 + 2) / 64], (w0 + 2) % 64);
+      const int hi1 = __builtin_amdgcn_readlane((int)gv[PH][(w0 + 3) / 64], (w0 + 3) % 64);
+      return cmk<TC>((TC)__hiloint2double(hi0, lo0), (TC)__hiloint2double(hi1, lo1));
+    }
+  };
+  // step k: fetch the column of step k + P (clamped: past the strip's end it loads in-grid
+  // values nobody uses), then (k >= 2R) the output xs + k - 2R
+  auto step = [&](int k, auto ph, bool out) {
+    constexpr int PH = decltype(ph)::value;  // k % RG
+    fetch(k + P, std::integral_constant<int, (PH + P) % RG>{});
+    if (out) {
+      const int xo = xs + k - 2 * R;
+      cpx<TC> acc = cmk<TC>(0, 0);
+      bstatic_for<0, K>([&](auto ei) {
+        constexpr int e = decltype(ei)::value;
+        constexpr int dx = shape_off<2, SHAPE>(e, 0), dy = shape_off<2, SHAPE>(e, 1);
+        acc = cfma(coef(ph, ei), ccast<TC>(c[(PH + dx - R + 2 * RG) % RG][dy + R]), acc);
+      });
+      const size_t o = ooff + (size_t)xo * 64;
+      if constexpr (MODE == OP_APPLY)
+        y[o] = ccast<TY>(acc);
+      else if constexpr (MODE == OP_RESID)
+        y[o] = ccast<TY>(ccast<TC>(of[PH]) - acc);
+      else
+        y[o] = ccast<TY>(ccast<TC>(of[PH]) + acc);
+    }
+  };
+  // the loads of every step are issued unconditionally and the main loop runs whole ring
+  // turns without a branch inside; the last partial turn is the only guarded code
+  bstatic_for<0, P>([&](auto i) { fetch(i.value, i); });
+  bstatic_for<0, 2 * R>([&](auto i) {
+    step(i.value, std::integral_constant<int, i.value % RG>{}, false);
+  });
+  int k0 = 2 * R;
+#pragma unroll 1
+  for (; k0 + RG <= nstep; k0 += RG)
+    bstatic_for<0, RG>([&](auto j) {
+      step(k0 + j.value, std::integral_constant<int, (2 * R + j.value) % RG>{}, true);
+    });
+  bstatic_for<0, RG - 1>([&](auto j) {
+    if (k0 + j.value < nstep)
+      step(k0 + j.value, std::integral_constant<int, (2 * R + j.value) % RG>{}, true);
+  });
+}
+
 
 template <int SHAPE, int MODE, class TC, class TX, class TY>
 __global__ __launch_bounds__(256) void kb_stencil2d_s64(Grid g, int tx,
@@ -242,6 +401,17 @@ __global__ __launch_bounds__(256) void kb_stencil2d_s64(Grid g, int tx,
   }
 }
 
+template <int SHAPE, int MODE, class TC, class TX, class TY, int P>
+static void launch_stencil_s64w(Grid g, int tx0, const void* A, const void* x, const void* b,
+                                void* y, hipStream_t st) {
+  const int nsx = (g.nx + tx0 - 1) / tx0;
+  const int tx = (g.nx + nsx - 1) / nsx;
+  const int nsx2 = (g.nx + tx - 1) / tx;
+  const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + 3) / 4);
+  kb_walk2d_s64<SHAPE, MODE, TC, TX, TY, P, false><<<nb, 256, 0, st>>>(
+      g, tx, (const cpx<TC>*)A, (const cpx<TX>*)x, (const cpx<TY>*)b, (cpx<TY>*)y);
+}
+
 template <int SHAPE, int MODE, class TC, class TX, class TY>
 static void launch_stencil_s64(Grid g, const void* A, const void* x, const void* b, void* y,
                                hipStream_t st) {
@@ -253,17 +423,32 @@ static void launch_stencil_s64(Grid g, const void* A, const void* x, const void*
       g, tx, (const cpx<TC>*)A, (const cpx<TX>*)x, (const cpx<TY>*)b, (cpx<TY>*)y);
 }
 
+// 64-source 2D stencil by tile code (as the sweep's: 1 = the LDS walk, 2..7 = the
+// independent-wave walk with prefetch 2 or 3 over strips of 16, 32 or 64 columns)
+template <int SHAPE, int MODE, class TC, class TX, class TY>
+static void launch_stencil_s64_tile(int tile, Grid g, const void* A, const void* x, const void* b,
+                                    void* y, hipStream_t st) {
+  static constexpr int TXS[3] = {16, 32, 64};
+  if (tile == 0) tile = S64_DEFAULT_TILE;
+  if (tile <= 1 || tile > S64_TILES)
+    launch_stencil_s64<SHAPE, MODE, TC, TX, TY>(g, A, x, b, y, st);
+  else if (tile <= 4)
+    launch_stencil_s64w<SHAPE, MODE, TC, TX, TY, 2>(g, TXS[tile - 2], A, x, b, y, st);
+  else
+    launch_stencil_s64w<SHAPE, MODE, TC, TX, TY, 3>(g, TXS[tile - 5], A, x, b, y, st);
+}
+
 template <int DIM, int SHAPE, class TC, class TX, class TY>
 static hipError_t bstencil_t(Grid g, int ls, int mode, const void* A, const void* x, const void* b,
-                             void* y, hipStream_t st) {
+                             void* y, hipStream_t st, int tile) {
   if constexpr (DIM == 2 && SHAPE != BOX3) {
     if (ls == 6) {
       if (mode == OP_APPLY)
-        launch_stencil_s64<SHAPE, OP_APPLY, TC, TX, TY>(g, A, x, b, y, st);
+        launch_stencil_s64_tile<SHAPE, OP_APPLY, TC, TX, TY>(tile, g, A, x, b, y, st);
       else if (mode == OP_RESID)
-        launch_stencil_s64<SHAPE, OP_RESID, TC, TX, TY>(g, A, x, b, y, st);
+        launch_stencil_s64_tile<SHAPE, OP_RESID, TC, TX, TY>(tile, g, A, x, b, y, st);
       else
-        launch_stencil_s64<SHAPE, OP_ADD, TC, TX, TY>(g, A, x, b, y, st);
+        launch_stencil_s64_tile<SHAPE, OP_ADD, TC, TX, TY>(tile, g, A, x, b, y, st);
       VHB_CHECK();
       return hipSuccess;
     }
@@ -285,27 +470,29 @@ static hipError_t bstencil_t(Grid g, int ls, int mode, const void* A, const void
 
 template <int DIM, int SHAPE>
 static hipError_t bstencil_p(Grid g, int ls, int mode, int pc, const void* A, int px,
-                             const void* x, int py, const void* b, void* y, hipStream_t st) {
+                             const void* x, int py, const void* b, void* y, hipStream_t st,
+                             int tile) {
   if (pc == PREC_F64 && px == PREC_F64 && py == PREC_F64)
-    return bstencil_t<DIM, SHAPE, double, double, double>(g, ls, mode, A, x, b, y, st);
+    return bstencil_t<DIM, SHAPE, double, double, double>(g, ls, mode, A, x, b, y, st, tile);
   if (pc == PREC_F32 && px == PREC_F32 && py == PREC_F32)
-    return bstencil_t<DIM, SHAPE, float, float, float>(g, ls, mode, A, x, b, y, st);
+    return bstencil_t<DIM, SHAPE, float, float, float>(g, ls, mode, A, x, b, y, st, tile);
   if (pc == PREC_F64 && px == PREC_F32 && py == PREC_F64)
-    return bstencil_t<DIM, SHAPE, double, float, double>(g, ls, mode, A, x, b, y, st);
+    return bstencil_t<DIM, SHAPE, double, float, double>(g, ls, mode, A, x, b, y, st, tile);
   return hipErrorInvalidValue;
 }
 
 hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,
-                         int px, const void* x, int py, const void* b, void* y, hipStream_t st) {
+                         int px, const void* x, int py, const void* b, void* y, hipStream_t st,
+                         int tile) {
   if (dim == 2) {
-    if (shape == CROSS) return bstencil_p<2, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
-    if (shape == BOX1) return bstencil_p<2, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);
-    if (shape == BOX2) return bstencil_p<2, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st);
-    if (shape == BOX3) return bstencil_p<2, BOX3>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == CROSS) return bstencil_p<2, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
+    if (shape == BOX1) return bstencil_p<2, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
+    if (shape == BOX2) return bstencil_p<2, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
+    if (shape == BOX3) return bstencil_p<2, BOX3>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
   } else {
-    if (shape == CROSS) return bstencil_p<3, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st);
-    if (shape == BOX1) return bstencil_p<3, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st);
-    if (shape == BOX2) return bstencil_p<3, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st);
+    if (shape == CROSS) return bstencil_p<3, CROSS>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
+    if (shape == BOX1) return bstencil_p<3, BOX1>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
+    if (shape == BOX2) return bstencil_p<3, BOX2>(g, ls, mode, pc, A, px, x, py, b, y, st, tile);
   }
   return hipErrorInvalidValue;
 }
@@ -580,108 +767,6 @@ __global__ __launch_bounds__(256) void kb_sweep2d_s64(Grid g, int tx,
   }
 }
 
-// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>)
-template <int B, int E, class F>
-__device__ __forceinline__ void bstatic_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    bstatic_for<B + 1, E>(f);
-  }
-}
-
-// 2D, 64 sources, walk without LDS: one wave = one grid row x 64 sources (lane = source)
-// walking along x over a strip of columns.  Each lane keeps the 5 x 5 residual window of
-// its node in a register ring of 5 + P columns: a step loads the next column (rows
-// y - 2 .. y + 2) straight from memory, P steps before its first use (the rows shared with
-// the neighbouring rows' waves come from the caches), together with u of the output of
-// that step and the node's smoother entries.  The entries are the same for all 64 lanes:
-// in complex64 one load spreads a node's 25 entries over the lanes (lane l holds float l)
-// and each is broadcast to an SGPR operand of the FMAs by a lane read; in complex128 they
-// are read through the scalar unit.  Loads go to clamped in-range addresses and out-of-grid
-// values are selected to zero afterwards, so the step has no branch and the loads of later
-// steps stay in flight.  No LDS and no barrier: waves run independently.
-template <int FORM, bool ZERO, class T, int P>
-__global__ __launch_bounds__(256) void kb_sweep2d_s64w(Grid g, int tx,
-                                                       const cpx<T>* __restrict__ G,
-                                                       const cpx<T>* __restrict__ r,
-                                                       cpx<T>* __restrict__ u) {
-  // the assembled stencil: its entries that point outside the grid are exact zeros (no
-  // patch contains an outside node), so the window may hold any finite in-grid values
-  // there; loads go to clamped in-grid addresses and need no select
-  static_assert(FORM == 2, "the walk relies on the zero entries of the assembled stencil");
-  constexpr int E = bsm_entries<2, FORM>();
-  constexpr int R = 5 + P;  // column ring: the window of 5 plus P in flight
-  constexpr bool LANE_G = sizeof(T) == 4 && 2 * E <= 64;
-  const int nsx = (g.nx + tx - 1) / tx;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const int xs = (int)(b % (unsigned)nsx) * tx;
-  const int y = (int)(b / (unsigned)nsx) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (y >= g.ny) return;  // a whole wave; nothing below synchronises
-  const int lane = threadIdx.x & 63;
-  const int xe = min(xs + tx, g.nx);
-  const int nstep = xe - xs + 4;  // step k loads column xs - 2 + k and outputs xs + k - 4
-  size_t roff[5];                 // offsets of the window rows y - 2 .. y + 2 (clamped)
-#pragma unroll
-  for (int d = 0; d < 5; ++d) roff[d] = (size_t)lin_b(g, 0, min(max(y - 2 + d, 0), g.ny - 1), 0) * 64 + lane;
-  const size_t uoff = (size_t)lin_b(g, 0, y, 0) * 64 + lane;
-  const size_t Np = (size_t)g.Np;
-  const size_t grow = (size_t)linp_b(g, 0, y, 0);  // entry e of node x at G[e * Np + grow + x]
-  // lane l of an entries load reads float (l & 1) of entry l >> 1 (lanes past 2E: entry 0)
-  const size_t gl = 2 * ((size_t)(lane < 2 * E ? lane >> 1 : 0) * Np + grow) + (lane & 1);
-  const T* Gf = (const T*)G;
-  cpx<T> c[R][5];
-  cpx<T> uf[R];
-  T gv[R];
-  const cpx<T> zero = cmk<T>(0, 0);
-  auto fetch = [&](int k, auto sl) {
-    constexpr int SL = decltype(sl)::value;
-    const size_t cc = (size_t)min(max(xs - 2 + k, 0), g.nx - 1) * 64;
-#pragma unroll
-    for (int d = 0; d < 5; ++d) c[SL][d] = r[roff[d] + cc];
-    const int xo = max(xs + k - 4, xs);  // output of step k (k >= 4 in use)
-    if (!ZERO) uf[SL] = u[uoff + (size_t)xo * 64];
-    if constexpr (LANE_G) gv[SL] = Gf[gl + 2 * (size_t)xo];
-  };
-  // step k: fetch the column of step k + P (clamped: past the strip's end it loads in-grid
-  // values nobody uses), then (k >= 4) the output xs + k - 4
-  auto step = [&](int k, auto ph, bool out) {
-    constexpr int PH = decltype(ph)::value;  // k % R
-    fetch(k + P, std::integral_constant<int, (PH + P) % R>{});
-    if (out) {
-      const int x = xs + k - 4;
-      cpx<T> acc = zero;
-      bstatic_for<0, E>([&](auto ei) {
-        constexpr int e = decltype(ei)::value;
-        constexpr int dx = bsm_off<2, FORM>(e, 0), dy = bsm_off<2, FORM>(e, 1);
-        cpx<T> ge;
-        if constexpr (LANE_G) {
-          ge.re = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[PH]), 2 * e));
-          ge.im = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[PH]), 2 * e + 1));
-        } else {
-          ge = G[(size_t)e * Np + grow + x];
-        }
-        acc = cfma(ge, c[(PH + dx - 2 + 2 * R) % R][dy + 2], acc);
-      });
-      u[uoff + (size_t)x * 64] = ZERO ? acc : (uf[PH] + acc);
-    }
-  };
-  // the loads of every step are issued unconditionally and the main loop runs whole ring
-  // turns without a branch inside, so the loads of later steps stay in flight across the
-  // waits of the current one; the last partial turn is the only guarded code
-  bstatic_for<0, P>([&](auto i) { fetch(i.value, i); });
-  bstatic_for<0, 4>([&](auto i) { step(i.value, std::integral_constant<int, i.value % R>{}, false); });
-  int k0 = 4;
-#pragma unroll 1
-  for (; k0 + R <= nstep; k0 += R)
-    bstatic_for<0, R>([&](auto j) {
-      step(k0 + j.value, std::integral_constant<int, (4 + j.value) % R>{}, true);
-    });
-  bstatic_for<0, R - 1>([&](auto j) {
-    if (k0 + j.value < nstep)
-      step(k0 + j.value, std::integral_constant<int, (4 + j.value) % R>{}, true);
-  });
-}
-
 template <int FORM, class T>
 static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero, hipStream_t st) {
   // balanced strips of at most B64_TX columns
@@ -700,17 +785,18 @@ static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero,
 template <int FORM, class T, int P>
 static void launch_s64w(Grid g, int tx0, const void* G, const void* r, void* u, bool zero,
                         hipStream_t st) {
+  static_assert(FORM == 2, "the walk relies on the zero entries of the assembled stencil");
   // balanced strips of at most tx0 columns; blocks of 4 rows (4 independent waves)
   const int nsx = (g.nx + tx0 - 1) / tx0;
   const int tx = (g.nx + nsx - 1) / nsx;
   const int nsx2 = (g.nx + tx - 1) / tx;
   const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + 3) / 4);
   if (zero)
-    kb_sweep2d_s64w<FORM, true, T, P><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
-                                                          (const cpx<T>*)r, (cpx<T>*)u);
+    kb_walk2d_s64<BOX2, OP_APPLY, T, T, T, P, true><<<nb, 256, 0, st>>>(
+        g, tx, (const cpx<T>*)G, (const cpx<T>*)r, nullptr, (cpx<T>*)u);
   else
-    kb_sweep2d_s64w<FORM, false, T, P><<<nb, 256, 0, st>>>(g, tx, (const cpx<T>*)G,
-                                                           (const cpx<T>*)r, (cpx<T>*)u);
+    kb_walk2d_s64<BOX2, OP_ADD, T, T, T, P, true><<<nb, 256, 0, st>>>(
+        g, tx, (const cpx<T>*)G, (const cpx<T>*)r, nullptr, (cpx<T>*)u);
 }
 
 // 64-source 2D assembled sweep by tile code (S64_TILES candidates, 1-based): 1 = the LDS

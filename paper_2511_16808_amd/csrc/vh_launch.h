@@ -123,16 +123,18 @@ hipError_t batch_gather(long long N, int S, int nsrc, const cpx<double>* q, cpx<
                         hipStream_t st);
 hipError_t batch_scatter(long long N, int S, int nsrc, const cpx<double>* X, cpx<double>* u,
                          hipStream_t st);
+// tile: the 64-source 2D sweep and stencil variant, 1 .. S64_TILES (0 = the default);
+// ignored by every other form and batch width
+constexpr int S64_TILES = 7;
+constexpr int S64_DEFAULT_TILE = 7;
+// tile: the 64-source 2D variant as for batch_sweep (0 = the default)
 hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,
-                         int px, const void* x, int py, const void* b, void* y, hipStream_t st);
+                         int px, const void* x, int py, const void* b, void* y, hipStream_t st,
+                         int tile = 0);
 // batched 2D Full-patch sweep on MFMA (1 << ls sources, ls in 4..6, complex64):
 // split = 0 FP32, 1 split BF16; txp = 16 or 32 patches per strip row; rows per block
 hipError_t batch_sweep_mfma(Grid g, int ls, int split, int txp, int rows, const void* G,
                             const void* r, void* u, bool zero, hipStream_t st);
-// tile: the 64-source 2D assembled sweep's variant, 1 .. S64_TILES (0 = the default);
-// ignored by every other form and batch width
-constexpr int S64_TILES = 7;
-constexpr int S64_DEFAULT_TILE = 7;
 hipError_t batch_sweep(int dim, int form, Grid g, int ls, int prec, const void* G, const void* r,
                        void* u, bool zero, hipStream_t st, int tile = 0);
 hipError_t batch_restrict(int dim, int rf, Grid gf, Grid gc, int ls, int prec, const void* r,

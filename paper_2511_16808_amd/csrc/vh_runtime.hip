@@ -74,7 +74,8 @@ struct Level {
                                           // SM_SYMHALF = its symmetric half
   int mfma_txp[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned matrix-core sweep tile per log2(S)
   int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
-  int s64_tile = 0;  // variant of the 64-source 2D assembled sweep (0: not chosen yet)
+  int s64_tile = 0;   // variant of the 64-source 2D assembled sweep (0: not chosen yet)
+  int s64_stile = 0;  // variant of the 64-source 2D stencil (operator, residual)
 };
 
 }  // namespace
@@ -773,9 +774,10 @@ vh_status tune_mfma(vh_handle* hd, int ls) {
   return st;
 }
 
-// Variant of the 64-source 2D assembled sweep for every smoothed level: the caller's
-// vh_options.sweep_tile, else the fastest of the S64_TILES candidates timed with HIP
-// events on the level's own grid (one warm-up and three timed launches each).  The
+// Variants of the 64-source 2D assembled sweep and of the 64-source 2D stencil (residual,
+// operator) for every smoothed level: the caller's vh_options.sweep_tile, else the fastest
+// of the S64_TILES candidates of each, timed with HIP events on the level's own grid (one
+// warm-up and three timed launches each).  The
 // choice depends only on the device, the grid and the precision, so it is kept for the
 // process and reused by later handles; every candidate computes the same sums in the same
 // order, so the choice does not change any result bit.
@@ -790,17 +792,18 @@ vh_status tune_s64(vh_handle* hd, int ls) {
   vh_status st = VH_OK;
   for (int l = 0; l + 1 < hd->levels && st == VH_OK; ++l) {
     Level& Lv = hd->L[l];
-    if (Lv.form != 2 || Lv.s64_tile) continue;
+    if (Lv.s64_tile) continue;
     if (hd->opt.sweep_tile > 0) {
-      Lv.s64_tile = hd->opt.sweep_tile;
+      Lv.s64_tile = Lv.s64_stile = hd->opt.sweep_tile;
       continue;
     }
-    const auto key = std::make_tuple(dev, Lv.g.nx, Lv.g.ny, hd->prec);
+    const auto key = std::make_tuple(dev, Lv.g.nx, Lv.g.ny, hd->prec * 16 + Lv.shape * 4 + Lv.form);
     {
       std::lock_guard<std::mutex> lock(g_tile_mu);
       auto it = g_tile_cache.find(key);
       if (it != g_tile_cache.end()) {
-        Lv.s64_tile = it->second;
+        Lv.s64_tile = it->second & 0xff;
+        Lv.s64_stile = it->second >> 8;
         continue;
       }
     }
@@ -816,31 +819,41 @@ vh_status tune_s64(vh_handle* hd, int ls) {
       st = fail(VH_EDEVICE, "fill failed");
       break;
     }
-    float best = 1e30f;
-    int btile = S64_DEFAULT_TILE;
-    for (int t = 1; t <= S64_TILES; ++t) {
-      float ms = 0.f;
-      hipError_t e = batch_sweep(2, 2, Lv.g, ls, hd->prec, Lv.B, hd->br[l], hd->bu[l], false,
-                                 hd->s, t);
-      if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
-      for (int k = 0; k < 3 && e == hipSuccess; ++k)
-        e = batch_sweep(2, 2, Lv.g, ls, hd->prec, Lv.B, hd->br[l], hd->bu[l], false, hd->s, t);
-      if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = fail(VH_EDEVICE, std::string("sweep tile timing: ") + hipGetErrorString(e));
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        btile = t;
+    // which = 0: the sweep (assembled form only), 1: the residual with the level operator
+    int chosen[2] = {S64_DEFAULT_TILE, S64_DEFAULT_TILE};
+    for (int which = 0; which < 2 && st == VH_OK; ++which) {
+      if (which == 0 && Lv.form != 2) continue;
+      auto launch = [&](int t) {
+        return which == 0 ? batch_sweep(2, 2, Lv.g, ls, hd->prec, Lv.B, hd->br[l], hd->bu[l],
+                                        false, hd->s, t)
+                          : batch_stencil(2, Lv.shape, Lv.g, ls, OP_RESID, hd->prec, Lv.A,
+                                          hd->prec, hd->bu[l], hd->prec, hd->bu[l], hd->br[l],
+                                          hd->s, t);
+      };
+      float best = 1e30f;
+      for (int t = 1; t <= S64_TILES; ++t) {
+        float ms = 0.f;
+        hipError_t e = launch(t);
+        if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = launch(t);
+        if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = fail(VH_EDEVICE, std::string("tile timing: ") + hipGetErrorString(e));
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          chosen[which] = t;
+        }
       }
     }
     if (st != VH_OK) break;
-    Lv.s64_tile = btile;
+    Lv.s64_tile = chosen[0];
+    Lv.s64_stile = chosen[1];
     std::lock_guard<std::mutex> lock(g_tile_mu);
-    g_tile_cache[key] = btile;
+    g_tile_cache[key] = chosen[0] | (chosen[1] << 8);
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -851,7 +864,7 @@ vh_status bresidual(vh_handle* hd, int l, int ls, const void* q, const void* u, 
   Level& Lv = hd->L[l];
   count(hd, (double)Lv.g.N, (double)hd->esz * (coef_reads(Lv) + 3 * (1 << ls)));
   VH_HIP(batch_stencil(hd->dim, Lv.shape, Lv.g, ls, OP_RESID, hd->prec, Lv.A, hd->prec, u,
-                       hd->prec, q, r, hd->s));
+                       hd->prec, q, r, hd->s, Lv.s64_stile));
   return VH_OK;
 }
 
@@ -993,7 +1006,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
       hd->tend(tk);
       count(hd, (double)N, 16.0 * k0 + S * (hd->esz + 16.0));
       VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_APPLY, PREC_F64, hd->Hfine, hd->prec, Zj(j),
-                           PREC_F64, nullptr, Vj(j + 1), s));
+                           PREC_F64, nullptr, Vj(j + 1), s, hd->L[0].s64_stile));
       count(hd, dNS, 16.0 * (2 * j + 6) + (lo ? 8.0 : 0.0));  // passes A and B
       VH_HIP(batch_dcgs_a(hd->bV, ldv, j, j + 1, N, ls, hd->bpart, hd->bnred, K, s));
       VH_HIP(batch_dcgs_fin(K, j, S, 0, s));
@@ -1023,7 +1036,7 @@ vh_status fgmres_batch(vh_handle* hd, const cpx<double>* q, int nsrc, cpx<double
     VH_HIP(batch_update_x(K, kmax, hd->prec, hd->bZ, ldv, hd->bX, N, ls, s));
     count(hd, (double)N, 16.0 * k0 + S * 48.0 + 48.0 * S);  // true residual, norm and scale
     VH_HIP(batch_stencil(hd->dim, hd->L[0].shape, g0, ls, OP_RESID, PREC_F64, hd->Hfine, PREC_F64, hd->bX,
-                         PREC_F64, hd->bQ, Vj(0), s));
+                         PREC_F64, hd->bQ, Vj(0), s, hd->L[0].s64_stile));
     VH_HIP(batch_cgs(2, hd->bV, ldv, 0, K->h2, Vj(0), N, ls, hd->bpart, hd->bnred, K->nrm2, s));
     VH_HIP(batch_cycle_init(K, m, S, s));
     VH_HIP(batch_scale(K, Vj(0), Vj(0), N, ls, s));

@@ -287,7 +287,10 @@ def vcycle_bytes(levels_info, dim, esz, smoother_entries, S=1):
         K, E = info["stencil_points"], smoother_entries[l]
         if l == 0 and K == 2 * dim + 1:
             K = 1  # 5/7-point operator: only the centre entries are read (fixed off-diagonals)
-        total += N * esz * (2 * E + 2 * K) + N * S * esz * 15 + Nc * S * esz * 2
+        # a residual formed inside the sweep is neither stored nor read back (3 vectors
+        # fewer); inside the restriction, 2 fewer
+        vec = 15 - 3 * info.get("fused_sweep", 0) - 2 * info.get("fused_restrict", 0)
+        total += N * esz * (2 * E + 2 * K) + N * S * esz * vec + Nc * S * esz * 2
     return total
 
 
@@ -424,6 +427,9 @@ def main():
                     help="override: sources one after another (0) or sharing each sweep (1)")
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
                     help="override the preconditioner precision")
+    ap.add_argument("--split-residual", action="store_true",
+                    help="separate residual launches instead of the residual formed inside "
+                         "the sweep and the restriction (same results)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -452,13 +458,14 @@ def main():
         del src, dst
     ceiling = copy_ceiling()
     out = run_workload(args.workload, args.steps, args.warmup, args.smoother, args.contraction,
-                       args.batch, args.precision, not args.no_cpu_baseline)
+                       args.batch, args.precision, not args.no_cpu_baseline,
+                       args.split_residual)
     out["roofline"].update(ceiling_fields(out["roofline"], ceiling))
     if args.workload == DEFAULT_WORKLOAD and args.c4_steps > 0:
         # the 512^2 half of the metric: 64 sources through one hierarchy, timed after the
         # 256^3 steps (its own warm-up, steps, roofline and CPU baseline)
         c4 = run_workload("c4", args.c4_steps, 1, None, "valu", None, None,
-                          not args.no_cpu_baseline)
+                          not args.no_cpu_baseline, args.split_residual)
         c4["roofline"].update(ceiling_fields(c4["roofline"], ceiling))
         out["c4"] = {k: c4[k] for k in ("metric", "value", "unit", "steps", "warmup",
                                         "ms_per_step", "dtype", "config", "iterations",
@@ -500,7 +507,7 @@ def ceiling_fields(roof, ceiling):
 
 
 def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, precision_o,
-                 with_cpu):
+                 with_cpu, split=False):
     """Times `steps` whole passes (setup + solve + destroy) of one workload after `warmup`
     untimed ones; returns the JSON object of the benchmark line."""
     import numpy as np
@@ -513,6 +520,7 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     args.workload, args.steps, args.warmup = key, steps, warmup
     args.smoother, args.contraction, args.batch, args.precision = (smoother_name, contraction_name,
                                                                     batch_o, precision_o)
+    args.split_residual = split
     w = dict(WORKLOADS[args.workload], key=args.workload)
     if args.smoother is None:
         args.smoother = w.get("smoother", "assembled")
@@ -539,7 +547,7 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     opt = B.make_options(precision=precision, restart=w["restart"], damping=w["damping"],
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
-                         contraction=contraction)
+                         contraction=contraction, split_residual=int(args.split_residual))
     if w.get("fine_patch"):
         opt.fine_patch = PATCHES[w["fine_patch"]]
     torch.cuda.synchronize()
@@ -580,7 +588,14 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     # dominant kernel: finest-level additive-Vanka sweep u += B r
     n_l = sum(r["stats"]["smooth1_launches"] for r in runs)
     ms_l = sum(r["stats"]["smooth1_ms"] for r in runs)
-    bytes_per_launch = N * esz * (E[0] + 3 * width)
+    fused0 = width == 1 and info[0].get("fused_sweep", 0) == 1
+    if fused0:
+        # u_out = u_in + B (q - A u_in): the smoother entries, the operator's coefficients
+        # (the centre entries of the 5/7-point finest operator) and q, u_in, u_out
+        K0 = 1 if info[0]["stencil_points"] == 2 * dim + 1 else info[0]["stencil_points"]
+        bytes_per_launch = N * esz * (E[0] + K0 + 3)
+    else:
+        bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
     if width == 1:
         kname = "k_vanka_sweep_sym" if args.smoother == "symmetric" else "k_vanka_sweep"
@@ -646,9 +661,13 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
         "bytes_moved_per_step": moved,
         "solve_GBps": moved / (solve_ms * 1e-3) / 1e9 if solve_ms > 0 else None,
         "c_f": (float(np.mean(cfs)) if cfs else None),
+        # per smoothed level: [residual formed in the sweep, in the restriction]
+        "fused": [[i.get("fused_sweep", 0), i.get("fused_restrict", 0)] for i in info[:-1]],
         "roofline": {
             **roof,
-            "kernel": f"finest-level additive Vanka sweep u += B r ({kname}, {width} source(s)"
+            "kernel": ("finest-level additive Vanka sweep u += B (q - A u), residual formed "
+                       "in the sweep" if fused0 else "finest-level additive Vanka sweep u += B r")
+                      + f" ({kname}, {width} source(s)"
                       + (f", tile {info[0]['sweep_tile']}" if info[0].get("sweep_tile") else "") + ")",
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,

@@ -147,6 +147,14 @@ typedef struct vh_options {
                                the 7 variants, timed on each level's grid at the first
                                64-source solve and kept for the process; 1..7 forces one.
                                The variants give identical results */
+    int split_residual;     /* where the residual q - A u is formed: inside the kernel
+                               that consumes it (the 2D smoothing sweep, Sec. 3.2 eq.
+                               (smoother); the restriction of the two-grid cycle, Sec. 2.2,
+                               2D and 3D-trilinear), so that it is never stored, or by a
+                               separate residual launch.  0 (default): per level, whichever
+                               is faster, timed at setup on the level's own grid and kept
+                               for the process; 1: always separate; 2: inside wherever such
+                               a kernel exists.  Results are identical bit for bit */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -185,6 +193,8 @@ typedef struct vh_level_info {
     int mfma_tile;          /* patches per strip row chosen by the tuner (16 or 32)      */
     int mfma_rows;          /* rows per block chosen by the tuner                        */
     int sweep_tile;         /* variant of the 64-source 2D sweep in use (0: none chosen)  */
+    int fused_sweep;        /* 1: the level's smoothing steps form the residual in the sweep */
+    int fused_restrict;     /* 1: the restriction to the next level forms the residual    */
 } vh_level_info;
 
 typedef struct vh_handle vh_handle;

@@ -53,7 +53,7 @@ class vh_options(ctypes.Structure):
         ("damping", ctypes.c_double * 16), ("stream", ctypes.c_void_p), ("timing", ctypes.c_int),
         ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("fine_patch", ctypes.c_int),
         ("cycle", ctypes.c_int),
-        ("contraction", ctypes.c_int), ("sweep_tile", ctypes.c_int),
+        ("contraction", ctypes.c_int), ("sweep_tile", ctypes.c_int), ("split_residual", ctypes.c_int),
     ]
 
 
@@ -76,7 +76,8 @@ class vh_level_info(ctypes.Structure):
         ("n", ctypes.c_int * 3), ("stencil_points", ctypes.c_int),
         ("smoother_entries", ctypes.c_int), ("offsets", (ctypes.c_int * 3) * 125),
         ("bytes", ctypes.c_size_t), ("mfma_sources", ctypes.c_int), ("mfma_tile", ctypes.c_int),
-        ("mfma_rows", ctypes.c_int), ("sweep_tile", ctypes.c_int),
+        ("mfma_rows", ctypes.c_int), ("sweep_tile", ctypes.c_int), ("fused_sweep", ctypes.c_int),
+        ("fused_restrict", ctypes.c_int),
     ]
 
 
@@ -282,6 +283,7 @@ def vh_get_level_info(hd, level):
         "offsets": [tuple(info.offsets[k]) for k in range(K)], "bytes": info.bytes,
         "mfma_sources": info.mfma_sources, "mfma_tile": info.mfma_tile,
         "mfma_rows": info.mfma_rows, "sweep_tile": info.sweep_tile,
+        "fused_sweep": info.fused_sweep, "fused_restrict": info.fused_restrict,
     }
 
 

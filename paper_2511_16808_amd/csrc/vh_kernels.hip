@@ -234,19 +234,12 @@ hipError_t check_media(long long N, const double* kappa, const double* gamma, in
   return hipSuccess;
 }
 
-// ------------------------------------------------------------------ stencil sweep
-// y = A x (APPLY), y = b - A x (RESID), y += A x (ADD); A stored [K][N] in TC,
-// accumulation in TC.  Coefficients that point outside the grid are zero by
-// construction, so those neighbours are skipped.
-template <int DIM, int SHAPE, int MODE, class TC, class TX, class TY>
-__global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restrict__ A,
-                                                 const cpx<TX>* __restrict__ x,
-                                                 const cpx<TY>* __restrict__ b,
-                                                 cpx<TY>* __restrict__ y) {
-  const unsigned i = node_id();
-  if (i >= g.N) return;
-  int cx, cy, cz;
-  decode(i, g, cx, cy, cz);
+// (A x)_i at node i = (cx, cy, cz), accumulated in TC.  Shared by the stencil sweep and
+// the kernels that form the residual on the fly, so that both give the same bits.
+template <int DIM, int SHAPE, class TC, class TX>
+__device__ __forceinline__ cpx<TC> stencil_acc(const Grid& g, const cpx<TC>* __restrict__ A,
+                                               const cpx<TX>* x, long long i, int cx, int cy,
+                                               int cz) {
   constexpr int K = shape_K<DIM, SHAPE>();
   const size_t N = (size_t)g.N;
   cpx<TC> acc = cmk<TC>(0, 0);
@@ -270,23 +263,62 @@ __global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restri
       const bool lo = c[d] == 0, hi = c[d] == n[d] - 1;
       const double wv = (g.offrule == 2 && ((up && lo) || (!up && hi))) ? -2.0 * g.ih2 : -g.ih2;
       const TC ov = ok ? (TC)(scale * wv) : (TC)0;
-      const long long j =
-          ok ? (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz) : (long long)i;
+      const long long j = ok ? i + dx + (long long)g.nx * (dy + (long long)g.ny * dz) : i;
       const cpx<TC> xv = ccast<TC>(x[j]);
       acc.re = fma(ov, xv.re, acc.re);
       acc.im = fma(ov, xv.im, acc.im);
     }
   } else {
+    // a coefficient that points outside the grid is an exact zero, so its term is taken
+    // with the node's own value in place of the missing neighbour: every load is issued
+    // unconditionally and the loads of all K terms can be in flight together
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int dx = shape_off<DIM, SHAPE>(k, 0), dy = shape_off<DIM, SHAPE>(k, 1),
                 dz = shape_off<DIM, SHAPE>(k, 2);
-      if (inside(g, cx + dx, cy + dy, cz + dz)) {
-        const long long j = (long long)i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-        acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[j]), acc);
-      }
+      const bool ok = inside(g, cx + dx, cy + dy, cz + dz);
+      const long long j = ok ? i + dx + (long long)g.nx * (dy + (long long)g.ny * dz) : i;
+      acc = cfma(A[(size_t)k * N + i], ccast<TC>(x[j]), acc);
     }
   }
+  return acc;
+}
+
+// the residual at tile node (gx, gy, gz), zero outside the grid: evaluated at the node
+// clamped into the grid, so that no load depends on a branch
+template <int DIM, int SHAPE, class T>
+__device__ __forceinline__ cpx<T> resid_tile(const Grid& g, const cpx<T>* __restrict__ A,
+                                             const cpx<T>* __restrict__ q, const cpx<T>* u,
+                                             bool valid, int gx, int gy, int gz) {
+  const bool in = valid && inside(g, gx, gy, gz);
+  const int cx = min(max(gx, 0), g.nx - 1), cy = min(max(gy, 0), g.ny - 1);
+  const int cz = (DIM == 3) ? min(max(gz, 0), g.nz - 1) : 0;
+  const cpx<T> rv = resid_at<DIM, SHAPE, T>(g, A, q, u, lin(g, cx, cy, cz), cx, cy, cz);
+  return in ? rv : cmk<T>(0, 0);
+}
+
+// the residual q - A u at node i, in T (the value the OP_RESID sweep stores)
+template <int DIM, int SHAPE, class T>
+__device__ __forceinline__ cpx<T> resid_at(const Grid& g, const cpx<T>* __restrict__ A,
+                                           const cpx<T>* __restrict__ q, const cpx<T>* u,
+                                           long long i, int cx, int cy, int cz) {
+  return q[i] - stencil_acc<DIM, SHAPE, T, T>(g, A, u, i, cx, cy, cz);
+}
+
+// ------------------------------------------------------------------ stencil sweep
+// y = A x (APPLY), y = b - A x (RESID), y += A x (ADD); A stored [K][N] in TC,
+// accumulation in TC.  Coefficients that point outside the grid are zero by
+// construction, so those neighbours are skipped.
+template <int DIM, int SHAPE, int MODE, class TC, class TX, class TY>
+__global__ __launch_bounds__(256) void k_stencil(Grid g, const cpx<TC>* __restrict__ A,
+                                                 const cpx<TX>* __restrict__ x,
+                                                 const cpx<TY>* __restrict__ b,
+                                                 cpx<TY>* __restrict__ y) {
+  const unsigned i = node_id();
+  if (i >= g.N) return;
+  int cx, cy, cz;
+  decode(i, g, cx, cy, cz);
+  const cpx<TC> acc = stencil_acc<DIM, SHAPE, TC, TX>(g, A, x, (long long)i, cx, cy, cz);
   if (MODE == OP_APPLY) {
     y[i] = ccast<TY>(acc);
   } else if (MODE == OP_RESID) {
@@ -380,10 +412,17 @@ __host__ __device__ constexpr int sm_off(int e, int c) {
                                patch_off<DIM, FORM>(e / patch_Np<DIM, FORM>(), c);
 }
 
-template <int DIM, int FORM, bool ZERO, class T>
+// RS >= 0 (the stencil shape of A): the residual is formed in the tile stage from
+// r := q, A and u_in (q - A u_in at every tile node, halo included), and the result
+// u_in + B (q - A u_in) goes to u, a different array (the halo reads u_in of the
+// neighbouring tiles, so the update cannot be in place).  RS < 0: r is read, and u is
+// updated in place (u_in unused).
+template <int DIM, int FORM, bool ZERO, class T, int RS = -1>
 __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __restrict__ G,
                                                      const cpx<T>* __restrict__ r,
-                                                     cpx<T>* __restrict__ u) {
+                                                     cpx<T>* __restrict__ u,
+                                                     const cpx<T>* __restrict__ A = nullptr,
+                                                     const cpx<T>* u_in = nullptr) {
   constexpr int SX = VT_X + 2 * VT_H, SY = VT_Y + 2 * VT_H, SZ = (DIM == 3) ? 1 + 2 * VT_H : 1;
   constexpr int HZ = (DIM == 3) ? VT_H : 0;
   __shared__ cpx<T> tile[SZ * SY * SX];
@@ -395,18 +434,31 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   // all loads of the residual tile are issued before the first LDS write; the barrier
   // orders LDS only, so the smoother-entry loads below may start before it
   constexpr int NTL = SX * SY * SZ, NPT = (NTL + VT_X * VT_Y - 1) / (VT_X * VT_Y);
-  cpx<T> tv[NPT];
+  if constexpr (RS >= 0) {
+    // one residual per lane at a time (its 2K + 1 loads in flight together), written
+    // straight to the tile
+#pragma unroll 1
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * VT_Y * k;
+      const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+      const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+      const cpx<T> v = resid_tile<DIM, RS, T>(g, A, r, u_in, e < NTL, gx, gy, gz);
+      if (e < NTL) tile[e] = v;
+    }
+  } else {
+    cpx<T> tv[NPT];
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int e = (int)threadIdx.x + VT_X * VT_Y * k;
-    const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
-    const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
-    tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
-  }
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * VT_Y * k;
+      const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+      const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+      tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
+    }
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int e = (int)threadIdx.x + VT_X * VT_Y * k;
-    if (e < NTL) tile[e] = tv[k];
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * VT_Y * k;
+      if (e < NTL) tile[e] = tv[k];
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -436,22 +488,32 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
       acc = cfma(gv, t0[(dz * SY + dy) * SX + dx], acc);
     }
   }
-  u[i] = ZERO ? acc : (u[i] + acc);
+  if constexpr (RS >= 0)
+    u[i] = u_in[i] + acc;
+  else
+    u[i] = ZERO ? acc : (u[i] + acc);
 }
 
 // The 1x1 patch (damped point Jacobi) needs no neighbour: u_i (+)= G_i r_i, streamed
 // without a residual tile.
-template <bool ZERO, class T>
+template <bool ZERO, class T, int DIM = 2, int RS = -1>
 __global__ __launch_bounds__(256) void k_point_sweep(Grid g, const cpx<T>* __restrict__ G,
                                                      const cpx<T>* __restrict__ r,
-                                                     cpx<T>* __restrict__ u) {
+                                                     cpx<T>* __restrict__ u,
+                                                     const cpx<T>* __restrict__ A = nullptr,
+                                                     const cpx<T>* u_in = nullptr) {
   const unsigned i = node_id();
   if (i >= g.N) return;
   int x, y, z;
   decode(i, g, x, y, z);
   const cpx<T> d = ld_stream(G + linp(g, x, y, z));
-  const cpx<T> acc = cfma(d, r[i], cmk<T>(0, 0));
-  u[i] = ZERO ? acc : (u[i] + acc);
+  if constexpr (RS >= 0) {
+    const cpx<T> rv = resid_at<DIM, RS, T>(g, A, r, u_in, (long long)i, x, y, z);
+    u[i] = u_in[i] + cfma(d, rv, cmk<T>(0, 0));
+  } else {
+    const cpx<T> acc = cfma(d, r[i], cmk<T>(0, 0));
+    u[i] = ZERO ? acc : (u[i] + acc);
+  }
 }
 
 template <int DIM, int FORM, class T>
@@ -832,10 +894,12 @@ __host__ __device__ constexpr int sym_entries() { return (ipow(5, DIM) + 1) / 2;
 template <class T>
 __host__ __device__ constexpr int sym_ty() { return sizeof(T) == 4 ? 8 : 4; }
 
-template <int DIM, bool ZERO, class T>
+template <int DIM, bool ZERO, class T, int RS = -1>
 __global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* __restrict__ S,
                                                          double w, const cpx<T>* __restrict__ r,
-                                                         cpx<T>* __restrict__ u) {
+                                                         cpx<T>* __restrict__ u,
+                                                         const cpx<T>* __restrict__ A = nullptr,
+                                                         const cpx<T>* u_in = nullptr) {
   constexpr int TY = sym_ty<T>();
   constexpr int SX = VT_X + 2 * VT_H, SY = TY + 2 * VT_H, SZ = (DIM == 3) ? 1 + 2 * VT_H : 1;
   constexpr int HZ = (DIM == 3) ? VT_H : 0;
@@ -848,18 +912,31 @@ __global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* _
   const int bz = (int)(t % (unsigned)g.nz), by = (int)(t / (unsigned)g.nz);
   const int x0 = bx * VT_X, y0 = by * TY, z0 = bz;
   constexpr int NTL = SX * SY * SZ, NPT = (NTL + VT_X * TY - 1) / (VT_X * TY);
-  cpx<T> tv[NPT];
+  if constexpr (RS >= 0) {
+    // one residual per lane at a time (its 2K + 1 loads in flight together), written
+    // straight to the tile
+#pragma unroll 1
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * TY * k;
+      const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+      const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+      const cpx<T> v = resid_tile<DIM, RS, T>(g, A, r, u_in, e < NTL, gx, gy, gz);
+      if (e < NTL) tile[e] = v;
+    }
+  } else {
+    cpx<T> tv[NPT];
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int e = (int)threadIdx.x + VT_X * TY * k;
-    const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
-    const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
-    tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
-  }
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * TY * k;
+      const int tx = e % SX, ty = (e / SX) % SY, tz = e / (SX * SY);
+      const int gx = x0 + tx - VT_H, gy = y0 + ty - VT_H, gz = z0 + tz - HZ;
+      tv[k] = (e < NTL && inside(g, gx, gy, gz)) ? r[lin(g, gx, gy, gz)] : cmk<T>(0, 0);
+    }
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int e = (int)threadIdx.x + VT_X * TY * k;
-    if (e < NTL) tile[e] = tv[k];
+    for (int k = 0; k < NPT; ++k) {
+      const int e = (int)threadIdx.x + VT_X * TY * k;
+      if (e < NTL) tile[e] = tv[k];
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -898,7 +975,10 @@ __global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* _
   }
   const T dw = (T)(w / (double)patch_count<DIM, PATCH_FULL>(g, x, y, z));
   acc = cmk<T>(dw * acc.re, dw * acc.im);
-  u[i] = ZERO ? acc : (u[i] + acc);
+  if constexpr (RS >= 0)
+    u[i] = u_in[i] + acc;
+  else
+    u[i] = ZERO ? acc : (u[i] + acc);
 }
 
 template <int DIM, class T>
@@ -931,6 +1011,70 @@ hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, c
   if (dim == 3)
     return prec == PREC_F64 ? vanka_sweep_sym_t<3, double>(g, S, w, r, u, zero, s)
                             : vanka_sweep_sym_t<3, float>(g, S, w, r, u, zero, s);
+  return hipErrorInvalidValue;
+}
+
+// u_out = u_in + B (q - A u_in) in one launch (2D; the residual is formed in the sweep's
+// tile stage).  A 3D tile with its halo of two planes holds about ten times the nodes it
+// updates, so forming the residual there would cost more stencil loads than the separate
+// residual sweep saves; 3D keeps the two launches.
+template <int FORM, int RS, class T>
+static hipError_t fused_sweep_t(Grid g, const void* G, const void* A, const void* q,
+                                const void* u_in, void* u_out, hipStream_t s) {
+  auto Gp = (const cpx<T>*)G;
+  auto Ap = (const cpx<T>*)A;
+  auto qp = (const cpx<T>*)q;
+  auto ui = (const cpx<T>*)u_in;
+  auto uo = (cpx<T>*)u_out;
+  if constexpr (FORM == SM_POINT) {
+    k_point_sweep<false, T, 2, RS><<<nblocks((size_t)g.N, 256), 256, 0, s>>>(g, Gp, qp, uo, Ap, ui);
+  } else {
+    const unsigned nb = (unsigned)(((g.nx + VT_X - 1) / VT_X) * ((g.ny + VT_Y - 1) / VT_Y));
+    k_vanka_sweep<2, FORM, false, T, RS><<<nb, VT_X * VT_Y, 0, s>>>(g, Gp, qp, uo, Ap, ui);
+  }
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+bool fused_sweep_ok(int dim, int form, int shape) {
+  return dim == 2 && (form == SM_FULL || form == SM_POINT || form == SM_BOX2 ||
+                      form == SM_ELEMENT || form == 6 /* symmetric half */) &&
+         (shape == CROSS || shape == BOX1 || shape == BOX2);
+}
+
+hipError_t vanka_sweep_fused(int dim, int form, int shape, Grid g, int prec, const void* G,
+                             double w, const void* A, const void* q, const void* u_in, void* u_out,
+                             hipStream_t s) {
+  if (!fused_sweep_ok(dim, form, shape) || u_in == u_out) return hipErrorInvalidValue;
+  if (form == 6) {
+    if (g.Np >= (1LL << 31)) return hipErrorInvalidValue;
+#define VH_FS(RS, T)                                                                           \
+  if (shape == RS) {                                                                           \
+    constexpr int TY = sym_ty<T>();                                                            \
+    const unsigned nb = (unsigned)(((g.nx + VT_X - 1) / VT_X) * ((g.ny + TY - 1) / TY));       \
+    k_vanka_sweep_sym<2, false, T, RS><<<nb, VT_X * TY, 0, s>>>(                                \
+        g, (const cpx<T>*)G, w, (const cpx<T>*)q, (cpx<T>*)u_out, (const cpx<T>*)A,             \
+        (const cpx<T>*)u_in);                                                                   \
+    VH_LAUNCH_CHECK();                                                                          \
+    return hipSuccess;                                                                          \
+  }
+    if (prec == PREC_F64) {
+      VH_FS(CROSS, double) VH_FS(BOX1, double) VH_FS(BOX2, double)
+    } else {
+      VH_FS(CROSS, float) VH_FS(BOX1, float) VH_FS(BOX2, float)
+    }
+#undef VH_FS
+    return hipErrorInvalidValue;
+  }
+#define VH_FV(F, RS)                                                                          \
+  if (form == F && shape == RS)                                                               \
+    return prec == PREC_F64 ? fused_sweep_t<F, RS, double>(g, G, A, q, u_in, u_out, s)       \
+                            : fused_sweep_t<F, RS, float>(g, G, A, q, u_in, u_out, s);
+  VH_FV(SM_FULL, CROSS) VH_FV(SM_FULL, BOX1) VH_FV(SM_FULL, BOX2)
+  VH_FV(SM_POINT, CROSS) VH_FV(SM_POINT, BOX1) VH_FV(SM_POINT, BOX2)
+  VH_FV(SM_BOX2, CROSS) VH_FV(SM_BOX2, BOX1) VH_FV(SM_BOX2, BOX2)
+  VH_FV(SM_ELEMENT, CROSS) VH_FV(SM_ELEMENT, BOX1) VH_FV(SM_ELEMENT, BOX2)
+#undef VH_FV
   return hipErrorInvalidValue;
 }
 
@@ -1307,9 +1451,10 @@ __global__ __launch_bounds__(256) void k_restrict(Grid gf, Grid gc, const cpx<T>
   rc[I] = acc;
 }
 
+// u = u_in + P e; u_in is u itself for the in-place correction
 template <int DIM, int PF, class T>
 __global__ __launch_bounds__(256) void k_prolong_add(Grid gf, Grid gc, const cpx<T>* __restrict__ e,
-                                                     cpx<T>* __restrict__ u) {
+                                                     cpx<T>* u, const cpx<T>* u_in) {
   const unsigned i = node_id();
   if (i >= gf.N) return;
   int c[3];
@@ -1342,7 +1487,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid gf, Grid gc, const cpx
           acc.re = fma(wt, ev.re, acc.re);
           acc.im = fma(wt, ev.im, acc.im);
         }
-    u[i] = u[i] + acc;
+    u[i] = u_in[i] + acc;
     return;
   }
   // per dimension: candidate coarse nodes J0-1, J0, J0+1 (J0 = c/2) and weights p(c - 2J)
@@ -1369,7 +1514,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(Grid gf, Grid gc, const cpx
         if (wt != (T)0 && inside(gc, Jx, Jy, Jz))
           acc = cfma(cmk<T>(wt, 0), e[lin(gc, Jx, Jy, Jz)], acc);
       }
-  u[i] = u[i] + acc;
+  u[i] = u_in[i] + acc;
 }
 
 hipError_t restrict_(int dim, int rf, Grid gf, Grid gc, int prec, const void* r, void* rc,
@@ -1392,12 +1537,96 @@ hipError_t restrict_(int dim, int rf, Grid gf, Grid gc, int prec, const void* r,
   return hipErrorInvalidValue;
 }
 
+// rc = R (q - A u) without storing the fine residual.  One block per 64 x 4 tile of
+// coarse nodes (one coarse plane in 3D): the fine residual over the tile's footprint (its
+// fine nodes plus the transfer radius, about 1.1x the fine nodes it covers in 2D, 1.7x
+// in 3D) is formed once into LDS with the arithmetic of the residual sweep, then every
+// lane gathers its coarse node in the order of k_restrict, so the result has the bits of
+// the two-launch path.
+constexpr int RT_X = 64, RT_Y = 4;
+
+template <int DIM, int RF, int SHAPE, class T>
+__global__ __launch_bounds__(256) void k_resid_restrict(Grid gf, Grid gc,
+                                                        const cpx<T>* __restrict__ A,
+                                                        const cpx<T>* __restrict__ q,
+                                                        const cpx<T>* __restrict__ u,
+                                                        cpx<T>* __restrict__ rc) {
+  constexpr int RR = fam_radius(RF), RW = 2 * RR + 1, NT = ipow(RW, DIM);
+  constexpr int FX = 2 * RT_X + 2 * RR - 1, FY = 2 * RT_Y + 2 * RR - 1;
+  constexpr int FZ = (DIM == 3) ? RW : 1;
+  constexpr int NTL = FX * FY * FZ, NPT = (NTL + RT_X * RT_Y - 1) / (RT_X * RT_Y);
+  __shared__ cpx<T> tile[NTL];
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (gc.nx + RT_X - 1) / RT_X, nby = (gc.ny + RT_Y - 1) / RT_Y;
+  const int bx = (int)(b % (unsigned)nbx), by = (int)((b / (unsigned)nbx) % (unsigned)nby);
+  const int bz = (int)(b / (unsigned)(nbx * nby));
+  const int X0 = bx * RT_X, Y0 = by * RT_Y, Z0 = bz;
+  const int fx0 = 2 * X0 - RR, fy0 = 2 * Y0 - RR, fz0 = (DIM == 3) ? 2 * Z0 - RR : 0;
+#pragma unroll 1
+  for (int k = 0; k < NPT; ++k) {
+    const int e = (int)threadIdx.x + RT_X * RT_Y * k;
+    const int tx = e % FX, ty = (e / FX) % FY, tz = e / (FX * FY);
+    const int gx = fx0 + tx, gy = fy0 + ty, gz = fz0 + tz;
+    const cpx<T> v = resid_tile<DIM, SHAPE, T>(gf, A, q, u, e < NTL, gx, gy, gz);
+    if (e < NTL) tile[e] = v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  const int Ix = X0 + (int)threadIdx.x % RT_X, Iy = Y0 + (int)threadIdx.x / RT_X, Iz = Z0;
+  if (Ix >= gc.nx || Iy >= gc.ny) return;
+  cpx<T> acc = cmk<T>(0, 0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tx = t % RW - RR, ty = (t / RW) % RW - RR, tz = (DIM == 3) ? t / (RW * RW) - RR : 0;
+    const int fx = 2 * Ix + tx, fy = 2 * Iy + ty, fz = 2 * Iz + tz;
+    if (inside(gf, fx, fy, fz)) {
+      const T w = (T)(fam_r(RF, tx) * fam_r(RF, ty) * (DIM == 3 ? fam_r(RF, tz) : 1.0));
+      acc = cfma(cmk<T>(w, 0), tile[((fz - fz0) * FY + (fy - fy0)) * FX + (fx - fx0)], acc);
+    }
+  }
+  rc[lin(gc, Ix, Iy, Iz)] = acc;
+}
+
+bool fused_restrict_ok(int dim, int rf, int shape) {
+  if (dim == 2) return shape == CROSS || shape == BOX1 || shape == BOX2;
+  return dim == 3 && rf == FAM_LINEAR && (shape == CROSS || shape == BOX1);
+}
+
+hipError_t resid_restrict(int dim, int rf, int shape, Grid gf, Grid gc, int prec, const void* A,
+                          const void* q, const void* u, void* rc, hipStream_t s) {
+  if (!fused_restrict_ok(dim, rf, shape)) return hipErrorInvalidValue;
+  const unsigned nb =
+      (unsigned)(((gc.nx + RT_X - 1) / RT_X) * ((gc.ny + RT_Y - 1) / RT_Y) * gc.nz);
+#define VH_RR(D, R, S, T)                                                                    \
+  if (dim == D && rf == R && shape == S) {                                                   \
+    k_resid_restrict<D, R, S, T><<<nb, RT_X * RT_Y, 0, s>>>(                                  \
+        gf, gc, (const cpx<T>*)A, (const cpx<T>*)q, (const cpx<T>*)u, (cpx<T>*)rc);          \
+    VH_LAUNCH_CHECK();                                                                        \
+    return hipSuccess;                                                                        \
+  }
+#define VH_RR2(T)                                                                             \
+  VH_RR(2, FAM_LINEAR, CROSS, T) VH_RR(2, FAM_LINEAR, BOX1, T) VH_RR(2, FAM_LINEAR, BOX2, T)  \
+  VH_RR(2, FAM_CUBIC, CROSS, T) VH_RR(2, FAM_CUBIC, BOX1, T) VH_RR(2, FAM_CUBIC, BOX2, T)     \
+  VH_RR(3, FAM_LINEAR, CROSS, T) VH_RR(3, FAM_LINEAR, BOX1, T)
+  if (prec == PREC_F64) {
+    VH_RR2(double)
+  } else {
+    VH_RR2(float)
+  }
+#undef VH_RR2
+#undef VH_RR
+  return hipErrorInvalidValue;
+}
+
 hipError_t prolong_add(int dim, int pf, Grid gf, Grid gc, int prec, const void* e, void* u,
-                       hipStream_t s) {
+                       hipStream_t s, const void* u_in) {
   const unsigned nb = nblocks(gf.N, 256);
+  if (!u_in) u_in = u;
 #define VH_PA(D, P, T)                                                                         \
   if (dim == D && pf == P) {                                                                   \
-    k_prolong_add<D, P, T><<<nb, 256, 0, s>>>(gf, gc, (const cpx<T>*)e, (cpx<T>*)u);           \
+    k_prolong_add<D, P, T><<<nb, 256, 0, s>>>(gf, gc, (const cpx<T>*)e, (cpx<T>*)u,            \
+                                              (const cpx<T>*)u_in);                            \
     VH_LAUNCH_CHECK();                                                                         \
     return hipSuccess;                                                                         \
   }

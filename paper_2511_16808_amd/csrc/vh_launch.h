@@ -68,6 +68,12 @@ hipError_t stencil(int dim, int shape, Grid g, int mode, int pc, const void* A, 
 // form: 0 = per-patch Full (Np*Np entries), 1 = per-patch point, 2 = assembled 5^dim box
 hipError_t vanka_sweep(int dim, int form, Grid g, int prec, const void* G, const void* r, void* u,
                        bool zero, hipStream_t s);
+// u_out = u_in + B (q - A u_in) in one launch, where fused_sweep_ok(dim, form, shape); form
+// 6 is the symmetric half (w its damping); u_out must not be u_in
+bool fused_sweep_ok(int dim, int form, int shape);
+hipError_t vanka_sweep_fused(int dim, int form, int shape, Grid g, int prec, const void* G,
+                             double w, const void* A, const void* q, const void* u_in, void* u_out,
+                             hipStream_t s);
 // A slab of the smoother setup: patches centred at nodes [c_lo, c_hi) (unpadded linear
 // index) write their rows to G[e * gstride + (padded member index - gbase)].  The whole
 // grid is {0, N, 0, Np}.
@@ -100,8 +106,13 @@ hipError_t galerkin(int dim, int sin, int sout, int rf, int pf, Grid gf, Grid gc
                     const cpx<double>* Af, cpx<double>* Ac, hipStream_t s);
 hipError_t restrict_(int dim, int rf, Grid gf, Grid gc, int prec, const void* r, void* rc,
                      hipStream_t s);
+// u = u_in + P e (u_in = nullptr: in place, u += P e)
 hipError_t prolong_add(int dim, int pf, Grid gf, Grid gc, int prec, const void* e, void* u,
-                       hipStream_t s);
+                       hipStream_t s, const void* u_in = nullptr);
+// rc = R (q - A u) in one launch, where fused_restrict_ok(dim, rf, shape)
+bool fused_restrict_ok(int dim, int rf, int shape);
+hipError_t resid_restrict(int dim, int rf, int shape, Grid gf, Grid gc, int prec, const void* A,
+                          const void* q, const void* u, void* rc, hipStream_t s);
 hipError_t dense_assemble(int dim, int shape, Grid g, const cpx<double>* A, cpx<double>* D,
                           hipStream_t s);
 hipError_t gj_invert(int n, cpx<double>* M, int* perm, cpx<double>* col, hipStream_t s);

@@ -76,6 +76,8 @@ struct Level {
   int mfma_rows[7] = {0, 0, 0, 0, 0, 0, 0};
   int s64_tile = 0;   // variant of the 64-source 2D assembled sweep (0: not chosen yet)
   int s64_stile = 0;  // variant of the 64-source 2D stencil (operator, residual)
+  // residual formed inside the sweep / the restriction (chosen per level at setup)
+  bool fuse_sweep = false, fuse_restrict = false;
 };
 
 }  // namespace
@@ -367,6 +369,8 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
     return fail(VH_EINVAL, "unknown contraction");
   if (o.sweep_tile < 0 || o.sweep_tile > S64_TILES)
     return fail(VH_EINVAL, "sweep_tile must be in [0, 7]");
+  if (o.split_residual < 0 || o.split_residual > 2)
+    return fail(VH_EINVAL, "split_residual must be 0, 1 or 2");
   if (o.contraction != VH_CONTRACT_VALU &&
       (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
        o.smoother != VH_SMOOTHER_PATCH ||
@@ -444,13 +448,129 @@ vh_status residual(vh_handle* hd, Level& Lv, const void* q, const void* u, void*
   return VH_OK;
 }
 
+// one smoothing step u_out = u_in + B (q - A u_in) in one launch (u_out != u_in)
+vh_status smooth_fused(vh_handle* hd, Level& Lv, const void* q, const void* u_in, void* u_out) {
+  const int tk = (&Lv == &hd->L[0]) ? hd->tbegin(1) : -1;
+  count(hd, (double)Lv.g.N, (double)hd->esz * (Lv.E + coef_reads(Lv) + 3));
+  VH_HIP(vanka_sweep_fused(hd->dim, Lv.form, Lv.shape, Lv.g, hd->prec, Lv.B, Lv.w, Lv.A, q, u_in,
+                           u_out, hd->s));
+  hd->tend(tk);
+  return VH_OK;
+}
+
+bool fuses_sweep(const vh_handle*, const Level& Lv) { return Lv.fuse_sweep; }
+bool fuses_restrict(const vh_handle*, const Level& Lv) { return Lv.fuse_restrict; }
+
+// Per level, whether the residual is formed inside the smoothing sweep and inside the
+// restriction (vh_options.split_residual): 1 never, 2 wherever a kernel exists, 0 where
+// the one launch is measured faster than the two it replaces.  The fused tile stage forms
+// the residual on the tile's halo too, so on operators of many points or on small grids
+// it can cost more than the stored residual saves; the timing (one warm-up and three timed
+// launches of each, on the level's own arrays) settles it.  The choice depends only on the
+// device, the level's grid, operator and smoother form and the precision, so it is kept for
+// the process; both paths give the same bits.
+std::mutex g_fuse_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_fuse_cache;
+
+vh_status tune_fuse(vh_handle* hd) {
+  const int mode = hd->opt.split_residual;
+  int dev = 0;
+  VH_HIP(hipGetDevice(&dev));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  vh_status st = VH_OK;
+  for (int l = 0; l + 1 < hd->levels && st == VH_OK; ++l) {
+    Level& Lv = hd->L[l];
+    Level& Lc = hd->L[l + 1];
+    const bool cs = fused_sweep_ok(hd->dim, Lv.form, Lv.shape);
+    const bool cr = fused_restrict_ok(hd->dim, Lv.rf, Lv.shape);
+    Lv.fuse_sweep = Lv.fuse_restrict = false;
+    if (mode == 1 || (!cs && !cr)) continue;
+    if (mode == 2) {
+      Lv.fuse_sweep = cs;
+      Lv.fuse_restrict = cr;
+      continue;
+    }
+    const auto key = std::make_tuple(dev, Lv.g.nx, Lv.g.ny, Lv.g.nz,
+                                     hd->prec | Lv.shape << 2 | Lv.form << 5 | Lv.rf << 9);
+    {
+      std::lock_guard<std::mutex> lock(g_fuse_mu);
+      auto it = g_fuse_cache.find(key);
+      if (it != g_fuse_cache.end()) {
+        Lv.fuse_sweep = (it->second & 1) != 0;
+        Lv.fuse_restrict = (it->second & 2) != 0;
+        continue;
+      }
+    }
+    if (!e0 && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+      st = fail(VH_EDEVICE, "hipEventCreate failed");
+      break;
+    }
+    // the level's arrays hold zeros here (set-up has not run a cycle yet)
+    auto split_sweep = [&]() {
+      hipError_t e = stencil(hd->dim, Lv.shape, Lv.g, OP_RESID, hd->prec, Lv.A, hd->prec, Lv.u,
+                             hd->prec, Lv.q, Lv.r, hd->s);
+      if (e != hipSuccess) return e;
+      return Lv.form == SM_SYMHALF
+                 ? vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, Lv.r, Lv.u, false, hd->s)
+                 : vanka_sweep(hd->dim, Lv.form, Lv.g, hd->prec, Lv.B, Lv.r, Lv.u, false, hd->s);
+    };
+    auto fused_sweep = [&]() {
+      return vanka_sweep_fused(hd->dim, Lv.form, Lv.shape, Lv.g, hd->prec, Lv.B, Lv.w, Lv.A,
+                               Lv.q, Lv.u, Lv.r, hd->s);
+    };
+    auto split_restrict = [&]() {
+      hipError_t e = stencil(hd->dim, Lv.shape, Lv.g, OP_RESID, hd->prec, Lv.A, hd->prec, Lv.u,
+                             hd->prec, Lv.q, Lv.r, hd->s);
+      if (e != hipSuccess) return e;
+      return restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s);
+    };
+    auto fused_restrict = [&]() {
+      return resid_restrict(hd->dim, Lv.rf, Lv.shape, Lv.g, Lc.g, hd->prec, Lv.A, Lv.q, Lv.u,
+                            Lc.q, hd->s);
+    };
+    auto timed = [&](auto&& f, float& ms) {
+      hipError_t e = f();
+      if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) e = f();
+      if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      return e;
+    };
+    float a = 0.f, b = 0.f;
+    hipError_t e = hipSuccess;
+    if (cs) {
+      e = timed(split_sweep, a);
+      if (e == hipSuccess) e = timed(fused_sweep, b);
+      Lv.fuse_sweep = e == hipSuccess && b < a;
+    }
+    if (cr && e == hipSuccess) {
+      e = timed(split_restrict, a);
+      if (e == hipSuccess) e = timed(fused_restrict, b);
+      Lv.fuse_restrict = e == hipSuccess && b < a;
+    }
+    if (e != hipSuccess) {
+      st = fail(VH_EDEVICE, std::string("fusion timing: ") + hipGetErrorString(e));
+      break;
+    }
+    std::lock_guard<std::mutex> lock(g_fuse_mu);
+    g_fuse_cache[key] = (Lv.fuse_sweep ? 1 : 0) | (Lv.fuse_restrict ? 2 : 0);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
 // number of visits of level l + 1 from level l: two for a W-cycle unless l + 1 is the
 // coarsest level (solved directly)
 int coarse_visits(const vh_handle* hd, int l) {
   return (hd->opt.cycle == VH_CYCLE_W && l + 2 < hd->levels) ? 2 : 1;
 }
 
-// u <- cycle(l, q, u); u is taken as zero on entry when from_zero (its content is ignored)
+// u <- cycle(l, q, u); u is taken as zero on entry when from_zero (its content is ignored).
+// Where the level forms the residual inside its sweep, each such step writes a second
+// array (the level's residual array, unused then); the first step of a run is placed so
+// that the last one lands in u.
 vh_status vcycle(vh_handle* hd, int l, const void* q, void* u, bool from_zero) {
   Level& Lv = hd->L[l];
   if (l == hd->levels - 1) {
@@ -459,28 +579,61 @@ vh_status vcycle(vh_handle* hd, int l, const void* q, void* u, bool from_zero) {
     return VH_OK;
   }
   const int nu1 = hd->opt.nu1, nu2 = hd->opt.nu2;
+  const bool fs = fuses_sweep(hd, Lv);
+  void* alt = Lv.r;
   if (nu1 == 0 && from_zero) {
     count(hd, (double)Lv.g.N, (double)hd->esz);
     VH_HIP(fill(u, (size_t)Lv.g.N, hd->prec, 0.0, 0.0, hd->s));
   }
-  for (int k = 0; k < nu1; ++k) {
-    if (k == 0 && from_zero) {
-      VH_TRY(smooth(hd, Lv, q, u, true));  // u = 0: the residual is q
+  {
+    int k = 0;
+    void* cur = u;
+    if (nu1 > 0 && from_zero) {  // u = 0: the first step is u = B q
+      cur = (fs && (nu1 - 1) % 2 == 1) ? alt : u;
+      VH_TRY(smooth(hd, Lv, q, cur, true));
+      k = 1;
+    }
+    if (fs && cur == u && (nu1 - k) % 2 == 1) {  // an odd run from u: one step in place
+      VH_TRY(residual(hd, Lv, q, u, Lv.r));
+      VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+      ++k;
+    }
+    for (; k < nu1; ++k) {
+      if (fs) {
+        void* nxt = (cur == u) ? alt : u;
+        VH_TRY(smooth_fused(hd, Lv, q, cur, nxt));
+        cur = nxt;
+      } else {
+        VH_TRY(residual(hd, Lv, q, u, Lv.r));
+        VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+      }
+    }
+  }
+  Level& Lc = hd->L[l + 1];
+  if (fuses_restrict(hd, Lv)) {
+    count(hd, (double)Lv.g.N, (double)hd->esz * (coef_reads(Lv) + 2));
+    count(hd, (double)Lc.g.N, (double)hd->esz);
+    VH_HIP(resid_restrict(hd->dim, Lv.rf, Lv.shape, Lv.g, Lc.g, hd->prec, Lv.A, q, u, Lc.q,
+                          hd->s));
+  } else {
+    VH_TRY(residual(hd, Lv, q, u, Lv.r));
+    count(hd, (double)(Lv.g.N + Lc.g.N), (double)hd->esz);
+    VH_HIP(restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s));
+  }
+  for (int v = 0; v < coarse_visits(hd, l); ++v) VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u, v == 0));
+  // the correction goes to the array the post-smoothing run starts from
+  void* cur = (fs && nu2 % 2 == 1) ? alt : u;
+  count(hd, (double)(2 * Lv.g.N + Lc.g.N), (double)hd->esz);
+  VH_HIP(prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, hd->prec, Lc.u, cur, hd->s, u));
+  for (int k = 0; k < nu2; ++k) {
+    if (fs) {
+      void* nxt = (cur == u) ? alt : u;
+      VH_TRY(smooth_fused(hd, Lv, q, cur, nxt));
+      cur = nxt;
     } else {
       VH_TRY(residual(hd, Lv, q, u, Lv.r));
       VH_TRY(smooth(hd, Lv, Lv.r, u, false));
     }
-  }
-  Level& Lc = hd->L[l + 1];
-  VH_TRY(residual(hd, Lv, q, u, Lv.r));
-  count(hd, (double)(Lv.g.N + Lc.g.N), (double)hd->esz);
-  VH_HIP(restrict_(hd->dim, Lv.rf, Lv.g, Lc.g, hd->prec, Lv.r, Lc.q, hd->s));
-  for (int v = 0; v < coarse_visits(hd, l); ++v) VH_TRY(vcycle(hd, l + 1, Lc.q, Lc.u, v == 0));
-  count(hd, (double)(2 * Lv.g.N + Lc.g.N), (double)hd->esz);
-  VH_HIP(prolong_add(hd->dim, Lv.pf, Lv.g, Lc.g, hd->prec, Lc.u, u, hd->s));
-  for (int k = 0; k < nu2; ++k) {
-    VH_TRY(residual(hd, Lv, q, u, Lv.r));
-    VH_TRY(smooth(hd, Lv, Lv.r, u, false));
   }
   return VH_OK;
 }
@@ -1290,6 +1443,7 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     hd->ev_kind.assign(64, 0);
     for (auto& e : hd->ev) VH_HIP(hipEventCreate(&e));
   }
+  VH_TRY(tune_fuse(hd));
   VH_HIP(hipStreamSynchronize(s));
   return VH_OK;
 }
@@ -1517,6 +1671,8 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   shape_offsets(hd->dim, Lv.shape, Lv.K, info->offsets);
   info->bytes = Lv.bytes;
   info->sweep_tile = Lv.s64_tile;
+  info->fused_sweep = Lv.fuse_sweep ? 1 : 0;
+  info->fused_restrict = Lv.fuse_restrict ? 1 : 0;
   for (int ls = 6; ls >= 0; --ls)
     if (Lv.mfma_txp[ls]) {
       info->mfma_sources = 1 << ls;
@@ -1567,15 +1723,28 @@ vh_status vh_apply_smoother(vh_handle* hd, int level, const void* q, void* u) {
     return fail(VH_EINVAL, "bad argument (the coarsest level has no smoother)");
   Level& Lv = hd->L[level];
   const size_t N = (size_t)Lv.g.N;
+  // the step the V-cycle takes on this level: in one launch where the level forms the
+  // residual inside its sweep (into the level's residual array, then copied back)
+  const bool fs = fuses_sweep(hd, Lv);
   if (hd->prec == PREC_F64) {
-    VH_TRY(residual(hd, Lv, q, u, Lv.r));
-    VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+    if (fs) {
+      VH_TRY(smooth_fused(hd, Lv, q, u, Lv.r));
+      VH_HIP(hipMemcpyAsync(u, Lv.r, N * hd->esz, hipMemcpyDeviceToDevice, hd->s));
+    } else {
+      VH_TRY(residual(hd, Lv, q, u, Lv.r));
+      VH_TRY(smooth(hd, Lv, Lv.r, u, false));
+    }
   } else {
     VH_HIP(convert(q, PREC_F64, Lv.q, hd->prec, N, hd->s));
     VH_HIP(convert(u, PREC_F64, Lv.u, hd->prec, N, hd->s));
-    VH_TRY(residual(hd, Lv, Lv.q, Lv.u, Lv.r));
-    VH_TRY(smooth(hd, Lv, Lv.r, Lv.u, false));
-    VH_HIP(convert(Lv.u, hd->prec, u, PREC_F64, N, hd->s));
+    if (fs) {
+      VH_TRY(smooth_fused(hd, Lv, Lv.q, Lv.u, Lv.r));
+      VH_HIP(convert(Lv.r, hd->prec, u, PREC_F64, N, hd->s));
+    } else {
+      VH_TRY(residual(hd, Lv, Lv.q, Lv.u, Lv.r));
+      VH_TRY(smooth(hd, Lv, Lv.r, Lv.u, false));
+      VH_HIP(convert(Lv.u, hd->prec, u, PREC_F64, N, hd->s));
+    }
   }
   VH_HIP(hipStreamSynchronize(hd->s));
   return VH_OK;

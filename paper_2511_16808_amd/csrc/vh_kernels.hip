@@ -1758,13 +1758,188 @@ __global__ __launch_bounds__(256) void k_gj_unscramble(int n, cpx<double>* __res
   }
 }
 
-hipError_t gj_invert(int n, cpx<double>* M, int* perm, cpx<double>* col, hipStream_t s) {
-  for (int k = 0; k < n; ++k) {
-    k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, perm, col);
-    VH_LAUNCH_CHECK();
-    dim3 grid((n + 255) / 256, n);
-    k_gj_elim<<<grid, 256, 0, s>>>(n, k, M, col);
-    VH_LAUNCH_CHECK();
+// Blocked form of the same elimination: b pivot steps at a time.  One workgroup takes a
+// panel of b columns into LDS together with the b identity columns the steps introduce
+// (column k of the identity enters at step k, after that step's row swap), and runs the b
+// steps there: pivot search in the panel column, row swap, scaling of the pivot row,
+// elimination of every other row.  The identity columns end up holding the panel's
+// columns of the in-place inverse, Ip (n x b).  Every other column x of the matrix takes
+// the same b steps at once: the swaps permute its rows (x -> x[sig]) and the scalings and
+// eliminations add Ip - E times its values at the panel rows (E the panel's unit
+// columns), since each step reads x only at its pivot row.  So one panel launch and one
+// update launch replace 2b launches, with the pivots of the unblocked elimination.
+constexpr int GJ_PANEL_MAX = 32;
+constexpr int GJ_LDS_ENTRIES = 8960;   // n * 2b complex FP64 entries (140 KB)
+constexpr int GJ_MAX_N = 2400;         // rows of the blocked form (row map in LDS)
+
+int gj_panel(int n) {
+  const int b = GJ_LDS_ENTRIES / (2 * (n > 0 ? n : 1));
+  return (n > GJ_MAX_N || b < 2) ? 0 : (b > GJ_PANEL_MAX ? GJ_PANEL_MAX : b);
+}
+
+static size_t gj_align(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t gj_workspace_bytes(int n) {
+  const size_t nn = (size_t)n;
+  const int b = gj_panel(n);
+  if (b == 0) return gj_align(nn * sizeof(int)) + gj_align(nn * sizeof(cpx<double>));
+  return gj_align(nn * sizeof(int)) * 2 + gj_align(nn * nn * sizeof(cpx<double>)) +
+         gj_align(nn * (size_t)b * sizeof(cpx<double>));
+}
+
+__global__ __launch_bounds__(1024) void k_gj_panel(int n, int k0, int b,
+                                                   const cpx<double>* __restrict__ M,
+                                                   int* __restrict__ perm, int* __restrict__ sig,
+                                                   cpx<double>* __restrict__ Ip) {
+  __shared__ cpx<double> P[GJ_LDS_ENTRIES];  // [n][2b]: panel columns, then identity columns
+  __shared__ int rmap[GJ_MAX_N];             // row of the panel's input now at each row
+  __shared__ double sv[16];
+  __shared__ int si[16];
+  __shared__ int spiv;
+  const int t = threadIdx.x, W2 = 2 * b;
+  for (int e = t; e < n * W2; e += 1024) {
+    const int r = e / W2, c = e % W2;
+    P[e] = c < b ? M[(size_t)r * n + k0 + c] : cmk(0.0, 0.0);
+  }
+  for (int r = t; r < n; r += 1024) rmap[r] = r;
+  __syncthreads();
+  for (int tt = 0; tt < b; ++tt) {
+    const int k = k0 + tt;
+    // pivot: the largest |re| + |im| in the panel column at rows >= k (the first on ties)
+    double bv = -1.0;
+    int bi = k;
+    for (int r = k + t; r < n; r += 1024) {
+      const cpx<double> v = P[r * W2 + tt];
+      const double a = fabs(v.re) + fabs(v.im);
+      if (a > bv) {
+        bv = a;
+        bi = r;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_down(bv, o, 64);
+      const int oi = __shfl_down(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if ((t & 63) == 0) {
+      sv[t >> 6] = bv;
+      si[t >> 6] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double v = sv[0];
+      int i = si[0];
+      for (int w = 1; w < 16; ++w)
+        if (sv[w] > v || (sv[w] == v && si[w] < i)) {
+          v = sv[w];
+          i = si[w];
+        }
+      spiv = i;
+      perm[k] = i;
+      const int m = rmap[k];
+      rmap[k] = rmap[i];
+      rmap[i] = m;
+    }
+    __syncthreads();
+    const int p = spiv;
+    if (p != k && t < W2) {
+      const cpx<double> a = P[k * W2 + t];
+      P[k * W2 + t] = P[p * W2 + t];
+      P[p * W2 + t] = a;
+    }
+    __syncthreads();
+    if (t == 0) P[k * W2 + b + tt] = cmk(1.0, 0.0);  // identity column k, after the swap
+    __syncthreads();
+    // scale the pivot row (the pivot column itself is dropped: it becomes a unit column)
+    const cpx<double> inv = cinv(P[k * W2 + tt]);
+    __syncthreads();
+    if (t > tt && t <= b + tt) P[k * W2 + t] = P[k * W2 + t] * inv;
+    __syncthreads();
+    // eliminate the pivot column from every other row: the remaining panel columns and
+    // the identity columns introduced so far
+    const int cols = b;  // columns tt+1 .. b+tt
+    for (int e = t; e < n * cols; e += 1024) {
+      const int r = e / cols, c = tt + 1 + e % cols;
+      if (r == k) continue;
+      const cpx<double> f = P[r * W2 + tt];
+      P[r * W2 + c] = P[r * W2 + c] - f * P[k * W2 + c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * b; e += 1024) Ip[e] = P[(e / b) * W2 + b + e % b];
+  for (int r = t; r < n; r += 1024) sig[r] = rmap[r];
+}
+
+// Md = the matrix after the panel's steps: the panel's columns from Ip; every other
+// column j: x[sig] (panel rows excluded) + Ip x[sig[panel rows]]
+constexpr int GJU_ROWS = 16;
+__global__ __launch_bounds__(256) void k_gj_update(int n, int k0, int b,
+                                                   const cpx<double>* __restrict__ Ms,
+                                                   cpx<double>* __restrict__ Md,
+                                                   const int* __restrict__ sig,
+                                                   const cpx<double>* __restrict__ Ip) {
+  __shared__ cpx<double> yp[GJ_PANEL_MAX][64];
+  const int jj = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + jj;
+  for (int e = threadIdx.x; e < b * 64; e += 256) {
+    const int q = e >> 6, jg = blockIdx.x * 64 + (e & 63);
+    yp[q][e & 63] = jg < n ? Ms[(size_t)sig[k0 + q] * n + jg] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (j >= n) return;
+  const int r1 = min(n, (int)(blockIdx.y + 1) * GJU_ROWS);
+  for (int r = blockIdx.y * GJU_ROWS + (int)(threadIdx.x >> 6); r < r1; r += 4) {
+    cpx<double> out;
+    if (j >= k0 && j < k0 + b) {
+      out = Ip[(size_t)r * b + (j - k0)];
+    } else {
+      const bool prow = r >= k0 && r < k0 + b;
+      cpx<double> acc = prow ? cmk(0.0, 0.0) : Ms[(size_t)sig[r] * n + j];
+      for (int q = 0; q < b; ++q) acc = cfma(Ip[(size_t)r * b + q], yp[q][jj], acc);
+      out = acc;
+    }
+    Md[(size_t)r * n + j] = out;
+  }
+}
+
+hipError_t gj_invert(int n, cpx<double>* M, void* work, hipStream_t s) {
+  char* w = (char*)work;
+  int* perm = (int*)w;
+  const int b = gj_panel(n);
+  if (b == 0) {  // one pivot step per launch pair
+    cpx<double>* col = (cpx<double>*)(w + gj_align((size_t)n * sizeof(int)));
+    for (int k = 0; k < n; ++k) {
+      k_gj_pivot<<<1, 256, 0, s>>>(n, k, M, perm, col);
+      VH_LAUNCH_CHECK();
+      dim3 grid((n + 255) / 256, n);
+      k_gj_elim<<<grid, 256, 0, s>>>(n, k, M, col);
+      VH_LAUNCH_CHECK();
+    }
+  } else {
+    int* sig = (int*)(w + gj_align((size_t)n * sizeof(int)));
+    cpx<double>* M2 = (cpx<double>*)(w + 2 * gj_align((size_t)n * sizeof(int)));
+    cpx<double>* Ip = (cpx<double>*)((char*)M2 + gj_align((size_t)n * n * sizeof(cpx<double>)));
+    cpx<double>* cur = M;
+    cpx<double>* oth = M2;
+    const dim3 ug((unsigned)((n + 63) / 64), (unsigned)((n + GJU_ROWS - 1) / GJU_ROWS));
+    for (int k0 = 0; k0 < n; k0 += b) {
+      const int bb = (n - k0) < b ? (n - k0) : b;
+      k_gj_panel<<<1, 1024, 0, s>>>(n, k0, bb, cur, perm, sig, Ip);
+      VH_LAUNCH_CHECK();
+      k_gj_update<<<ug, 256, 0, s>>>(n, k0, bb, cur, oth, sig, Ip);
+      VH_LAUNCH_CHECK();
+      cpx<double>* tmp = cur;
+      cur = oth;
+      oth = tmp;
+    }
+    if (cur != M) {
+      const hipError_t e =
+          hipMemcpyAsync(M, cur, (size_t)n * n * sizeof(cpx<double>), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
   }
   k_gj_unscramble<<<(n + 255) / 256, 256, 0, s>>>(n, M, perm);
   VH_LAUNCH_CHECK();

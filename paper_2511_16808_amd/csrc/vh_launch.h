@@ -115,7 +115,9 @@ hipError_t resid_restrict(int dim, int rf, int shape, Grid gf, Grid gc, int prec
                           const void* q, const void* u, void* rc, hipStream_t s);
 hipError_t dense_assemble(int dim, int shape, Grid g, const cpx<double>* A, cpx<double>* D,
                           hipStream_t s);
-hipError_t gj_invert(int n, cpx<double>* M, int* perm, cpx<double>* col, hipStream_t s);
+// in-place inverse of the n x n row-major FP64 matrix M; work holds gj_workspace_bytes(n)
+size_t gj_workspace_bytes(int n);
+hipError_t gj_invert(int n, cpx<double>* M, void* work, hipStream_t s);
 hipError_t dense_matvec(int n, const cpx<double>* D, int prec, const void* x, void* y,
                         hipStream_t s);
 hipError_t cgs_pass(int mode, const cpx<double>* V, size_t ldv, int nv, const cpx<double>* h,

@@ -1403,17 +1403,14 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     Level& Lc = hd->L[hd->levels - 1];
     const int nc = (int)Lc.g.N;
     hd->nc = nc;
-    int* perm = nullptr;
-    cpx<double>* col = nullptr;
+    void* work = nullptr;
     VH_TRY(hd->alloc((void**)&hd->Dinv, (size_t)nc * nc * sizeof(cpx<double>)));
-    VH_TRY(hd->alloc((void**)&perm, (size_t)nc * sizeof(int), true));
-    VH_TRY(hd->alloc((void**)&col, (size_t)nc * sizeof(cpx<double>), true));
+    VH_TRY(hd->alloc(&work, gj_workspace_bytes(nc), true));
     VH_HIP(fill(hd->Dinv, (size_t)nc * nc, PREC_F64, 0, 0, s));
     VH_HIP(dense_assemble(dim, Lc.shape, Lc.g, A64[hd->levels - 1], hd->Dinv, s));
-    VH_HIP(gj_invert(nc, hd->Dinv, perm, col, s));
+    VH_HIP(gj_invert(nc, hd->Dinv, work, s));
     VH_HIP(hipStreamSynchronize(s));
-    hd->release(perm);
-    hd->release(col);
+    hd->release(work);
   }
   VH_HIP(hipStreamSynchronize(s));
   if (hd->prec != PREC_F64)
@@ -2121,7 +2118,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     common += (size_t)K * N * esz + 3 * N * esz;
     if (l + 1 == levels) {
       common += N * N * 16;                                   // coarsest inverse
-      coarse_tmp = N * (sizeof(int) + sizeof(cpx<double>));  // pivots and a column
+      coarse_tmp = gj_workspace_bytes((int)N);  // pivots, row map, second copy, panel
       break;
     }
     const int lp = (l == 0 && o.fine_patch >= 0) ? o.fine_patch : patch;

@@ -427,6 +427,8 @@ def main():
                     help="override: sources one after another (0) or sharing each sweep (1)")
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
                     help="override the preconditioner precision")
+    ap.add_argument("--sweep-tile", type=int, default=0,
+                    help="64-source 2D walk variant (1..7; 0: timed per grid)")
     ap.add_argument("--split-residual", action="store_true",
                     help="separate residual launches instead of the residual formed inside "
                          "the sweep and the restriction (same results)")
@@ -459,13 +461,13 @@ def main():
     ceiling = copy_ceiling()
     out = run_workload(args.workload, args.steps, args.warmup, args.smoother, args.contraction,
                        args.batch, args.precision, not args.no_cpu_baseline,
-                       args.split_residual)
+                       args.split_residual, args.sweep_tile)
     out["roofline"].update(ceiling_fields(out["roofline"], ceiling))
     if args.workload == DEFAULT_WORKLOAD and args.c4_steps > 0:
         # the 512^2 half of the metric: 64 sources through one hierarchy, timed after the
         # 256^3 steps (its own warm-up, steps, roofline and CPU baseline)
         c4 = run_workload("c4", args.c4_steps, 1, None, "valu", None, None,
-                          not args.no_cpu_baseline, args.split_residual)
+                          not args.no_cpu_baseline, args.split_residual, args.sweep_tile)
         c4["roofline"].update(ceiling_fields(c4["roofline"], ceiling))
         out["c4"] = {k: c4[k] for k in ("metric", "value", "unit", "steps", "warmup",
                                         "ms_per_step", "dtype", "config", "iterations",
@@ -507,7 +509,7 @@ def ceiling_fields(roof, ceiling):
 
 
 def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, precision_o,
-                 with_cpu, split=False):
+                 with_cpu, split=False, sweep_tile=0):
     """Times `steps` whole passes (setup + solve + destroy) of one workload after `warmup`
     untimed ones; returns the JSON object of the benchmark line."""
     import numpy as np
@@ -521,6 +523,7 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     args.smoother, args.contraction, args.batch, args.precision = (smoother_name, contraction_name,
                                                                     batch_o, precision_o)
     args.split_residual = split
+    args.sweep_tile = sweep_tile
     w = dict(WORKLOADS[args.workload], key=args.workload)
     if args.smoother is None:
         args.smoother = w.get("smoother", "assembled")
@@ -547,7 +550,8 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     opt = B.make_options(precision=precision, restart=w["restart"], damping=w["damping"],
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
-                         contraction=contraction, split_residual=int(args.split_residual))
+                         contraction=contraction, split_residual=int(args.split_residual),
+                         sweep_tile=args.sweep_tile)
     if w.get("fine_patch"):
         opt.fine_patch = PATCHES[w["fine_patch"]]
     torch.cuda.synchronize()

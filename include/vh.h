@@ -143,10 +143,11 @@ typedef struct vh_options {
                                per-patch smoother (2D, Full patch, VH_SMOOTHER_PATCH,
                                VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */
     int sweep_tile;         /* variant of the 64-source 2D sweep of the assembled smoother
-                               (batch = 1, VALU contraction): 0 (default) = the fastest of
-                               the 7 variants, timed on each level's grid at the first
-                               64-source solve and kept for the process; 1..7 forces one.
-                               The variants give identical results */
+                               and of the 64-source stencil (batch = 1, VALU contraction):
+                               0 (default) = the fastest of the 7 variants, timed on each
+                               level's grid at the first 64-source solve and kept for the
+                               process; 1..7 forces one.  The variants give identical
+                               results */
     int split_residual;     /* where the residual q - A u is formed: inside the kernel
                                that consumes it (the 2D smoothing sweep, Sec. 3.2 eq.
                                (smoother); the restriction of the two-grid cycle, Sec. 2.2,

@@ -465,8 +465,9 @@ bool fuses_restrict(const vh_handle*, const Level& Lv) { return Lv.fuse_restrict
 // restriction (vh_options.split_residual): 1 never, 2 wherever a kernel exists, 0 where
 // the one launch is measured faster than the two it replaces.  The fused tile stage forms
 // the residual on the tile's halo too, so on operators of many points or on small grids
-// it can cost more than the stored residual saves; the timing (one warm-up and three timed
-// launches of each, on the level's own arrays) settles it.  The choice depends only on the
+// it can cost more than the stored residual saves; the timing (each form twice, one warm-up
+// and eight timed launches each time, on the level's own arrays; the fused form must be 5 %
+// ahead) settles it.  The choice depends only on the
 // device, the level's grid, operator and smoother form and the precision, so it is kept for
 // the process; both paths give the same bits.
 std::mutex g_fuse_mu;
@@ -529,26 +530,28 @@ vh_status tune_fuse(vh_handle* hd) {
                             Lc.q, hd->s);
     };
     auto timed = [&](auto&& f, float& ms) {
+      float t = 0.f;
       hipError_t e = f();
       if (e == hipSuccess) e = hipEventRecord(e0, hd->s);
-      for (int k = 0; k < 3 && e == hipSuccess; ++k) e = f();
+      for (int k = 0; k < 8 && e == hipSuccess; ++k) e = f();
       if (e == hipSuccess) e = hipEventRecord(e1, hd->s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      ms += t;
       return e;
     };
-    float a = 0.f, b = 0.f;
+    // the two forms alternate twice; the fused one is taken only when it is clearly ahead
+    auto pick = [&](auto&& split_f, auto&& fused_f, hipError_t& e) {
+      float a = 0.f, b = 0.f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = timed(split_f, a);
+        if (e == hipSuccess) e = timed(fused_f, b);
+      }
+      return e == hipSuccess && b < 0.95f * a;
+    };
     hipError_t e = hipSuccess;
-    if (cs) {
-      e = timed(split_sweep, a);
-      if (e == hipSuccess) e = timed(fused_sweep, b);
-      Lv.fuse_sweep = e == hipSuccess && b < a;
-    }
-    if (cr && e == hipSuccess) {
-      e = timed(split_restrict, a);
-      if (e == hipSuccess) e = timed(fused_restrict, b);
-      Lv.fuse_restrict = e == hipSuccess && b < a;
-    }
+    if (cs) Lv.fuse_sweep = pick(split_sweep, fused_sweep, e);
+    if (cr && e == hipSuccess) Lv.fuse_restrict = pick(split_restrict, fused_restrict, e);
     if (e != hipSuccess) {
       st = fail(VH_EDEVICE, std::string("fusion timing: ") + hipGetErrorString(e));
       break;

@@ -428,7 +428,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=["c128", "c64"],
                     help="override the preconditioner precision")
     ap.add_argument("--sweep-tile", type=int, default=0,
-                    help="64-source 2D walk variant (1..7; 0: timed per grid)")
+                    help="64-source 2D walk variant (1..10; 0: timed per grid)")
     ap.add_argument("--split-residual", action="store_true",
                     help="separate residual launches instead of the residual formed inside "
                          "the sweep and the restriction (same results)")

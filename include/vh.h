@@ -144,9 +144,9 @@ typedef struct vh_options {
                                VH_PREC_C64 only; VH_EUNSUPPORTED otherwise); default VALU */
     int sweep_tile;         /* variant of the 64-source 2D sweep of the assembled smoother
                                and of the 64-source stencil (batch = 1, VALU contraction):
-                               0 (default) = the fastest of the 7 variants, timed on each
+                               0 (default) = the fastest of the 10 variants, timed on each
                                level's grid at the first 64-source solve and kept for the
-                               process; 1..7 forces one.  The variants give identical
+                               process; 1..10 forces one.  The variants give identical
                                results */
     int split_residual;     /* where the residual q - A u is formed: inside the kernel
                                that consumes it (the 2D smoothing sweep, Sec. 3.2 eq.

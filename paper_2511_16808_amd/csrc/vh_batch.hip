@@ -182,7 +182,11 @@ __device__ __forceinline__ void bstatic_for(F&& f) {
 // the ring turns have no branch, so the loads of later steps stay in flight.  No LDS and no
 // barrier: waves run independently.  The entries are summed in the same order as in the
 // LDS walks, so both give the same bits.
-template <int SHAPE, int MODE, class TC, class TX, class TY, int P, bool PADG>
+// LB: instead of lane reads (two per complex coefficient, vector ALU instructions), each
+// wave writes its node's coefficient words to a slot of its own in LDS and reads every
+// coefficient back as one broadcast LDS read (all lanes one address).  LDS operations of
+// one wave complete in order, so no barrier is needed; the FMAs are the same.
+template <int SHAPE, int MODE, class TC, class TX, class TY, int P, bool PADG, bool LB = false>
 __global__ __launch_bounds__(256) void kb_walk2d_s64(Grid g, int tx, const cpx<TC>* __restrict__ A,
                                                      const cpx<TX>* __restrict__ x,
                                                      const cpx<TY>* __restrict__ b,
@@ -219,6 +223,9 @@ __global__ __launch_bounds__(256) void kb_walk2d_s64(Grid g, int tx, const cpx<T
   cpx<TX> c[RG][W];
   cpx<TY> of[RG];
   unsigned gv[RG][NL];
+  // LB: one slot of 64 * NL words per wave (the step's coefficients)
+  __shared__ unsigned cws[LB ? 4 : 1][LB ? 64 * NL : 1];
+  unsigned* cw = cws[LB ? (threadIdx.x >> 6) : 0];
   auto fetch = [&](int k, auto sl) {
     constexpr int SL = decltype(sl)::value;
     const size_t cc = (size_t)min(max(xs - R + k, 0), g.nx - 1) * 64;
@@ -233,7 +240,9 @@ __global__ __launch_bounds__(256) void kb_walk2d_s64(Grid g, int tx, const cpx<T
   auto coef = [&](auto ph, auto ei) -> cpx<TC> {
     constexpr int PH = decltype(ph)::value, e = decltype(ei)::value;
     constexpr int w0 = e * WPE;
-    if constexpr (sizeof(TC) == 4) {
+    if constexpr (LB) {
+      return *(const cpx<TC>*)(cw + w0);
+    } else if constexpr (sizeof(TC) == 4) {
       cpx<TC> v;
       v.re = __int_as_float(__builtin_amdgcn_readlane((int)gv[PH][w0 / 64], w0 % 64));
       v.im = __int_as_float(__builtin_amdgcn_readlane((int)gv[PH][(w0 + 1) / 64], (w0 + 1) % 64));
@@ -253,12 +262,49 @@ __global__ __launch_bounds__(256) void kb_walk2d_s64(Grid g, int tx, const cpx<T
     fetch(k + P, std::integral_constant<int, (PH + P) % RG>{});
     if (out) {
       const int xo = xs + k - 2 * R;
+      if constexpr (LB) {
+        // the previous step's broadcast reads were issued before this write (one wave's
+        // LDS operations complete in order); the words are read back as complex values,
+        // so a compiler barrier keeps those reads after the write
+#pragma unroll
+        for (int q = 0; q < NL; ++q) cw[lane + 64 * q] = gv[PH][q];
+        asm volatile("" ::: "memory");
+      }
       cpx<TC> acc = cmk<TC>(0, 0);
-      bstatic_for<0, K>([&](auto ei) {
-        constexpr int e = decltype(ei)::value;
-        constexpr int dx = shape_off<2, SHAPE>(e, 0), dy = shape_off<2, SHAPE>(e, 1);
-        acc = cfma(coef(ph, ei), ccast<TC>(c[(PH + dx - R + 2 * RG) % RG][dy + R]), acc);
-      });
+      if constexpr (LB) {
+        // the broadcast reads go in groups of 5 entries, each group read while the
+        // previous one is summed; a compiler barrier between groups keeps the reads from
+        // all being hoisted to the top (register pressure)
+        constexpr int NG = (K + 4) / 5;
+        cpx<TC> cb[2][5];
+        auto rd = [&](auto gi) {
+          constexpr int G = decltype(gi)::value;
+          bstatic_for<0, 5>([&](auto qi) {
+            constexpr int e = G * 5 + decltype(qi)::value;
+            if constexpr (e < K) cb[G & 1][decltype(qi)::value] = coef(ph, std::integral_constant<int, e>{});
+          });
+        };
+        rd(std::integral_constant<int, 0>{});
+        bstatic_for<0, NG>([&](auto gi) {
+          constexpr int G = decltype(gi)::value;
+          if constexpr (G + 1 < NG) rd(std::integral_constant<int, G + 1>{});
+          asm volatile("" ::: "memory");
+          bstatic_for<0, 5>([&](auto qi) {
+            constexpr int e = G * 5 + decltype(qi)::value;
+            if constexpr (e < K) {
+              constexpr int dx = shape_off<2, SHAPE>(e, 0), dy = shape_off<2, SHAPE>(e, 1);
+              acc = cfma(cb[G & 1][decltype(qi)::value],
+                         ccast<TC>(c[(PH + dx - R + 2 * RG) % RG][dy + R]), acc);
+            }
+          });
+        });
+      } else {
+        bstatic_for<0, K>([&](auto ei) {
+          constexpr int e = decltype(ei)::value;
+          constexpr int dx = shape_off<2, SHAPE>(e, 0), dy = shape_off<2, SHAPE>(e, 1);
+          acc = cfma(coef(ph, ei), ccast<TC>(c[(PH + dx - R + 2 * RG) % RG][dy + R]), acc);
+        });
+      }
       const size_t o = ooff + (size_t)xo * 64;
       if constexpr (MODE == OP_APPLY)
         y[o] = ccast<TY>(acc);
@@ -401,14 +447,14 @@ __global__ __launch_bounds__(256) void kb_stencil2d_s64(Grid g, int tx,
   }
 }
 
-template <int SHAPE, int MODE, class TC, class TX, class TY, int P>
+template <int SHAPE, int MODE, class TC, class TX, class TY, int P, bool LB = false>
 static void launch_stencil_s64w(Grid g, int tx0, const void* A, const void* x, const void* b,
                                 void* y, hipStream_t st) {
   const int nsx = (g.nx + tx0 - 1) / tx0;
   const int tx = (g.nx + nsx - 1) / nsx;
   const int nsx2 = (g.nx + tx - 1) / tx;
   const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + 3) / 4);
-  kb_walk2d_s64<SHAPE, MODE, TC, TX, TY, P, false><<<nb, 256, 0, st>>>(
+  kb_walk2d_s64<SHAPE, MODE, TC, TX, TY, P, false, LB><<<nb, 256, 0, st>>>(
       g, tx, (const cpx<TC>*)A, (const cpx<TX>*)x, (const cpx<TY>*)b, (cpx<TY>*)y);
 }
 
@@ -424,7 +470,8 @@ static void launch_stencil_s64(Grid g, const void* A, const void* x, const void*
 }
 
 // 64-source 2D stencil by tile code (as the sweep's: 1 = the LDS walk, 2..7 = the
-// independent-wave walk with prefetch 2 or 3 over strips of 16, 32 or 64 columns)
+// independent-wave walk with prefetch 2 or 3 over strips of 16, 32 or 64 columns, 8..10 =
+// tiles 5..7 with the coefficients broadcast from LDS instead of lane reads)
 template <int SHAPE, int MODE, class TC, class TX, class TY>
 static void launch_stencil_s64_tile(int tile, Grid g, const void* A, const void* x, const void* b,
                                     void* y, hipStream_t st) {
@@ -434,8 +481,10 @@ static void launch_stencil_s64_tile(int tile, Grid g, const void* A, const void*
     launch_stencil_s64<SHAPE, MODE, TC, TX, TY>(g, A, x, b, y, st);
   else if (tile <= 4)
     launch_stencil_s64w<SHAPE, MODE, TC, TX, TY, 2>(g, TXS[tile - 2], A, x, b, y, st);
-  else
+  else if (tile <= 7)
     launch_stencil_s64w<SHAPE, MODE, TC, TX, TY, 3>(g, TXS[tile - 5], A, x, b, y, st);
+  else
+    launch_stencil_s64w<SHAPE, MODE, TC, TX, TY, 3, true>(g, TXS[tile - 8], A, x, b, y, st);
 }
 
 template <int DIM, int SHAPE, class TC, class TX, class TY>
@@ -782,7 +831,7 @@ static void launch_s64(Grid g, const void* G, const void* r, void* u, bool zero,
                                                        (const cpx<T>*)r, (cpx<T>*)u);
 }
 
-template <int FORM, class T, int P>
+template <int FORM, class T, int P, bool LB = false>
 static void launch_s64w(Grid g, int tx0, const void* G, const void* r, void* u, bool zero,
                         hipStream_t st) {
   static_assert(FORM == 2, "the walk relies on the zero entries of the assembled stencil");
@@ -792,16 +841,17 @@ static void launch_s64w(Grid g, int tx0, const void* G, const void* r, void* u, 
   const int nsx2 = (g.nx + tx - 1) / tx;
   const unsigned nb = (unsigned)nsx2 * (unsigned)((g.ny + 3) / 4);
   if (zero)
-    kb_walk2d_s64<BOX2, OP_APPLY, T, T, T, P, true><<<nb, 256, 0, st>>>(
+    kb_walk2d_s64<BOX2, OP_APPLY, T, T, T, P, true, LB><<<nb, 256, 0, st>>>(
         g, tx, (const cpx<T>*)G, (const cpx<T>*)r, nullptr, (cpx<T>*)u);
   else
-    kb_walk2d_s64<BOX2, OP_ADD, T, T, T, P, true><<<nb, 256, 0, st>>>(
+    kb_walk2d_s64<BOX2, OP_ADD, T, T, T, P, true, LB><<<nb, 256, 0, st>>>(
         g, tx, (const cpx<T>*)G, (const cpx<T>*)r, nullptr, (cpx<T>*)u);
 }
 
 // 64-source 2D assembled sweep by tile code (S64_TILES candidates, 1-based): 1 = the LDS
 // walk of four rows per block (16 columns per strip), 2..7 = the independent-wave walk
-// with prefetch distance 2 or 3 over strips of 16, 32 or 64 columns
+// with prefetch distance 2 or 3 over strips of 16, 32 or 64 columns, 8..10 = tiles 5..7
+// with the smoother entries broadcast from LDS
 template <int FORM, class T>
 static void launch_s64_tile(int tile, Grid g, const void* G, const void* r, void* u, bool zero,
                             hipStream_t st) {
@@ -811,8 +861,10 @@ static void launch_s64_tile(int tile, Grid g, const void* G, const void* r, void
     launch_s64<FORM, T>(g, G, r, u, zero, st);
   } else if (tile <= 4) {
     launch_s64w<FORM, T, 2>(g, TXS[tile - 2], G, r, u, zero, st);
-  } else {
+  } else if (tile <= 7) {
     launch_s64w<FORM, T, 3>(g, TXS[tile - 5], G, r, u, zero, st);
+  } else {
+    launch_s64w<FORM, T, 3, true>(g, TXS[tile - 8], G, r, u, zero, st);
   }
 }
 

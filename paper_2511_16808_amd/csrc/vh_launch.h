@@ -138,7 +138,7 @@ hipError_t batch_scatter(long long N, int S, int nsrc, const cpx<double>* X, cpx
                          hipStream_t st);
 // tile: the 64-source 2D sweep and stencil variant, 1 .. S64_TILES (0 = the default);
 // ignored by every other form and batch width
-constexpr int S64_TILES = 7;
+constexpr int S64_TILES = 10;
 constexpr int S64_DEFAULT_TILE = 7;
 // tile: the 64-source 2D variant as for batch_sweep (0 = the default)
 hipError_t batch_stencil(int dim, int shape, Grid g, int ls, int mode, int pc, const void* A,

@@ -368,7 +368,7 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
   if (o.contraction < VH_CONTRACT_VALU || o.contraction > VH_CONTRACT_MFMA_BF16X3)
     return fail(VH_EINVAL, "unknown contraction");
   if (o.sweep_tile < 0 || o.sweep_tile > S64_TILES)
-    return fail(VH_EINVAL, "sweep_tile must be in [0, 7]");
+    return fail(VH_EINVAL, "sweep_tile must be in [0, 10]");
   if (o.split_residual < 0 || o.split_residual > 2)
     return fail(VH_EINVAL, "split_residual must be 0, 1 or 2");
   if (o.contraction != VH_CONTRACT_VALU &&

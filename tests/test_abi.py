@@ -86,7 +86,7 @@ def test_footprint_counts_the_setup_peak_of_a_complex64_hierarchy():
 
 def test_setup_rejects_bad_options():
     for field, value in (("restart", 0), ("restart", 65), ("precision", 7), ("nu1", -1),
-                         ("bc", 5), ("smoother", 3), ("sweep_tile", 8), ("sweep_tile", -1),
+                         ("bc", 5), ("smoother", 3), ("sweep_tile", 11), ("sweep_tile", -1),
                          ("split_residual", 3), ("split_residual", -1)):
         o = B.make_options(**{field: value})
         with pytest.raises(B.VhError) as e:

@@ -170,12 +170,13 @@ def test_batch_3d_assembled_smoothing_and_vcycle(nsrc):
 
 
 def test_every_64_source_sweep_tile_gives_the_same_result():
-    """The seven variants of the 64-source assembled sweep (the LDS walk and the
-    independent-wave walk with prefetch 2 or 3 over strips of 16, 32 or 64 columns) sum the
-    same terms in the same order: identical outputs on an 81 x 69 grid (ragged strips, a
-    last block of one row) and its 41 x 35 level, and one of them equals the oracle's
-    relaxation per source (complex64, 1e-5).  With vh_options.sweep_tile = 0 the timing
-    tuner picks one of the seven for every smoothed level."""
+    """The ten variants of the 64-source assembled sweep and stencil (the LDS walk, the
+    independent-wave walk with prefetch 2 or 3 over strips of 16, 32 or 64 columns, and the
+    prefetch-3 walks with the entries broadcast from LDS) sum the same terms in the same
+    order: identical outputs on an 81 x 69 grid (ragged strips, a last block of one row)
+    and its 41 x 35 level, and one of them equals the oracle's relaxation per source
+    (complex64, 1e-5).  With vh_options.sweep_tile = 0 the timing tuner picks one of the
+    ten for every smoothed level."""
     c = Case(n=(81, 69), levels=3, alpha=0.3, medium="layered", seed=6, sponge_width=8,
              smoother=B.VH_SMOOTHER_ASSEMBLED, precision=1)
     ops, mg = c.oracle()
@@ -186,7 +187,7 @@ def test_every_64_source_sweep_tile_gives_the_same_result():
         data.append((rng.standard_normal((64, N)) + 1j * rng.standard_normal((64, N)),
                      rng.standard_normal((64, N)) + 1j * rng.standard_normal((64, N))))
     outs = {}
-    for tile in range(0, 8):
+    for tile in range(0, 11):
         print(f"sweep tile {tile}", flush=True)
         hd = c.gpu(batch=1, sweep_tile=tile)
         try:
@@ -197,14 +198,15 @@ def test_every_64_source_sweep_tile_gives_the_same_result():
                                                                   device="cuda"), ug)
                 res.append(ug.cpu().numpy())
                 chosen = B.vh_get_level_info(hd, l)["sweep_tile"]
-                assert (chosen == tile) if tile else (1 <= chosen <= 7), (l, chosen)
+                assert (chosen == tile) if tile else (1 <= chosen <= 10), (l, chosen)
             outs[tile] = res
         finally:
             B.vh_destroy(hd)
-    for tile in range(0, 8):
+    for tile in range(0, 11):
         for l in range(c.levels - 1):
             assert np.array_equal(outs[tile][l], outs[1][l]), (tile, l)
     for l, (q, u) in enumerate(data):
         for s in (0, 29, 63):
             ref = mg.relax(l, q[s], u[s])
             assert rel(outs[7][l][s], ref) <= 1e-5, (l, s)
+            assert rel(outs[10][l][s], ref) <= 1e-5, (l, s)

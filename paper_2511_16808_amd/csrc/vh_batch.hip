@@ -1620,9 +1620,9 @@ hipError_t batch_dcgs_a(const cpx<double>* V, size_t ldv, int j, int wcol, long 
     else
       rows = dcgs_a_launch<DG>(V, ldv, c0, nc, j, wcol, first, N, ls, part, nb, st);
     VHB_CHECK();
-    kb_reduce<<<dim3(2 * DG + 3, RSL), 256, 0, st>>>(part, rows, ls, part2);
+    kb_reduce<<<dim3(PA_ROWS, RSL), 256, 0, st>>>(part, rows, ls, part2);
     VHB_CHECK();
-    kb_reduce_fin<<<2 * DG + 3, 64, 0, st>>>(part2, 1 << ls, K->pa + (size_t)q * 27 * 64);
+    kb_reduce_fin<<<PA_ROWS, 64, 0, st>>>(part2, 1 << ls, K->pa + (size_t)q * PA_ROWS * 64);
     VHB_CHECK();
   }
   return hipSuccess;
@@ -1639,11 +1639,11 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
   };
   auto bv = [&](int i) {
     const int q = i / DG, li = i % DG;
-    return K->pa[((size_t)q * 27 + li) * 64 + s];
+    return K->pa[((size_t)q * PA_ROWS + li) * 64 + s];
   };
   auto dv = [&](int i) {
     const int q = i / DG, li = i % DG;
-    return K->pa[((size_t)q * 27 + DG + li) * 64 + s];
+    return K->pa[((size_t)q * PA_ROWS + DG + li) * 64 + s];
   };
   const cpx<double> e = K->pa[(size_t)(2 * DG) * 64 + s];
   const double f = K->pa[(size_t)(2 * DG + 1) * 64 + s].re;
@@ -1726,17 +1726,22 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
 // pass B over the column group [c0, c0 + nc): t0 = V_j - sum xb_i v_i,
 // t1 = V_{j+1} - sum yd_i v_i (minus gam u in the first group); the last group scales
 // by ib and inu.  Columns past nc re-read the last one with a zero coefficient.
-template <int NJ>
+// Pass B over columns c0 .. c0+nc-1 of the basis in one sweep of the vectors: the
+// coefficients of every column and source sit in LDS ([column][source], nc * S each for
+// x and y), the columns are taken eight at a time with their loads in flight together,
+// and u, w are read and written once however many columns there are.
 __global__ __launch_bounds__(256) void kb_dcgs_b(cpx<double>* __restrict__ V, size_t ldv, int c0,
                                                  int nc, int j, int first, int last, long long N,
                                                  int ls, const BatchKrylovDev* __restrict__ K,
                                                  cpx<float>* __restrict__ lo) {
-  __shared__ cpx<double> xs[NJ][64], ys[NJ][64];
+  extern __shared__ cpx<double> cs[];
   const int S = 1 << ls;
-  for (int e = threadIdx.x; e < NJ * 64; e += 256) {
-    const int q = e >> 6;
-    xs[q][e & 63] = q < nc ? K->xb[(size_t)(c0 + q) * 64 + (e & 63)] : cmk(0.0, 0.0);
-    ys[q][e & 63] = q < nc ? K->yd[(size_t)(c0 + q) * 64 + (e & 63)] : cmk(0.0, 0.0);
+  cpx<double>* xs = cs;
+  cpx<double>* ys = cs + (size_t)nc * S;
+  for (int e = threadIdx.x; e < nc * S; e += 256) {
+    const int q = e >> ls, sv = e & (S - 1);
+    xs[e] = K->xb[(size_t)(c0 + q) * 64 + sv];
+    ys[e] = K->yd[(size_t)(c0 + q) * 64 + sv];
   }
   __syncthreads();
   const int s = threadIdx.x & (S - 1);
@@ -1745,18 +1750,27 @@ __global__ __launch_bounds__(256) void kb_dcgs_b(cpx<double>* __restrict__ V, si
   cpx<double>* u = V + (size_t)j * ldv;
   cpx<double>* w = V + (size_t)(j + 1) * ldv;
   const long long total = N << ls;
+  constexpr int UN = 8;
   for (long long t = (long long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x; t < total;
        t += (long long)gridDim.x * 256) {
     const size_t o = (size_t)t;
     cpx<double> t0 = u[o], t1 = w[o];
     if (first) t1 = t1 - gam * t0;
-    if (nc > 0) {
+    int q = 0;
+    for (; q + UN <= nc; q += UN) {
+      cpx<double> v[UN];
 #pragma unroll
-      for (int q = 0; q < NJ; ++q) {
-        const cpx<double> v = V[(size_t)(c0 + (q < nc ? q : nc - 1)) * ldv + o];
-        t0 = t0 - xs[q][s] * v;
-        t1 = t1 - ys[q][s] * v;
+      for (int r = 0; r < UN; ++r) v[r] = V[(size_t)(c0 + q + r) * ldv + o];
+#pragma unroll
+      for (int r = 0; r < UN; ++r) {
+        t0 = t0 - xs[(q + r) * S + s] * v[r];
+        t1 = t1 - ys[(q + r) * S + s] * v[r];
       }
+    }
+    for (; q < nc; ++q) {
+      const cpx<double> v = V[(size_t)(c0 + q) * ldv + o];
+      t0 = t0 - xs[q * S + s] * v;
+      t1 = t1 - ys[q * S + s] * v;
     }
     if (last) {
       t0 = ib * t0;
@@ -1778,18 +1792,18 @@ hipError_t batch_dcgs_fin(BatchKrylovDev* K, int j, int S, int closing, hipStrea
 hipError_t batch_dcgs_b(cpx<double>* V, size_t ldv, int j, long long N, int ls,
                         const BatchKrylovDev* K, cpx<float>* lo, hipStream_t st) {
   if (j < 0 || j >= MMAX) return hipErrorInvalidValue;
-  const int ng = j > 0 ? (j + DG - 1) / DG : 1;
+  // columns per sweep: the coefficients of all of them in at most 48 KB of LDS (every
+  // column in one sweep up to 24 columns at 64 sources, 48 at 32, ...)
+  const int S = 1 << ls;
+  const int gb = (48 * 1024) / (2 * S * (int)sizeof(cpx<double>));
+  const int ng = j > 0 ? (j + gb - 1) / gb : 1;
   const long long total = N << ls;
   const unsigned nb = (unsigned)std::min<long long>((total + 255) / 256, 4096);
   for (int q = 0; q < ng; ++q) {
-    const int c0 = q * DG, nc = j - c0 < DG ? j - c0 : DG;
+    const int c0 = q * gb, nc = j - c0 < gb ? j - c0 : gb;
     const int first = q == 0, last = q == ng - 1;
-    if (nc <= 4)
-      kb_dcgs_b<4><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
-    else if (nc <= 8)
-      kb_dcgs_b<8><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
-    else
-      kb_dcgs_b<DG><<<nb, 256, 0, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
+    const size_t lds = (size_t)2 * (nc > 0 ? nc : 0) * S * sizeof(cpx<double>);
+    kb_dcgs_b<<<nb, 256, lds, st>>>(V, ldv, c0, nc, j, first, last, N, ls, K, lo);
     VHB_CHECK();
   }
   return hipSuccess;

@@ -29,6 +29,10 @@ struct KrylovDev {
 
 // Device-resident FGMRES state of a batch of up to 64 sources (FP64); every array
 // is source-fastest with a stride of 64.
+constexpr int DG = 12;  // basis columns per group of the delayed reduction pass
+constexpr int PA_ROWS = 2 * DG + 3;            // pass-A sums per column group
+constexpr int PA_GROUPS = (MMAX + DG) / DG;    // column groups of j <= MMAX
+
 struct BatchKrylovDev {
   cpx<double> H[MMAX * (MMAX + 1) * 64];
   double cs[MMAX * 64];
@@ -42,7 +46,7 @@ struct BatchKrylovDev {
   double inv_nrm[64];
   int kcols[64];          // columns used by the next solution update (0 = frozen source)
   // delayed reorthogonalisation (one reduction pass and one update pass per step)
-  cpx<double> pa[6 * 27 * 64];         // pass-A sums, column group q at rows q*27 ...
+  cpx<double> pa[PA_GROUPS * PA_ROWS * 64];  // pass-A sums, column group q at rows q*PA_ROWS
   cpx<double> cprev[(MMAX + 1) * 64];  // first-pass coefficients of the last A z
   double nuprev[64];                   // norm of its lagged residual
   cpx<double> xb[MMAX * 64];           // pass B: v_j = (u - sum xb_i v_i) * ib
@@ -50,7 +54,6 @@ struct BatchKrylovDev {
   cpx<double> gam[64];
   double ib[64], inu[64];
 };
-constexpr int DG = 12;  // basis columns per group of the delayed passes
 
 hipError_t fill(void* p, size_t n, int prec, double re, double im, hipStream_t s);
 hipError_t convert(const void* a, int pa, void* b, int pb, size_t n, hipStream_t s);

@@ -1430,9 +1430,11 @@ __global__ void kb_finalize(BatchKrylovDev* __restrict__ K, int j, int S) {
   auto H = [&](int col, int row) -> cpx<double>& {
     return K->H[((size_t)col * ldh + row) * 64 + s];
   };
+#pragma unroll 8
   for (int i = 0; i <= j; ++i) H(j, i) = K->h1[i * 64 + s] + K->h2[i * 64 + s];
   const double nrm = sqrt(K->nrm2[s].re);
   H(j, j + 1) = cmk(nrm, 0.0);
+#pragma unroll 8
   for (int i = 0; i < j; ++i) {
     const cpx<double> a = H(j, i), b = H(j, i + 1);
     const double c = K->cs[i * 64 + s];
@@ -1479,16 +1481,22 @@ __global__ void kb_cycle_init(BatchKrylovDev* __restrict__ K, int m, int S) {
 }
 
 // y = R^{-1} g over the first kcols[s] columns of source s (0: nothing to update)
+// the solved y_q are kept in LDS as they are produced, so that the inner products read
+// only H from memory (loads independent of each other, issued several at a time)
 __global__ void kb_backsolve(BatchKrylovDev* __restrict__ K, int S) {
+  __shared__ cpx<double> ys[MMAX][64];
   const int s = threadIdx.x;
   if (s >= S) return;
   const int ldh = MMAX + 1;
   const int k = K->kcols[s];
   for (int i = k - 1; i >= 0; --i) {
     cpx<double> acc = K->g[i * 64 + s];
+#pragma unroll 8
     for (int q = i + 1; q < k; ++q)
-      acc = acc - K->H[((size_t)q * ldh + i) * 64 + s] * K->y[q * 64 + s];
-    K->y[i * 64 + s] = acc * cinv(K->H[((size_t)i * ldh + i) * 64 + s]);
+      acc = acc - K->H[((size_t)q * ldh + i) * 64 + s] * ys[q][s];
+    const cpx<double> yi = acc * cinv(K->H[((size_t)i * ldh + i) * 64 + s]);
+    ys[i][s] = yi;
+    K->y[i * 64 + s] = yi;
   }
 }
 
@@ -1652,6 +1660,7 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
   bool bad = false;
   if (j >= 1) {
     double bb = 0.0;
+#pragma unroll 8
     for (int i = 0; i < j; ++i) {
       const cpx<double> b = bv(i);
       bb += b.re * b.re + b.im * b.im;
@@ -1660,8 +1669,10 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
     beta = b2 > 0.0 ? sqrt(b2) : 0.0;
     const double nu = K->nuprev[s];
     const int jj = j - 1;  // the column completed now
+#pragma unroll 8
     for (int i = 0; i < j; ++i) H(jj, i) = K->cprev[i * 64 + s] + nu * bv(i);
     const double nrm = nu * beta;
+#pragma unroll 8
     for (int i = 0; i < jj; ++i) {
       const cpx<double> a = H(jj, i), b = H(jj, i + 1);
       const double c = K->cs[i * 64 + s];
@@ -1697,6 +1708,7 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
   if (!closing) {
     const double ibeta = beta > 0.0 ? 1.0 / beta : 0.0;
     cpx<double> bd = cmk(0.0, 0.0);
+#pragma unroll 8
     for (int i = 0; i < j; ++i) {
       const cpx<double> b = bv(i);
       bd = cfma_conj(b, dv(i), bd);
@@ -1704,6 +1716,7 @@ __global__ void kb_dcgs_fin(BatchKrylovDev* __restrict__ K, int j, int S, int cl
     const cpx<double> cj = ibeta * (e - bd);
     const cpx<double> gam = ibeta * cj;
     double cc = cj.re * cj.re + cj.im * cj.im;
+#pragma unroll 8
     for (int i = 0; i < j; ++i) {
       const cpx<double> d = dv(i), b = bv(i);
       cc += d.re * d.re + d.im * d.im;

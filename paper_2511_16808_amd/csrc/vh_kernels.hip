@@ -642,6 +642,38 @@ __device__ __forceinline__ unsigned dpp_max(unsigned v, int ctrl_sel) {
   return o > v ? o : v;
 }
 
+// acc += c p with the FMAs of the elimination update in its order (re: c.re p.re, then
+// -c.im p.im; im: c.re p.im, then c.im p.re), p = lane L of each 16-lane row of the
+// register pair, read through the FMA's own row-broadcast operand.  The s_nop covers the
+// wait a broadcast operand needs after a vector ALU write to it.
+template <int L>
+__device__ __forceinline__ void cupd_rowb(cpx<double>& acc, const cpx<double>& c,
+                                          const cpx<double>& p) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %3, %4 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %2, %5 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc.re), "+v"(acc.im)
+      : "v"(p.re), "v"(p.im), "v"(c.re), "v"(c.im), "i"(L));
+}
+// the same for two entries (one wait for both)
+template <int L0, int L1>
+__device__ __forceinline__ void cupd2_rowb(cpx<double>& a0, cpx<double>& a1, const cpx<double>& c,
+                                           const cpx<double>& p0, const cpx<double>& p1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, -%5, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %6, %8 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, -%7, %9 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %7, %8 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %6, %9 row_newbcast:%11 row_mask:0xf bank_mask:0xf"
+      : "+v"(a0.re), "+v"(a0.im), "+v"(a1.re), "+v"(a1.im)
+      : "v"(p0.re), "v"(p0.im), "v"(p1.re), "v"(p1.im), "v"(c.re), "v"(c.im), "i"(L0), "i"(L1));
+}
+
 template <int DIM, int SHAPE, int PATCH, class T>
 __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
                                                      double w, cpx<T>* __restrict__ G, Slab sl) {
@@ -743,19 +775,42 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     const double dd = 1.0 / (ps.re * ps.re + ps.im * ps.im);
     const cpx<double> inv = cmk(ps.re * dd, -ps.im * dd);
     const cpx<double> c = am ? cmk(0.0, 0.0) : cmk(0.0, 0.0) - as * inv;
+    if constexpr (GW % 16 == 0) {
+      // a patch fills whole 16-lane rows: every row reads the pivot row once (lane
+      // 16r + i entries i and 16 + i, two LDS reads per lane instead of Np - 1) and each
+      // FMA takes its entry from lane m % 16 of its row through the operand broadcast
+      const int li = (int)(lane & 15u);
+      const cpx<double> pA = pr[li];
+      const cpx<double> pB = pr[16 + li < Np ? 16 + li : 0];
+      static_for<1, Np>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        if constexpr (m % 2 == 1) {
+          cpx<double> t0 = a[m];
+          if constexpr (m + 1 < Np) {
+            cpx<double> t1 = a[m + 1];
+            cupd2_rowb<m % 16, (m + 1) % 16>(t0, t1, c, m < 16 ? pA : pB, m + 1 < 16 ? pA : pB);
+            a[m] = t1;
+          } else {
+            cupd_rowb<m % 16>(t0, c, m < 16 ? pA : pB);
+          }
+          a[m - 1] = t0;
+        }
+      });
+    } else {
 #pragma unroll
-    for (int m0 = 0; m0 + 1 < Np; m0 += CH) {
-      cpx<double> pb[CH];
+      for (int m0 = 0; m0 + 1 < Np; m0 += CH) {
+        cpx<double> pb[CH];
 #pragma unroll
-      for (int q = 0; q < CH; ++q)
-        if (m0 + q + 1 < Np) pb[q] = pr[m0 + q + 1];
+        for (int q = 0; q < CH; ++q)
+          if (m0 + q + 1 < Np) pb[q] = pr[m0 + q + 1];
 #pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        if (m0 + q + 1 < Np) {
-          cpx<double> t;
-          t.re = fma(-c.im, pb[q].im, fma(c.re, pb[q].re, a[m0 + q + 1].re));
-          t.im = fma(c.im, pb[q].re, fma(c.re, pb[q].im, a[m0 + q + 1].im));
-          a[m0 + q] = t;
+        for (int q = 0; q < CH; ++q) {
+          if (m0 + q + 1 < Np) {
+            cpx<double> t;
+            t.re = fma(-c.im, pb[q].im, fma(c.re, pb[q].re, a[m0 + q + 1].re));
+            t.im = fma(c.im, pb[q].re, fma(c.re, pb[q].im, a[m0 + q + 1].im));
+            a[m0 + q] = t;
+          }
         }
       }
     }

@@ -152,10 +152,11 @@ typedef struct vh_options {
                                that consumes it (the 2D smoothing sweep, Sec. 3.2 eq.
                                (smoother); the restriction of the two-grid cycle, Sec. 2.2,
                                2D and 3D-trilinear), so that it is never stored, or by a
-                               separate residual launch.  0 (default): per level, whichever
-                               is faster, timed at setup on the level's own grid and kept
-                               for the process; 1: always separate; 2: inside wherever such
-                               a kernel exists.  Results are identical bit for bit */
+                               separate residual launch.  0 (default): per level, timed at
+                               setup on the level's own grid (the one-launch form when it
+                               is at least 5 % faster) and kept for the process; 1: always
+                               separate; 2: inside wherever such a kernel exists.  Results
+                               are identical bit for bit */
 } vh_options;
 
 typedef struct vh_solve_stats {

@@ -52,7 +52,7 @@ WORKLOADS = {
                     "6-level trilinear V(1,1), Full 3x3x3 Vanka, complex64 preconditioner, "
                     "FGMRES(30) in complex128",
                dim=3, n=(257, 257, 257), levels=6, alpha=0.5, medium="geophysical_3d", seed=3,
-               precision=1, restart=30, damping=[1.08, 0.5, 1.0, 0.4],
+               precision=1, restart=30, damping=[1.08, 0.5, 1.0, 0.4], smoother="symmetric",
                sample=dict(n=(65, 65, 65), levels=4)),
     "p2": dict(desc="the paper's own 2D configuration scaled to 1025x1025 nodes: kappa^2 linear in "
                     "depth over [0.25, 1] (Table heterogeneous2D model), 10 ppw at kappa_max, gamma = 0, "
@@ -429,6 +429,9 @@ def main():
                     help="override the preconditioner precision")
     ap.add_argument("--sweep-tile", type=int, default=0,
                     help="64-source 2D walk variant (1..10; 0: timed per grid)")
+    ap.add_argument("--sym-planes", type=int, default=0,
+                    help="3D symmetric-half sweep: planes per workgroup (-1: one plane per "
+                         "workgroup; 0: chosen from the grid)")
     ap.add_argument("--split-residual", action="store_true",
                     help="separate residual launches instead of the residual formed inside "
                          "the sweep and the restriction (same results)")
@@ -461,7 +464,7 @@ def main():
     ceiling = copy_ceiling()
     out = run_workload(args.workload, args.steps, args.warmup, args.smoother, args.contraction,
                        args.batch, args.precision, not args.no_cpu_baseline,
-                       args.split_residual, args.sweep_tile)
+                       args.split_residual, args.sweep_tile, args.sym_planes)
     out["roofline"].update(ceiling_fields(out["roofline"], ceiling))
     if args.workload == DEFAULT_WORKLOAD and args.c4_steps > 0:
         # the 512^2 half of the metric: 64 sources through one hierarchy, timed after the
@@ -509,7 +512,7 @@ def ceiling_fields(roof, ceiling):
 
 
 def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, precision_o,
-                 with_cpu, split=False, sweep_tile=0):
+                 with_cpu, split=False, sweep_tile=0, sym_planes=0):
     """Times `steps` whole passes (setup + solve + destroy) of one workload after `warmup`
     untimed ones; returns the JSON object of the benchmark line."""
     import numpy as np
@@ -551,7 +554,7 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
                          contraction=contraction, split_residual=int(args.split_residual),
-                         sweep_tile=args.sweep_tile)
+                         sweep_tile=args.sweep_tile, sym_planes=sym_planes)
     if w.get("fine_patch"):
         opt.fine_patch = PATCHES[w["fine_patch"]]
     torch.cuda.synchronize()
@@ -601,7 +604,9 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
     else:
         bytes_per_launch = N * esz * (E[0] + 3 * width)
     achieved = bytes_per_launch / (ms_l / n_l * 1e-3) / 1e9 if n_l else None
-    if width == 1:
+    if width == 1 and info[0].get("sym_planes", 0) > 0:
+        kname = "k_vanka_sweep_sym3z"  # the 3D symmetric half walked along z
+    elif width == 1:
         kname = "k_vanka_sweep_sym" if args.smoother == "symmetric" else "k_vanka_sweep"
     elif contraction != B.VH_CONTRACT_VALU and width >= 16:
         kname = "kb_sweep_mfma"

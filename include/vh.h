@@ -157,6 +157,13 @@ typedef struct vh_options {
                                is at least 5 % faster) and kept for the process; 1: always
                                separate; 2: inside wherever such a kernel exists.  Results
                                are identical bit for bit */
+    int sym_planes;         /* 3D symmetric-half sweep (VH_SMOOTHER_SYMMETRIC): how many
+                               z-planes one workgroup walks, reading the entries of each
+                               plane once for its own terms and, from the caches, for the
+                               mirrored terms of the planes above.  0 (default): 24 where
+                               the level still gets >= 1024 workgroups, else one plane per
+                               workgroup; -1: one plane per workgroup; 1..64 forced.  The
+                               forms agree to rounding (they sum in different orders)    */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -197,6 +204,8 @@ typedef struct vh_level_info {
     int sweep_tile;         /* variant of the 64-source 2D sweep in use (0: none chosen)  */
     int fused_sweep;        /* 1: the level's smoothing steps form the residual in the sweep */
     int fused_restrict;     /* 1: the restriction to the next level forms the residual    */
+    int sym_planes;         /* 3D symmetric half: z-planes one workgroup of the level's
+                               sweep walks (0: not symmetric, or one plane per workgroup) */
 } vh_level_info;
 
 typedef struct vh_handle vh_handle;

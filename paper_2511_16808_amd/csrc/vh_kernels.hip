@@ -477,15 +477,38 @@ __global__ __launch_bounds__(256) void k_vanka_sweep(Grid g, const cpx<T>* __res
   const size_t Np = (size_t)g.Np;
   const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
   cpx<T> acc = cmk<T>(0, 0);
-#pragma unroll 1
-  for (int e0 = 0; e0 < E; e0 += UNR) {
+  if constexpr (DIM == 2 && FORM == SM_FULL && sizeof(T) == 8 && RS < 0) {
+    // 81 complex128 entries: in one sequence the compiler issues the loads one at a time,
+    // each waited for; in groups of 16, issued together before the group's products, a
+    // group is in flight at once (same summation order)
+    constexpr int NG = 16;
+    static_for<0, (E + NG - 1) / NG>([&](auto gc) {
+      constexpr int e0 = decltype(gc)::value * NG, ne = (E - e0) < NG ? (E - e0) : NG;
+      cpx<T> gv[ne];
+      static_for<0, ne>([&](auto kc) {
+        gv[decltype(kc)::value] = ld_stream(G + (size_t)(e0 + decltype(kc)::value) * Np + ip);
+      });
+      // pins the group's loads ahead of its products (the scheduler would otherwise move
+      // each load down to its product)
 #pragma unroll
-    for (int q = 0; q < UNR; ++q) {
-      const int e = e0 + q;
-      const int dx = sm_off<DIM, FORM>(e, 0), dy = sm_off<DIM, FORM>(e, 1),
-                dz = sm_off<DIM, FORM>(e, 2);
-      const cpx<T> gv = NT ? ld_stream(G + (size_t)e * Np + ip) : G[(size_t)e * Np + ip];
-      acc = cfma(gv, t0[(dz * SY + dy) * SX + dx], acc);
+      for (int k = 0; k < ne; ++k) asm volatile("" : "+v"(gv[k].re), "+v"(gv[k].im));
+      static_for<0, ne>([&](auto kc) {
+        constexpr int e = e0 + decltype(kc)::value;
+        constexpr int dx = sm_off<DIM, FORM>(e, 0), dy = sm_off<DIM, FORM>(e, 1);
+        acc = cfma(gv[decltype(kc)::value], t0[dy * SX + dx], acc);
+      });
+    });
+  } else {
+#pragma unroll 1
+    for (int e0 = 0; e0 < E; e0 += UNR) {
+#pragma unroll
+      for (int q = 0; q < UNR; ++q) {
+        const int e = e0 + q;
+        const int dx = sm_off<DIM, FORM>(e, 0), dy = sm_off<DIM, FORM>(e, 1),
+                  dz = sm_off<DIM, FORM>(e, 2);
+        const cpx<T> gv = NT ? ld_stream(G + (size_t)e * Np + ip) : G[(size_t)e * Np + ip];
+        acc = cfma(gv, t0[(dz * SY + dy) * SX + dx], acc);
+      }
     }
   }
   if constexpr (RS >= 0)
@@ -949,6 +972,8 @@ __host__ __device__ constexpr int sym_entries() { return (ipow(5, DIM) + 1) / 2;
 template <class T>
 __host__ __device__ constexpr int sym_ty() { return sizeof(T) == 4 ? 8 : 4; }
 
+constexpr int SYM_GROUP = 16;
+
 template <int DIM, bool ZERO, class T, int RS = -1>
 __global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* __restrict__ S,
                                                          double w, const cpx<T>* __restrict__ r,
@@ -1008,26 +1033,38 @@ __global__ __launch_bounds__(512) void k_vanka_sweep_sym(Grid g, const cpx<T>* _
   const cpx<T>* t0 = tile + (HZ * SY + (ly + VT_H)) * SX + (lx + VT_H);
   cpx<T> acc = cmk<T>(0, 0);
   // own entries: S(i, i + d), d >= 0; the plane base is uniform, the per-lane part a
-  // 32-bit offset
-#pragma unroll
-  for (int q = 0; q < EH; ++q) {
-    const int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
-              dz = shape_off<DIM, BOX2>(C + q, 2);
-    const cpx<T>* Sq = S + (size_t)q * Np;
-    acc = cfma(Sq[ipu], t0[(dz * SY + dy) * SX + dx], acc);
-  }
-  // mirrored entries: S(i - d, i) stored at i - d, d > 0 (cached loads: which of the two
-  // reads of an entry comes first depends on the tile order).  A
+  // 32-bit offset.  Mirrored entries: S(i - d, i) stored at i - d, d > 0 (cached loads:
+  // which of the two reads of an entry comes first depends on the tile order).  A
   // neighbour i - d outside the grid has r = 0 in the tile, so its entry only has to be
   // finite: the address stays inside the allocation (a zero guard of sym_guard() entries
-  // precedes plane 0; earlier planes otherwise) and every load is unconditional.
-#pragma unroll
-  for (int q = 1; q < EH; ++q) {
-    const int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
-              dz = shape_off<DIM, BOX2>(C + q, 2);
-    const cpx<T>* Sm = S + (size_t)q * Np - (long long)(dx + sy * dy + sz * dz);
-    acc = cfma(Sm[ipu], t0[-((dz * SY + dy) * SX + dx)], acc);
-  }
+  // precedes plane 0; earlier planes otherwise) and every load is unconditional.  In 3D
+  // the loads go in groups of SYM_GROUP, each group issued before its products, so that
+  // a group is in flight together (in one sequence the loads are otherwise issued one at
+  // a time, each waited for).
+  constexpr int NG = DIM == 3 ? SYM_GROUP : 2 * EH;
+  static_for<0, (2 * EH - 1 + NG - 1) / NG>([&](auto gc) {
+    constexpr int j0 = decltype(gc)::value * NG;
+    constexpr int nj = (2 * EH - 1 - j0) < NG ? (2 * EH - 1 - j0) : NG;
+    // sequence j: the own entry q = j for j < EH, then the mirrored entry q = j - EH + 1
+    cpx<T> sv[nj];
+    static_for<0, nj>([&](auto kc) {
+      constexpr int j = j0 + decltype(kc)::value;
+      constexpr int q = j < EH ? j : j - EH + 1;
+      constexpr int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
+                    dz = shape_off<DIM, BOX2>(C + q, 2);
+      const cpx<T>* Sq = S + (size_t)q * Np;
+      sv[decltype(kc)::value] =
+          j < EH ? Sq[ipu] : (Sq - (long long)(dx + sy * dy + sz * dz))[ipu];
+    });
+    static_for<0, nj>([&](auto kc) {
+      constexpr int j = j0 + decltype(kc)::value;
+      constexpr int q = j < EH ? j : j - EH + 1;
+      constexpr int dx = shape_off<DIM, BOX2>(C + q, 0), dy = shape_off<DIM, BOX2>(C + q, 1),
+                    dz = shape_off<DIM, BOX2>(C + q, 2);
+      constexpr int to = (dz * SY + dy) * SX + dx;
+      acc = cfma(sv[decltype(kc)::value], t0[j < EH ? to : -to], acc);
+    });
+  });
   const T dw = (T)(w / (double)patch_count<DIM, PATCH_FULL>(g, x, y, z));
   acc = cmk<T>(dw * acc.re, dw * acc.im);
   if constexpr (RS >= 0)
@@ -1057,16 +1094,192 @@ long long sym_guard(const Grid& g) {
   return 2 + 2LL * g.nxp + (g.dim == 3 ? 2LL * g.nxp * g.ny : 0);
 }
 
+// entries after the last plane that the mirrored loads of the 3D sweep may touch
+long long sym_tail(const Grid& g) { return g.dim == 3 ? 2 + 2LL * g.nxp : 0; }
+
+// 3D form of the symmetric-half sweep, walked along z.  A block takes a 32 x 8 column of
+// nodes through a chunk of planes (24 by default).  At plane z each lane reads the 63
+// stored entries of its node once for its own terms, S(i, i + d) r(i + d), and, in the
+// same step, the entries stored at the nodes i - d of plane z for the mirrored terms
+// S(i - d, i) r(i - d) of the targets i in planes z, z + 1, z + 2: those loads touch the
+// lines the neighbouring lanes of the block are loading for their own terms at that
+// moment, so they come from the caches instead of reaching back two planes.  The mirrored
+// sums of the next two planes ride along in registers; a chunk starts two planes early to
+// collect them for its first targets.  The residual planes z .. z + 2 (with a halo of 2,
+// zero outside the grid) sit in a four-slot LDS ring; the slot of plane z + 3 is filled
+// while plane z is summed.  One stencil row (5 own and 5 mirrored loads) per iteration
+// keeps 62 VGPRs and 8 waves per SIMD; tiles of 64 x 8, 64 x 16, 32 x 16 and 16 x 16 and
+// chunks of 12 to 32 planes measured within 10 % of this one at 257^3.
+constexpr int SZ_TX = 32, SZ_TY = 8;
+
+template <bool ZERO, class T>
+__global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
+                                                                    const cpx<T>* __restrict__ S,
+                                                                    double w,
+                                                                    const cpx<T>* __restrict__ r,
+                                                                    cpx<T>* __restrict__ u,
+                                                                    int zc) {
+  constexpr int RX = SZ_TX + 4, RY = SZ_TY + 4, NR = RX * RY, NT = SZ_TX * SZ_TY;
+  constexpr int NRT = (NR + NT - 1) / NT;
+  __shared__ cpx<T> ring[4][NR];
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int nbx = (g.nx + SZ_TX - 1) / SZ_TX, nby = (g.ny + SZ_TY - 1) / SZ_TY;
+  const int bx = (int)(b % (unsigned)nbx), by = (int)((b / (unsigned)nbx) % (unsigned)nby);
+  const int bz = (int)(b / (unsigned)(nbx * nby));
+  const int x0 = bx * SZ_TX, y0 = by * SZ_TY;
+  const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
+  const int lx = (int)threadIdx.x % SZ_TX, ly = (int)threadIdx.x / SZ_TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool own = x < g.nx && y < g.ny;
+  const int xc = min(x, g.nx - 1), yc = min(y, g.ny - 1);  // idle lanes load for a grid node
+  const size_t Np = (size_t)g.Np;
+  cpx<T> rv[NRT];
+  auto fetch = [&](int zz) {
+#pragma unroll
+    for (int k = 0; k < NRT; ++k) {
+      const int e = (int)threadIdx.x + NT * k;
+      const int gx = x0 + e % RX - 2, gy = y0 + e / RX - 2;
+      rv[k] = (e < NR && inside(g, gx, gy, zz)) ? r[lin(g, gx, gy, zz)] : cmk<T>(0, 0);
+    }
+  };
+  auto store = [&](int zz) {
+#pragma unroll
+    for (int k = 0; k < NRT; ++k) {
+      const int e = (int)threadIdx.x + NT * k;
+      if (e < NR) ring[zz & 3][e] = rv[k];
+    }
+  };
+  const int zs = z0 >= 2 ? z0 - 2 : 0;
+  fetch(zs);
+  store(zs);
+  fetch(zs + 1);
+  store(zs + 1);
+  fetch(zs + 2);
+  store(zs + 2);
+  __syncthreads();
+  cpx<T> m0 = cmk<T>(0, 0), m1 = cmk<T>(0, 0), m2 = cmk<T>(0, 0);
+  const int tix = (ly + 2) * RX + (lx + 2);
+  unsigned ipu = 0;  // padded index of (xc, yc, z) < 2^31 (checked on the host)
+  cpx<T> acc = cmk<T>(0, 0);
+  // one stencil row (dy, DZ) of the half, dx = DXLO .. 2 (entry q = 25 DZ + 5 dy + dx).
+  // OWN: the node's own terms S(i, i + d) r(i + d).  Mirrored terms: the source
+  // (x - dx, y - dy) of plane z gives S(i - d, i) r(i - d) to the target of plane z + DZ.
+  // A source outside the grid has r = 0 in the ring, so its entry only has to be finite:
+  // the address, the lane's index shifted by a block-uniform amount, stays inside the
+  // allocation (zero guards before plane 0 and after the last plane, earlier or later
+  // rows and planes otherwise) and one 32-bit lane offset serves every load.
+  auto row = [&](auto dzc, auto dxlo, auto ownc, int z, int dy) {
+    constexpr int DZ = decltype(dzc)::value, DXLO = decltype(dxlo)::value;
+    constexpr bool OWN = decltype(ownc)::value;
+    const cpx<T>* S0 = S + (long long)(25 * DZ + 5 * dy) * (long long)Np;
+    const cpx<T>* ro = ring[(z + DZ) & 3] + tix + dy * RX;
+    const cpx<T>* rm = ring[z & 3] + tix - dy * RX;
+    const long long sh = (long long)g.nxp * dy;
+    constexpr int NE = 3 - DXLO;
+    // the row's loads first, then its products, so that they are in flight together
+    cpx<T> so[NE], sm[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int dx = DXLO + k;
+      const cpx<T>* Sq = S0 + (long long)dx * (long long)Np;
+      if constexpr (OWN) so[k] = Sq[ipu];
+      sm[k] = (Sq - (sh + dx))[ipu];
+    }
+    cpx<T>& m = DZ == 0 ? m0 : (DZ == 1 ? m1 : m2);
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int dx = DXLO + k;
+      if constexpr (OWN) acc = cfma(so[k], ro[dx], acc);
+      if (DZ > 0 || DXLO < 0 || dx > 0) m = cfma(sm[k], rm[-dx], m);
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using IM2 = std::integral_constant<int, -2>;
+  using YES = std::true_type;
+  using NO = std::false_type;
+  auto rotate = [&]() {
+    m0 = m1;
+    m1 = m2;
+    m2 = cmk<T>(0, 0);
+  };
+  // the (at most two) planes before the chunk: mirrored terms of its first targets only
+  for (int z = zs; z < z0; ++z) {
+    fetch(z + 3);
+    ipu = (unsigned)(xc + g.nxp * (yc + g.ny * z));
+    if (z0 - z <= 1) {
+#pragma unroll 1
+      for (int dy = -2; dy <= 2; ++dy) row(I1{}, IM2{}, NO{}, z, dy);
+    }
+#pragma unroll 1
+    for (int dy = -2; dy <= 2; ++dy) row(I2{}, IM2{}, NO{}, z, dy);
+    rotate();
+    store(z + 3);
+    __syncthreads();
+  }
+  for (int z = z0; z < z1; ++z) {
+    fetch(z + 3);
+    ipu = (unsigned)(xc + g.nxp * (yc + g.ny * z));
+    acc = cmk<T>(0, 0);
+    // targets beyond the chunk take mirrored terms that are then dropped: their loads hit
+    // the lines just read for the own terms
+    row(I0{}, I0{}, YES{}, z, 0);
+#pragma unroll 1
+    for (int dy = 1; dy <= 2; ++dy) row(I0{}, IM2{}, YES{}, z, dy);
+#pragma unroll 1
+    for (int dy = -2; dy <= 2; ++dy) row(I1{}, IM2{}, YES{}, z, dy);
+#pragma unroll 1
+    for (int dy = -2; dy <= 2; ++dy) row(I2{}, IM2{}, YES{}, z, dy);
+    if (own) {
+      const T dw = (T)(w / (double)patch_count<3, PATCH_FULL>(g, x, y, z));
+      const cpx<T> t = acc + m0;
+      const cpx<T> v = cmk<T>(dw * t.re, dw * t.im);
+      const long long i = lin(g, x, y, z);
+      u[i] = ZERO ? v : (u[i] + v);
+    }
+    rotate();
+    store(z + 3);
+    __syncthreads();
+  }
+}
+
+template <class T>
+static hipError_t vanka_sweep_sym3z_t(Grid g, const void* S, double w, const void* r, void* u,
+                                      bool zero, int zc, hipStream_t s) {
+  const unsigned nb = (unsigned)(((g.nx + SZ_TX - 1) / SZ_TX) * ((g.ny + SZ_TY - 1) / SZ_TY) *
+                                 ((g.nz + zc - 1) / zc));
+  if (zero)
+    k_vanka_sweep_sym3z<true, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(g, (const cpx<T>*)S, w,
+                                                              (const cpx<T>*)r, (cpx<T>*)u, zc);
+  else
+    k_vanka_sweep_sym3z<false, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(g, (const cpx<T>*)S, w,
+                                                               (const cpx<T>*)r, (cpx<T>*)u, zc);
+  VH_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int sym_walk_planes(const Grid& g) {
+  if (g.dim != 3) return -1;
+  const long long cols = (long long)((g.nx + SZ_TX - 1) / SZ_TX) * ((g.ny + SZ_TY - 1) / SZ_TY);
+  return cols * ((g.nz + SYM_WALK_PLANES - 1) / SYM_WALK_PLANES) >= SYM_WALK_MIN_BLOCKS
+             ? SYM_WALK_PLANES
+             : -1;
+}
+
 hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
-                           void* u, bool zero, hipStream_t s) {
+                           void* u, bool zero, hipStream_t s, int planes) {
   if (g.Np >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit lane offsets
   if (dim == 2)
     return prec == PREC_F64 ? vanka_sweep_sym_t<2, double>(g, S, w, r, u, zero, s)
                             : vanka_sweep_sym_t<2, float>(g, S, w, r, u, zero, s);
-  if (dim == 3)
+  if (dim != 3) return hipErrorInvalidValue;
+  if (planes == 0) planes = sym_walk_planes(g);
+  if (planes < 0)
     return prec == PREC_F64 ? vanka_sweep_sym_t<3, double>(g, S, w, r, u, zero, s)
                             : vanka_sweep_sym_t<3, float>(g, S, w, r, u, zero, s);
-  return hipErrorInvalidValue;
+  return prec == PREC_F64 ? vanka_sweep_sym3z_t<double>(g, S, w, r, u, zero, planes, s)
+                          : vanka_sweep_sym3z_t<float>(g, S, w, r, u, zero, planes, s);
 }
 
 // u_out = u_in + B (q - A u_in) in one launch (2D; the residual is formed in the sweep's

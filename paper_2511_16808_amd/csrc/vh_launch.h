@@ -95,10 +95,16 @@ hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hip
 hipError_t vanka_assemble_sym(int dim, Grid g, int prec, const void* G, Slab sl, double w, void* S,
                               hipStream_t s);
 // the sweep reads up to sym_guard(g) entries before plane 0: S must be preceded by that
-// many zero entries of the same allocation
+// many zero entries of the same allocation, and followed by sym_tail(g) of them
 long long sym_guard(const Grid& g);
+long long sym_tail(const Grid& g);
+// 3D: planes < 0 sweeps one plane per block, planes > 0 walks that many planes per block
+// (the mirrored entries of a plane come from the caches), 0 takes sym_walk_planes(g): the
+// walk of SYM_WALK_PLANES planes when it still gives SYM_WALK_MIN_BLOCKS blocks
+constexpr int SYM_WALK_PLANES = 24, SYM_WALK_MIN_BLOCKS = 1024;
+int sym_walk_planes(const Grid& g);
 hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
-                           void* u, bool zero, hipStream_t s);
+                           void* u, bool zero, hipStream_t s, int planes = 0);
 hipError_t unpad_sym(Grid g, double w, int prec, const void* S, cpx<double>* dst, hipStream_t s);
 hipError_t sample_sym(Grid g, double w, int prec, int count, const long long* nodes, const void* S,
                       cpx<double>* out, hipStream_t s);

@@ -371,6 +371,8 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
     return fail(VH_EINVAL, "sweep_tile must be in [0, 10]");
   if (o.split_residual < 0 || o.split_residual > 2)
     return fail(VH_EINVAL, "split_residual must be 0, 1 or 2");
+  if (o.sym_planes < -1 || o.sym_planes > 64)
+    return fail(VH_EINVAL, "sym_planes must be in [-1, 64]");
   if (o.contraction != VH_CONTRACT_VALU &&
       (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
        o.smoother != VH_SMOOTHER_PATCH ||
@@ -434,7 +436,8 @@ vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   const int form = Lv.form;
   count(hd, (double)Lv.g.N, (double)hd->esz * (Lv.E + (zero ? 2 : 3)));
   if (form == SM_SYMHALF)
-    VH_HIP(vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, r, u, zero, hd->s));
+    VH_HIP(vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, r, u, zero, hd->s,
+                           hd->opt.sym_planes));
   else
     VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
@@ -512,7 +515,8 @@ vh_status tune_fuse(vh_handle* hd) {
                              hd->prec, Lv.q, Lv.r, hd->s);
       if (e != hipSuccess) return e;
       return Lv.form == SM_SYMHALF
-                 ? vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, Lv.r, Lv.u, false, hd->s)
+                 ? vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, Lv.r, Lv.u, false, hd->s,
+                                   hd->opt.sym_planes)
                  : vanka_sweep(hd->dim, Lv.form, Lv.g, hd->prec, Lv.B, Lv.r, Lv.u, false, hd->s);
     };
     auto fused_sweep = [&]() {
@@ -1268,11 +1272,12 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
   const int K5 = dim == 2 ? 25 : 125;
   const int E = sym ? (K5 + 1) / 2 : K5;
   const size_t Npad = (size_t)g.Np;
-  // the symmetric sweep reads up to sym_guard entries before the first plane: a zero guard
-  const size_t guard = sym ? (size_t)sym_guard(g) : 0;
+  // the symmetric sweep reads up to sym_guard entries before the first plane and sym_tail
+  // after the last: zero guards
+  const size_t guard = sym ? (size_t)sym_guard(g) : 0, tail = sym ? (size_t)sym_tail(g) : 0;
   void* base = nullptr;
-  VH_TRY(hd->alloc(&base, ((size_t)E * Npad + guard) * hd->esz));
-  VH_HIP(fill(base, (size_t)E * Npad + guard, hd->prec, 0, 0, s));  // row padding stays zero
+  VH_TRY(hd->alloc(&base, ((size_t)E * Npad + guard + tail) * hd->esz));
+  VH_HIP(fill(base, (size_t)E * Npad + guard + tail, hd->prec, 0, 0, s));  // row padding stays zero
   Lv.B = (char*)base + guard * hd->esz;
   for (long long p0 = 0; p0 < p.n_out; p0 += p.SZ) {
     const long long p1 = p0 + p.SZ < p.n_out ? p0 + p.SZ : p.n_out;
@@ -1673,6 +1678,10 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->sweep_tile = Lv.s64_tile;
   info->fused_sweep = Lv.fuse_sweep ? 1 : 0;
   info->fused_restrict = Lv.fuse_restrict ? 1 : 0;
+  if (Lv.form == SM_SYMHALF && hd->dim == 3) {
+    const int pl = hd->opt.sym_planes == 0 ? sym_walk_planes(Lv.g) : hd->opt.sym_planes;
+    info->sym_planes = pl > 0 ? pl : 0;
+  }
   for (int ls = 6; ls >= 0; --ls)
     if (Lv.mfma_txp[ls]) {
       info->mfma_sources = 1 << ls;
@@ -2134,7 +2143,7 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     const int E = assembled ? (sym ? (K5 + 1) / 2 : K5) : Np * Np;
     const Grid g = make_grid(dim, (int)nn[0], (int)nn[1], (int)nn[2]);
     const size_t Npad = (size_t)g.Np;
-    common += ((size_t)E * Npad + (sym ? (size_t)sym_guard(g) : 0)) * esz;
+    common += ((size_t)E * Npad + (sym ? (size_t)(sym_guard(g) + sym_tail(g)) : 0)) * esz;
     if (assembled) {  // a temporary slab buffer when the basis is too small to hold one
       const SlabPlan p = slab_plan(dim, g, Np, esz, (size_t)(o.restart + 1) * N0 * 16);
       if (p.own && (size_t)p.cnt_max * p.per_plane > slab_tmp) slab_tmp = (size_t)p.cnt_max * p.per_plane;

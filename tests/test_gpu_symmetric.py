@@ -21,6 +21,9 @@ CASES = {
     "3d": dict(n=(17, 33, 17), levels=3, alpha=0.5, medium="random", seed=4, sponge_width=4),
     "3d_dirichlet": dict(n=(33, 17, 21), levels=3, alpha=0.4, medium="random", seed=6,
                          bc="dirichlet", damping=[1.0, 0.8]),
+    # several 16-plane chunks of the z walk, the last one short, on both smoothed levels
+    "3d_chunks": dict(n=(41, 17, 37), levels=3, alpha=0.5, medium="layered", seed=5,
+                      sponge_width=4),
 }
 
 
@@ -33,15 +36,24 @@ def to_gpu(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
 
 
-@pytest.mark.parametrize("key", list(CASES))
-def test_symmetric_vcycle_matches_oracle(key):
+# 3D sweep forms (vh_options.sym_planes): the default choice (one plane per workgroup on
+# these small grids), and the z walk of 5 planes (several chunks, a short last one) or 16
+WALKS = [("2d_cubic", 0), ("2d_levdep", 0), ("3d", 0), ("3d", 16), ("3d_dirichlet", 0),
+         ("3d_dirichlet", 5), ("3d_chunks", 0), ("3d_chunks", 5), ("3d_chunks", 16)]
+
+
+@pytest.mark.parametrize("key,planes", WALKS)
+def test_symmetric_vcycle_matches_oracle(key, planes):
     """FP64 V-cycle with the symmetric half on every symmetric level: 1e-10 of the
     oracle, like the full stencil."""
     c = Case(**CASES[key], smoother=SYM)
     ops, mg = c.oracle()
-    hd = c.gpu()
+    hd = c.gpu(sym_planes=planes)
     try:
-        assert B.vh_get_level_info(hd, 0)["smoother_entries"] == 5 ** c.dim
+        info = B.vh_get_level_info(hd, 0)
+        assert info["smoother_entries"] == 5 ** c.dim
+        # the default is one plane per workgroup on grids this small
+        assert info["sym_planes"] == (planes if c.dim == 3 else 0)
         v = cplx_randn(c.N, 8)
         z = torch.empty(c.N, dtype=torch.complex128, device="cuda")
         B.vh_apply_vcycle(hd, to_gpu(v), z)
@@ -50,14 +62,14 @@ def test_symmetric_vcycle_matches_oracle(key):
         B.vh_destroy(hd)
 
 
-@pytest.mark.parametrize("key", list(CASES))
+@pytest.mark.parametrize("key,planes", WALKS)
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-6)])
-def test_symmetric_sweep_equals_full_stencil(key, precision, tol):
+def test_symmetric_sweep_equals_full_stencil(key, planes, precision, tol):
     """Every smoothed level: the exported stencil (rebuilt from the half) equals the full
     assembled one, and one smoothing step u + B(q - A u) agrees (FP64 to 1e-12, complex64
     to 2e-6, the rounding of the stored entries)."""
     c = Case(**CASES[key], precision=precision)
-    hs = Case(**CASES[key], smoother=SYM, precision=precision).gpu()
+    hs = Case(**CASES[key], smoother=SYM, precision=precision).gpu(sym_planes=planes)
     hf = Case(**CASES[key], smoother=FULL, precision=precision).gpu()
     try:
         for l in range(c.levels - 1):

@@ -440,7 +440,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              f"(multi-GPU sharding is design-only, see DESIGN.md)", file=sys.stderr)
+              f"(sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

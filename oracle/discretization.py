@@ -9,7 +9,7 @@ Grid convention: N cells per dimension -> N+1 nodes, all unknown, x_j = j h.
 Arrays are numpy arrays of shape n[::-1] (x fastest), flattened in C order, so the
 linear index of node (x, y[, z]) is x + nx*(y + ny*z).
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
   * absorbing layer: gamma_abc = amp*omega*sum_d ((W - s_d)/W)^2 for s_d < W, s_d
     the distance in cells to the nearer face along d, W = 20 cells (Sec. 5 says
     only "a layer of 20 grid cells of increasing attenuation");

@@ -164,6 +164,12 @@ typedef struct vh_options {
                                the level still gets >= 1024 workgroups, else one plane per
                                workgroup; -1: one plane per workgroup; 1..64 forced.  The
                                forms agree to rounding (they sum in different orders)    */
+    int setup_pivot;        /* patch inversion (Sec. 3.2): 0 (default) eliminates in the
+                               natural order without pivoting where the patch matrices are
+                               complex symmetric with a positive definite imaginary part
+                               (5/7-point operator, transfers with R = c P^T, shift > 0, Full
+                               patch), else with partial pivoting; 1: partial pivoting on
+                               every level.  The two agree to rounding                   */
 } vh_options;
 
 typedef struct vh_solve_stats {
@@ -206,6 +212,7 @@ typedef struct vh_level_info {
     int fused_restrict;     /* 1: the restriction to the next level forms the residual    */
     int sym_planes;         /* 3D symmetric half: z-planes one workgroup of the level's
                                sweep walks (0: not symmetric, or one plane per workgroup) */
+    int setup_pivot;        /* 1: the level's patch inverses used partial pivoting       */
 } vh_level_info;
 
 typedef struct vh_handle vh_handle;

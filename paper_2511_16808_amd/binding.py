@@ -54,7 +54,7 @@ class vh_options(ctypes.Structure):
         ("batch", ctypes.c_int), ("stencil", ctypes.c_int), ("fine_patch", ctypes.c_int),
         ("cycle", ctypes.c_int),
         ("contraction", ctypes.c_int), ("sweep_tile", ctypes.c_int), ("split_residual", ctypes.c_int),
-        ("sym_planes", ctypes.c_int),
+        ("sym_planes", ctypes.c_int), ("setup_pivot", ctypes.c_int),
     ]
 
 
@@ -79,6 +79,7 @@ class vh_level_info(ctypes.Structure):
         ("bytes", ctypes.c_size_t), ("mfma_sources", ctypes.c_int), ("mfma_tile", ctypes.c_int),
         ("mfma_rows", ctypes.c_int), ("sweep_tile", ctypes.c_int), ("fused_sweep", ctypes.c_int),
         ("fused_restrict", ctypes.c_int), ("sym_planes", ctypes.c_int),
+        ("setup_pivot", ctypes.c_int),
     ]
 
 
@@ -285,7 +286,7 @@ def vh_get_level_info(hd, level):
         "mfma_sources": info.mfma_sources, "mfma_tile": info.mfma_tile,
         "mfma_rows": info.mfma_rows, "sweep_tile": info.sweep_tile,
         "fused_sweep": info.fused_sweep, "fused_restrict": info.fused_restrict,
-        "sym_planes": info.sym_planes,
+        "sym_planes": info.sym_planes, "setup_pivot": info.setup_pivot,
     }
 
 

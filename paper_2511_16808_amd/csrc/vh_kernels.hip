@@ -697,7 +697,7 @@ __device__ __forceinline__ void cupd2_rowb(cpx<double>& a0, cpx<double>& a1, con
       : "v"(p0.re), "v"(p0.im), "v"(p1.re), "v"(p1.im), "v"(c.re), "v"(c.im), "i"(L0), "i"(L1));
 }
 
-template <int DIM, int SHAPE, int PATCH, class T>
+template <int DIM, int SHAPE, int PATCH, class T, bool NOPIV = false>
 __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double>* __restrict__ A,
                                                      double w, cpx<T>* __restrict__ G, Slab sl) {
   constexpr int Np = patch_Np<DIM, PATCH>();
@@ -756,16 +756,31 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   // row: c = 0 and a[Np-1] <- 1, so it stays unnormalised and its pivot value d is
   // kept to scale the row once at the end.  The pivot sequence of each patch is kept
   // in LDS.
+  // NOPIV (the patch matrix complex symmetric with a positive definite imaginary part,
+  // where elimination in the natural order needs no pivoting): step s takes row s, and
+  // the working matrix stays symmetric up to the scaling of the rows already used, so
+  // the pivot row is assembled from every row's own leading entry: position
+  // (k - s) mod Np of the pivot row is a_k[0] for a row k not yet used and -a_k[0] / d_k
+  // for a used row k with pivot value d_k.  Every lane writes one entry, in one LDS
+  // store, instead of the pivot lane writing all Np.
   __shared__ unsigned char pivs[PB * Np];
   __shared__ cpx<double> prow[WPB][PPW][Np];
   bool used = false;
   int mystep = k;
   cpx<double> dpiv = cmk(1.0, 0.0);
+  cpx<double> ndinv = cmk(0.0, 0.0);  // -1 / d of this lane's row once used (NOPIV)
   cpx<double>* pr = prow[wib][slot < (unsigned)PPW ? slot : 0];
   constexpr int CH = 6;  // pivot-row entries read per batch
 #pragma unroll 3
   for (int s = 0; s < Np; ++s) {
     const cpx<double> as = a[0];
+    int best = s;
+    if constexpr (NOPIV) {
+      if (in_slot) {
+        const int pos = k >= s ? k - s : k - s + Np;
+        pr[pos] = used ? as * ndinv : as;
+      }
+    } else {
     const float mag = (float)(fabs(as.re) + fabs(as.im));
     unsigned key = (in_slot && !used) ? ((__float_as_uint(mag) & ~31u) | (31u - (unsigned)k)) : 0u;
     if constexpr (GW == 32) {
@@ -784,10 +799,11 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
       }
       key = (unsigned)__shfl((int)key, base, 64);
     }
-    const int best = 31 - (int)(key & 31u);
+    best = 31 - (int)(key & 31u);
     if (in_slot && k == 0) pivs[pslot * Np + s] = (unsigned char)best;
+    }
     const bool am = in_slot && (k == best);
-    if (am) {
+    if (!NOPIV && am) {
 #pragma unroll
       for (int m = 0; m < Np; ++m) pr[m] = a[m];
     }
@@ -842,6 +858,7 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
       used = true;
       mystep = s;
       dpiv = ps;
+      ndinv = cmk(0.0, 0.0) - inv;
     }
     // every lane has read the row before the next step's pivot lane overwrites it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -871,7 +888,8 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
     const double dd = 1.0 / (dpiv.re * dpiv.re + dpiv.im * dpiv.im);
     const cpx<double> sc = cmk(wt * dpiv.re * dd, -wt * dpiv.im * dd);  // w / (cnt d)
 #pragma unroll
-    for (int s = 0; s < Np; ++s) stage[(pivs[pslot * Np + s] + i * Np) * PB + pslot] = ccast<T>(sc * a[s]);
+    for (int s = 0; s < Np; ++s)
+      stage[((NOPIV ? s : (int)pivs[pslot * Np + s]) + i * Np) * PB + pslot] = ccast<T>(sc * a[s]);
     okrow[i * PB + pslot] = ok ? 1 : 0;
     if (k == 0) cpad[pslot] = active ? linp(g, cx, cy, cz) : 0;
   }
@@ -889,29 +907,42 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   }
 }
 
+template <int DIM, int SHAPE, int PATCH, class T, bool NOPIV>
+static void vanka_setup_l(Grid g, const cpx<double>* A, double w, void* G, Slab sl,
+                          hipStream_t s) {
+  constexpr int PPW = 64 / setup_group<DIM, PATCH>();
+  constexpr int WPB = setup_waves<DIM, PATCH, T>();
+  const long long nc = sl.c_hi - sl.c_lo;
+  const unsigned nb = (unsigned)((nc + WPB * PPW - 1) / (WPB * PPW));
+  k_vanka_setup<DIM, SHAPE, PATCH, T, NOPIV><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<T>*)G, sl);
+}
+
 template <int DIM, int SHAPE, int PATCH>
 static hipError_t vanka_setup_s(Grid g, const cpx<double>* A, double w, int prec, void* G,
-                                Slab sl, hipStream_t s) {
-  constexpr int PPW = 64 / setup_group<DIM, PATCH>();
+                                Slab sl, bool nopiv, hipStream_t s) {
   if (sl.c_lo < 0 || sl.c_hi > (long long)g.N || sl.c_lo >= sl.c_hi) return hipErrorInvalidValue;
-  const long long nc = sl.c_hi - sl.c_lo;
+  // elimination without pivoting is built for the Full patch only
+  constexpr bool NP = PATCH == PATCH_FULL;
   if (prec == PREC_F64) {
-    constexpr int WPB = setup_waves<DIM, PATCH, double>();
-    const unsigned nb = (unsigned)((nc + WPB * PPW - 1) / (WPB * PPW));
-    k_vanka_setup<DIM, SHAPE, PATCH, double><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<double>*)G, sl);
+    if (NP && nopiv)
+      vanka_setup_l<DIM, SHAPE, PATCH, double, NP>(g, A, w, G, sl, s);
+    else
+      vanka_setup_l<DIM, SHAPE, PATCH, double, false>(g, A, w, G, sl, s);
   } else {
-    constexpr int WPB = setup_waves<DIM, PATCH, float>();
-    const unsigned nb = (unsigned)((nc + WPB * PPW - 1) / (WPB * PPW));
-    k_vanka_setup<DIM, SHAPE, PATCH, float><<<nb, 64 * WPB, 0, s>>>(g, A, w, (cpx<float>*)G, sl);
+    if (NP && nopiv)
+      vanka_setup_l<DIM, SHAPE, PATCH, float, NP>(g, A, w, G, sl, s);
+    else
+      vanka_setup_l<DIM, SHAPE, PATCH, float, false>(g, A, w, G, sl, s);
   }
   VH_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
-                       int prec, void* G, Slab sl, hipStream_t s) {
-#define VH_VS(D, S, P) \
-  if (dim == D && shape == S && patch == P) return vanka_setup_s<D, S, P>(g, A, w, prec, G, sl, s);
+                       int prec, void* G, Slab sl, hipStream_t s, bool nopiv) {
+#define VH_VS(D, S, P)                            \
+  if (dim == D && shape == S && patch == P) \
+    return vanka_setup_s<D, S, P>(g, A, w, prec, G, sl, nopiv, s);
   VH_VS(2, CROSS, PATCH_FULL)
   VH_VS(2, BOX1, PATCH_FULL)
   VH_VS(2, BOX2, PATCH_FULL)

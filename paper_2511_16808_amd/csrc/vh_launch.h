@@ -85,8 +85,10 @@ struct Slab {
   long long gbase;
   size_t gstride;
 };
+// nopiv: eliminate in the natural order without pivoting (Full patch; for complex symmetric
+// patch matrices with a positive definite imaginary part, where no pivot can vanish)
 hipError_t vanka_setup(int dim, int shape, int patch, Grid g, const cpx<double>* A, double w,
-                       int prec, void* G, Slab sl, hipStream_t s);
+                       int prec, void* G, Slab sl, hipStream_t s, bool nopiv = false);
 hipError_t sample(Grid g, int E, int padded, int prec, int count, const long long* nodes,
                   const void* src, cpx<double>* out, hipStream_t s);
 hipError_t unpad(Grid g, int E, int prec, const void* src, cpx<double>* dst, hipStream_t s);

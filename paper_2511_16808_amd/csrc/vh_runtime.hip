@@ -78,6 +78,7 @@ struct Level {
   int s64_stile = 0;  // variant of the 64-source 2D stencil (operator, residual)
   // residual formed inside the sweep / the restriction (chosen per level at setup)
   bool fuse_sweep = false, fuse_restrict = false;
+  bool nopiv = false;  // patch inverses eliminated without pivoting
 };
 
 }  // namespace
@@ -373,6 +374,7 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
     return fail(VH_EINVAL, "split_residual must be 0, 1 or 2");
   if (o.sym_planes < -1 || o.sym_planes > 64)
     return fail(VH_EINVAL, "sym_planes must be in [-1, 64]");
+  if (o.setup_pivot < 0 || o.setup_pivot > 1) return fail(VH_EINVAL, "setup_pivot must be 0 or 1");
   if (o.contraction != VH_CONTRACT_VALU &&
       (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
        o.smoother != VH_SMOOTHER_PATCH ||
@@ -1261,7 +1263,7 @@ SlabPlan slab_plan(int dim, const Grid& g, int Np, size_t esz, size_t scratch_by
 // array: each slab of output planes gets its patch inverses in the scratch area (the
 // patches centred within one plane of the slab), then its assembled rows.
 vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
-                         void* scratch, size_t scratch_bytes, bool sym) {
+                         void* scratch, size_t scratch_bytes, bool sym, bool nopiv) {
   const int dim = hd->dim;
   const Grid& g = Lv.g;
   hipStream_t s = hd->s;
@@ -1284,7 +1286,7 @@ vh_status assemble_level(vh_handle* hd, Level& Lv, const cpx<double>* A, int Np,
     const long long b0 = p0 - 2 > 0 ? p0 - 2 : 0;
     const long long c0 = p0 - 1 > 0 ? p0 - 1 : 0, c1 = p1 + 1 < p.n_out ? p1 + 1 : p.n_out;
     VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, g, A, Lv.w, hd->prec, buf,
-                       Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s));
+                       Slab{c0 * p.plane, c1 * p.plane, b0 * p.plane_pad, gstride}, s, nopiv));
     const Slab so{p0 * p.plane, p1 * p.plane, b0 * p.plane_pad, gstride};
     if (sym)
       VH_HIP(vanka_assemble_sym(dim, g, hd->prec, buf, so, Lv.w, Lv.B, s));
@@ -1388,17 +1390,22 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
     // H_s^l is symmetric when H_s is and every transfer above level l has R and P of
     // one family (R = c P^T); below a mixed transfer the full stencil is kept
     sym_above = sym_above && (l == 0 || (hd->L[l - 1].rf == hd->L[l - 1].pf));
+    // patch matrices of a complex symmetric H_s^l (5/7-point operator) whose imaginary part
+    // is positive definite (shift > 0; omega = 0 leaves the Laplacian, positive definite):
+    // elimination without pivoting (vh_options.setup_pivot = 1 keeps partial pivoting)
+    Lv.nopiv = o.setup_pivot == 0 && sym_above && o.stencil == VH_STENCIL_FD2 &&
+               Lv.patch == VH_PATCH_FULL && (hd->shift > 0.0 || hd->omega == 0.0);
     if ((o.smoother == VH_SMOOTHER_ASSEMBLED || o.smoother == VH_SMOOTHER_SYMMETRIC) &&
         Lv.patch != VH_PATCH_POINT) {
       const bool sym = o.smoother == VH_SMOOTHER_SYMMETRIC && sym_above;
       VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>),
-                            sym));
+                            sym, Lv.nopiv));
       Lv.form = sym ? SM_SYMHALF : 2;
     } else {
       VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
       VH_HIP(fill(Lv.B, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
       VH_HIP(vanka_setup(dim, Lv.shape, Lv.patch, Lv.g, A64[l], Lv.w, hd->prec, Lv.B,
-                         Slab{0, (long long)N, 0, Npad}, s));
+                         Slab{0, (long long)N, 0, Npad}, s, Lv.nopiv));
       Lv.E = Np * Np;
       Lv.form = Lv.patch;
     }
@@ -1678,6 +1685,7 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->sweep_tile = Lv.s64_tile;
   info->fused_sweep = Lv.fuse_sweep ? 1 : 0;
   info->fused_restrict = Lv.fuse_restrict ? 1 : 0;
+  info->setup_pivot = (level + 1 < hd->levels && !Lv.nopiv) ? 1 : 0;
   if (Lv.form == SM_SYMHALF && hd->dim == 3) {
     const int pl = hd->opt.sym_planes == 0 ? sym_walk_planes(Lv.g) : hd->opt.sym_planes;
     info->sym_planes = pl > 0 ? pl : 0;

@@ -432,6 +432,10 @@ def main():
     ap.add_argument("--sym-planes", type=int, default=0,
                     help="3D symmetric-half sweep: planes per workgroup (-1: one plane per "
                          "workgroup; 0: chosen from the grid)")
+    ap.add_argument("--setup-pivot", type=int, default=0, choices=[0, 1],
+                    help="1: partial pivoting in every patch inversion (0: none where the "
+                         "patch matrices are complex symmetric with a positive definite "
+                         "imaginary part)")
     ap.add_argument("--split-residual", action="store_true",
                     help="separate residual launches instead of the residual formed inside "
                          "the sweep and the restriction (same results)")
@@ -464,7 +468,7 @@ def main():
     ceiling = copy_ceiling()
     out = run_workload(args.workload, args.steps, args.warmup, args.smoother, args.contraction,
                        args.batch, args.precision, not args.no_cpu_baseline,
-                       args.split_residual, args.sweep_tile, args.sym_planes)
+                       args.split_residual, args.sweep_tile, args.sym_planes, args.setup_pivot)
     out["roofline"].update(ceiling_fields(out["roofline"], ceiling))
     if args.workload == DEFAULT_WORKLOAD and args.c4_steps > 0:
         # the 512^2 half of the metric: 64 sources through one hierarchy, timed after the
@@ -512,7 +516,7 @@ def ceiling_fields(roof, ceiling):
 
 
 def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, precision_o,
-                 with_cpu, split=False, sweep_tile=0, sym_planes=0):
+                 with_cpu, split=False, sweep_tile=0, sym_planes=0, setup_pivot=0):
     """Times `steps` whole passes (setup + solve + destroy) of one workload after `warmup`
     untimed ones; returns the JSON object of the benchmark line."""
     import numpy as np
@@ -554,7 +558,8 @@ def run_workload(key, steps, warmup, smoother_name, contraction_name, batch_o, p
                          intergrid=B.VH_IG_LEVDEP if dim == 2 else B.VH_IG_LINEAR, stencil=stencil,
                          smoother=smoother, stream=stream, timing=1, batch=batch,
                          contraction=contraction, split_residual=int(args.split_residual),
-                         sweep_tile=args.sweep_tile, sym_planes=sym_planes)
+                         sweep_tile=args.sweep_tile, sym_planes=sym_planes,
+                         setup_pivot=setup_pivot)
     if w.get("fine_patch"):
         opt.fine_patch = PATCHES[w["fine_patch"]]
     torch.cuda.synchronize()

@@ -430,8 +430,8 @@ def main():
     ap.add_argument("--sweep-tile", type=int, default=0,
                     help="64-source 2D walk variant (1..10; 0: timed per grid)")
     ap.add_argument("--sym-planes", type=int, default=0,
-                    help="3D symmetric-half sweep: planes per workgroup (-1: one plane per "
-                         "workgroup; 0: chosen from the grid)")
+                    help="3D symmetric-half sweep: planes per workgroup (2..64; -1: one "
+                         "plane per workgroup; 0: chosen from the grid)")
     ap.add_argument("--setup-pivot", type=int, default=0, choices=[0, 1],
                     help="1: partial pivoting in every patch inversion (0: none where the "
                          "patch matrices are complex symmetric with a positive definite "

@@ -160,10 +160,12 @@ typedef struct vh_options {
     int sym_planes;         /* 3D symmetric-half sweep (VH_SMOOTHER_SYMMETRIC): how many
                                z-planes one workgroup walks, reading the entries of each
                                plane once for its own terms and, from the caches, for the
-                               mirrored terms of the planes above.  0 (default): 24 where
+                               mirrored terms of the planes above.  0 (default): 8 where
                                the level still gets >= 1024 workgroups, else one plane per
-                               workgroup; -1: one plane per workgroup; 1..64 forced.  The
-                               forms agree to rounding (they sum in different orders)    */
+                               workgroup; -1: one plane per workgroup; 2..64 forced (a
+                               walked level keeps a small carry buffer: two planes per
+                               chunk boundary).  The forms agree to rounding (they sum
+                               in different orders)                                      */
     int setup_pivot;        /* patch inversion (Sec. 3.2): 0 (default) eliminates in the
                                natural order without pivoting where the patch matrices are
                                complex symmetric with a positive definite imaginary part

@@ -1129,18 +1129,20 @@ long long sym_guard(const Grid& g) {
 long long sym_tail(const Grid& g) { return g.dim == 3 ? 2 + 2LL * g.nxp : 0; }
 
 // 3D form of the symmetric-half sweep, walked along z.  A block takes a 32 x 8 column of
-// nodes through a chunk of planes (24 by default).  At plane z each lane reads the 63
-// stored entries of its node once for its own terms, S(i, i + d) r(i + d), and, in the
+// nodes through a chunk of zc >= 2 planes (8 by default).  At plane z each lane reads the
+// 63 stored entries of its node once for its own terms, S(i, i + d) r(i + d), and, in the
 // same step, the entries stored at the nodes i - d of plane z for the mirrored terms
 // S(i - d, i) r(i - d) of the targets i in planes z, z + 1, z + 2: those loads touch the
 // lines the neighbouring lanes of the block are loading for their own terms at that
 // moment, so they come from the caches instead of reaching back two planes.  The mirrored
-// sums of the next two planes ride along in registers; a chunk starts two planes early to
-// collect them for its first targets.  The residual planes z .. z + 2 (with a halo of 2,
-// zero outside the grid) sit in a four-slot LDS ring; the slot of plane z + 3 is filled
-// while plane z is summed.  One stencil row (5 own and 5 mirrored loads) per iteration
-// keeps 62 VGPRs and 8 waves per SIMD; tiles of 64 x 8, 64 x 16, 32 x 16 and 16 x 16 and
-// chunks of 12 to 32 planes measured within 10 % of this one at 257^3.
+// sums of the next two planes ride along in registers.  Those a chunk collects for the
+// first two planes of the next chunk go to `carry` (two planes per chunk boundary, x
+// fastest), and sym_carry_add() adds them once every chunk is done.  The residual planes
+// z .. z + 2 (with a halo of 2, zero outside the grid) sit in a four-slot LDS ring; the
+// slot of plane z + 3 is filled while plane z is summed.  One stencil row (5 own and 5
+// mirrored loads) per iteration keeps 62 VGPRs and 8 waves per SIMD; tiles of 64 x 8,
+// 64 x 16, 32 x 16 and 16 x 16 measured within 15 % of this one at 257^3, and chunks of
+// 12 to 43 planes 1 to 10 % slower than 8.
 constexpr int SZ_TX = 32, SZ_TY = 8;
 
 template <bool ZERO, class T>
@@ -1149,7 +1151,8 @@ __global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
                                                                     double w,
                                                                     const cpx<T>* __restrict__ r,
                                                                     cpx<T>* __restrict__ u,
-                                                                    int zc) {
+                                                                    int zc,
+                                                                    cpx<T>* __restrict__ carry) {
   constexpr int RX = SZ_TX + 4, RY = SZ_TY + 4, NR = RX * RY, NT = SZ_TX * SZ_TY;
   constexpr int NRT = (NR + NT - 1) / NT;
   __shared__ cpx<T> ring[4][NR];
@@ -1180,28 +1183,26 @@ __global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
       if (e < NR) ring[zz & 3][e] = rv[k];
     }
   };
-  const int zs = z0 >= 2 ? z0 - 2 : 0;
-  fetch(zs);
-  store(zs);
-  fetch(zs + 1);
-  store(zs + 1);
-  fetch(zs + 2);
-  store(zs + 2);
+  fetch(z0);
+  store(z0);
+  fetch(z0 + 1);
+  store(z0 + 1);
+  fetch(z0 + 2);
+  store(z0 + 2);
   __syncthreads();
   cpx<T> m0 = cmk<T>(0, 0), m1 = cmk<T>(0, 0), m2 = cmk<T>(0, 0);
   const int tix = (ly + 2) * RX + (lx + 2);
   unsigned ipu = 0;  // padded index of (xc, yc, z) < 2^31 (checked on the host)
   cpx<T> acc = cmk<T>(0, 0);
-  // one stencil row (dy, DZ) of the half, dx = DXLO .. 2 (entry q = 25 DZ + 5 dy + dx).
-  // OWN: the node's own terms S(i, i + d) r(i + d).  Mirrored terms: the source
+  // one stencil row (dy, DZ) of the half, dx = DXLO .. 2 (entry q = 25 DZ + 5 dy + dx):
+  // the node's own terms S(i, i + d) r(i + d), and the mirrored terms, where the source
   // (x - dx, y - dy) of plane z gives S(i - d, i) r(i - d) to the target of plane z + DZ.
   // A source outside the grid has r = 0 in the ring, so its entry only has to be finite:
   // the address, the lane's index shifted by a block-uniform amount, stays inside the
   // allocation (zero guards before plane 0 and after the last plane, earlier or later
   // rows and planes otherwise) and one 32-bit lane offset serves every load.
-  auto row = [&](auto dzc, auto dxlo, auto ownc, int z, int dy) {
+  auto row = [&](auto dzc, auto dxlo, int z, int dy) {
     constexpr int DZ = decltype(dzc)::value, DXLO = decltype(dxlo)::value;
-    constexpr bool OWN = decltype(ownc)::value;
     const cpx<T>* S0 = S + (long long)(25 * DZ + 5 * dy) * (long long)Np;
     const cpx<T>* ro = ring[(z + DZ) & 3] + tix + dy * RX;
     const cpx<T>* rm = ring[z & 3] + tix - dy * RX;
@@ -1213,14 +1214,14 @@ __global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
     for (int k = 0; k < NE; ++k) {
       const int dx = DXLO + k;
       const cpx<T>* Sq = S0 + (long long)dx * (long long)Np;
-      if constexpr (OWN) so[k] = Sq[ipu];
+      so[k] = Sq[ipu];
       sm[k] = (Sq - (sh + dx))[ipu];
     }
     cpx<T>& m = DZ == 0 ? m0 : (DZ == 1 ? m1 : m2);
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
       const int dx = DXLO + k;
-      if constexpr (OWN) acc = cfma(so[k], ro[dx], acc);
+      acc = cfma(so[k], ro[dx], acc);
       if (DZ > 0 || DXLO < 0 || dx > 0) m = cfma(sm[k], rm[-dx], m);
     }
   };
@@ -1228,40 +1229,17 @@ __global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
   using I1 = std::integral_constant<int, 1>;
   using I2 = std::integral_constant<int, 2>;
   using IM2 = std::integral_constant<int, -2>;
-  using YES = std::true_type;
-  using NO = std::false_type;
-  auto rotate = [&]() {
-    m0 = m1;
-    m1 = m2;
-    m2 = cmk<T>(0, 0);
-  };
-  // the (at most two) planes before the chunk: mirrored terms of its first targets only
-  for (int z = zs; z < z0; ++z) {
-    fetch(z + 3);
-    ipu = (unsigned)(xc + g.nxp * (yc + g.ny * z));
-    if (z0 - z <= 1) {
-#pragma unroll 1
-      for (int dy = -2; dy <= 2; ++dy) row(I1{}, IM2{}, NO{}, z, dy);
-    }
-#pragma unroll 1
-    for (int dy = -2; dy <= 2; ++dy) row(I2{}, IM2{}, NO{}, z, dy);
-    rotate();
-    store(z + 3);
-    __syncthreads();
-  }
   for (int z = z0; z < z1; ++z) {
     fetch(z + 3);
     ipu = (unsigned)(xc + g.nxp * (yc + g.ny * z));
     acc = cmk<T>(0, 0);
-    // targets beyond the chunk take mirrored terms that are then dropped: their loads hit
-    // the lines just read for the own terms
-    row(I0{}, I0{}, YES{}, z, 0);
+    row(I0{}, I0{}, z, 0);
 #pragma unroll 1
-    for (int dy = 1; dy <= 2; ++dy) row(I0{}, IM2{}, YES{}, z, dy);
+    for (int dy = 1; dy <= 2; ++dy) row(I0{}, IM2{}, z, dy);
 #pragma unroll 1
-    for (int dy = -2; dy <= 2; ++dy) row(I1{}, IM2{}, YES{}, z, dy);
+    for (int dy = -2; dy <= 2; ++dy) row(I1{}, IM2{}, z, dy);
 #pragma unroll 1
-    for (int dy = -2; dy <= 2; ++dy) row(I2{}, IM2{}, YES{}, z, dy);
+    for (int dy = -2; dy <= 2; ++dy) row(I2{}, IM2{}, z, dy);
     if (own) {
       const T dw = (T)(w / (double)patch_count<3, PATCH_FULL>(g, x, y, z));
       const cpx<T> t = acc + m0;
@@ -1269,24 +1247,63 @@ __global__ __launch_bounds__(SZ_TX * SZ_TY) void k_vanka_sweep_sym3z(Grid g,
       const long long i = lin(g, x, y, z);
       u[i] = ZERO ? v : (u[i] + v);
     }
-    rotate();
+    m0 = m1;
+    m1 = m2;
+    m2 = cmk<T>(0, 0);
     store(z + 3);
     __syncthreads();
   }
+  // m0, m1: the mirrored sums of planes z1, z1 + 1 from this chunk's planes
+  if (own && z1 < g.nz) {
+    const size_t plane = (size_t)g.nx * g.ny, at = (size_t)x + (size_t)g.nx * y;
+    cpx<T>* c = carry + (size_t)bz * 2 * plane + at;
+    c[0] = m0;
+    if (z1 + 1 < g.nz) c[plane] = m1;
+  }
+}
+
+// u += (w / cnt) * carry at the first two planes of every chunk but the first
+template <class T>
+__global__ __launch_bounds__(256) void k_sym_carry_add(Grid g, double w, int zc,
+                                                       const cpx<T>* __restrict__ carry,
+                                                       cpx<T>* __restrict__ u) {
+  const size_t plane = (size_t)g.nx * g.ny;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = (g.nz + zc - 1) / zc;
+  if (t >= (size_t)(nb - 1) * 2 * plane) return;
+  const int j = (int)(t / (2 * plane)), k = (int)((t / plane) % 2);
+  const int at = (int)(t % plane);
+  const int x = at % g.nx, y = at / g.nx, z = (j + 1) * zc + k;
+  if (z >= g.nz) return;
+  const cpx<T> c = carry[t];
+  const T dw = (T)(w / (double)patch_count<3, PATCH_FULL>(g, x, y, z));
+  const long long i = lin(g, x, y, z);
+  u[i] = u[i] + cmk<T>(dw * c.re, dw * c.im);
+}
+
+long long sym_carry_elems(const Grid& g, int planes) {
+  if (g.dim != 3 || planes < 2) return 0;
+  return (long long)((g.nz + planes - 1) / planes - 1) * 2 * g.nx * g.ny;
 }
 
 template <class T>
 static hipError_t vanka_sweep_sym3z_t(Grid g, const void* S, double w, const void* r, void* u,
-                                      bool zero, int zc, hipStream_t s) {
+                                      bool zero, int zc, void* carry, hipStream_t s) {
   const unsigned nb = (unsigned)(((g.nx + SZ_TX - 1) / SZ_TX) * ((g.ny + SZ_TY - 1) / SZ_TY) *
                                  ((g.nz + zc - 1) / zc));
   if (zero)
-    k_vanka_sweep_sym3z<true, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(g, (const cpx<T>*)S, w,
-                                                              (const cpx<T>*)r, (cpx<T>*)u, zc);
+    k_vanka_sweep_sym3z<true, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(
+        g, (const cpx<T>*)S, w, (const cpx<T>*)r, (cpx<T>*)u, zc, (cpx<T>*)carry);
   else
-    k_vanka_sweep_sym3z<false, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(g, (const cpx<T>*)S, w,
-                                                               (const cpx<T>*)r, (cpx<T>*)u, zc);
+    k_vanka_sweep_sym3z<false, T><<<nb, SZ_TX * SZ_TY, 0, s>>>(
+        g, (const cpx<T>*)S, w, (const cpx<T>*)r, (cpx<T>*)u, zc, (cpx<T>*)carry);
   VH_LAUNCH_CHECK();
+  const long long nc = sym_carry_elems(g, zc);
+  if (nc > 0) {
+    k_sym_carry_add<T><<<nblocks(nc, 256), 256, 0, s>>>(g, w, zc, (const cpx<T>*)carry,
+                                                         (cpx<T>*)u);
+    VH_LAUNCH_CHECK();
+  }
   return hipSuccess;
 }
 
@@ -1299,7 +1316,7 @@ int sym_walk_planes(const Grid& g) {
 }
 
 hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
-                           void* u, bool zero, hipStream_t s, int planes) {
+                           void* u, bool zero, hipStream_t s, int planes, void* carry) {
   if (g.Np >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit lane offsets
   if (dim == 2)
     return prec == PREC_F64 ? vanka_sweep_sym_t<2, double>(g, S, w, r, u, zero, s)
@@ -1309,8 +1326,9 @@ hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, c
   if (planes < 0)
     return prec == PREC_F64 ? vanka_sweep_sym_t<3, double>(g, S, w, r, u, zero, s)
                             : vanka_sweep_sym_t<3, float>(g, S, w, r, u, zero, s);
-  return prec == PREC_F64 ? vanka_sweep_sym3z_t<double>(g, S, w, r, u, zero, planes, s)
-                          : vanka_sweep_sym3z_t<float>(g, S, w, r, u, zero, planes, s);
+  if (planes < 2 || (sym_carry_elems(g, planes) > 0 && !carry)) return hipErrorInvalidValue;
+  return prec == PREC_F64 ? vanka_sweep_sym3z_t<double>(g, S, w, r, u, zero, planes, carry, s)
+                          : vanka_sweep_sym3z_t<float>(g, S, w, r, u, zero, planes, carry, s);
 }
 
 // u_out = u_in + B (q - A u_in) in one launch (2D; the residual is formed in the sweep's

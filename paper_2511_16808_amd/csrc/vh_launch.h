@@ -100,13 +100,17 @@ hipError_t vanka_assemble_sym(int dim, Grid g, int prec, const void* G, Slab sl,
 // many zero entries of the same allocation, and followed by sym_tail(g) of them
 long long sym_guard(const Grid& g);
 long long sym_tail(const Grid& g);
-// 3D: planes < 0 sweeps one plane per block, planes > 0 walks that many planes per block
+// 3D: planes < 0 sweeps one plane per block, planes >= 2 walks that many planes per block
 // (the mirrored entries of a plane come from the caches), 0 takes sym_walk_planes(g): the
-// walk of SYM_WALK_PLANES planes when it still gives SYM_WALK_MIN_BLOCKS blocks
-constexpr int SYM_WALK_PLANES = 24, SYM_WALK_MIN_BLOCKS = 1024;
+// walk of SYM_WALK_PLANES planes when it still gives SYM_WALK_MIN_BLOCKS blocks.  The walk
+// needs `carry`, device scratch of sym_carry_elems(g, planes) complex entries at the
+// preconditioner precision (the mirrored sums handed from one chunk of planes to the next)
+constexpr int SYM_WALK_PLANES = 8, SYM_WALK_MIN_BLOCKS = 1024;
 int sym_walk_planes(const Grid& g);
+long long sym_carry_elems(const Grid& g, int planes);
 hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,
-                           void* u, bool zero, hipStream_t s, int planes = 0);
+                           void* u, bool zero, hipStream_t s, int planes = 0,
+                           void* carry = nullptr);
 hipError_t unpad_sym(Grid g, double w, int prec, const void* S, cpx<double>* dst, hipStream_t s);
 hipError_t sample_sym(Grid g, double w, int prec, int count, const long long* nodes, const void* S,
                       cpx<double>* out, hipStream_t s);

@@ -79,6 +79,8 @@ struct Level {
   // residual formed inside the sweep / the restriction (chosen per level at setup)
   bool fuse_sweep = false, fuse_restrict = false;
   bool nopiv = false;  // patch inverses eliminated without pivoting
+  int sym_planes = -1;    // 3D symmetric half: planes per workgroup of the z walk (or -1)
+  void* carry = nullptr;  // the walk's mirrored sums handed between chunks of planes
 };
 
 }  // namespace
@@ -372,8 +374,8 @@ vh_status validate(int dim, const int* n, double h, double omega, double shift, 
     return fail(VH_EINVAL, "sweep_tile must be in [0, 10]");
   if (o.split_residual < 0 || o.split_residual > 2)
     return fail(VH_EINVAL, "split_residual must be 0, 1 or 2");
-  if (o.sym_planes < -1 || o.sym_planes > 64)
-    return fail(VH_EINVAL, "sym_planes must be in [-1, 64]");
+  if (o.sym_planes < -1 || o.sym_planes == 1 || o.sym_planes > 64)
+    return fail(VH_EINVAL, "sym_planes must be -1, 0 or in [2, 64]");
   if (o.setup_pivot < 0 || o.setup_pivot > 1) return fail(VH_EINVAL, "setup_pivot must be 0 or 1");
   if (o.contraction != VH_CONTRACT_VALU &&
       (dim != 2 || patch != VH_PATCH_FULL || (o.fine_patch != -1 && o.fine_patch != VH_PATCH_FULL) ||
@@ -439,7 +441,7 @@ vh_status smooth(vh_handle* hd, Level& Lv, const void* r, void* u, bool zero) {
   count(hd, (double)Lv.g.N, (double)hd->esz * (Lv.E + (zero ? 2 : 3)));
   if (form == SM_SYMHALF)
     VH_HIP(vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, r, u, zero, hd->s,
-                           hd->opt.sym_planes));
+                           Lv.sym_planes, Lv.carry));
   else
     VH_HIP(vanka_sweep(hd->dim, form, Lv.g, hd->prec, Lv.B, r, u, zero, hd->s));
   hd->tend(tk);
@@ -518,7 +520,7 @@ vh_status tune_fuse(vh_handle* hd) {
       if (e != hipSuccess) return e;
       return Lv.form == SM_SYMHALF
                  ? vanka_sweep_sym(hd->dim, Lv.g, hd->prec, Lv.B, Lv.w, Lv.r, Lv.u, false, hd->s,
-                                   hd->opt.sym_planes)
+                                   Lv.sym_planes, Lv.carry)
                  : vanka_sweep(hd->dim, Lv.form, Lv.g, hd->prec, Lv.B, Lv.r, Lv.u, false, hd->s);
     };
     auto fused_sweep = [&]() {
@@ -1401,6 +1403,14 @@ vh_status build(vh_handle* hd, const double* kappa, const double* gamma) {
       VH_TRY(assemble_level(hd, Lv, A64[l], Np, hd->V, (size_t)(hd->m + 1) * N0 * sizeof(cpx<double>),
                             sym, Lv.nopiv));
       Lv.form = sym ? SM_SYMHALF : 2;
+      if (sym && dim == 3) {
+        Lv.sym_planes = o.sym_planes == 0 ? sym_walk_planes(Lv.g) : o.sym_planes;
+        const size_t nc = (size_t)sym_carry_elems(Lv.g, Lv.sym_planes);
+        if (nc) {
+          VH_TRY(hd->alloc(&Lv.carry, nc * hd->esz));
+          Lv.bytes += nc * hd->esz;
+        }
+      }
     } else {
       VH_TRY(hd->alloc(&Lv.B, (size_t)Np * Np * Npad * hd->esz));
       VH_HIP(fill(Lv.B, (size_t)Np * Np * Npad, hd->prec, 0, 0, s));
@@ -1686,10 +1696,7 @@ vh_status vh_get_level_info(const vh_handle* hd, int level, vh_level_info* info)
   info->fused_sweep = Lv.fuse_sweep ? 1 : 0;
   info->fused_restrict = Lv.fuse_restrict ? 1 : 0;
   info->setup_pivot = (level + 1 < hd->levels && !Lv.nopiv) ? 1 : 0;
-  if (Lv.form == SM_SYMHALF && hd->dim == 3) {
-    const int pl = hd->opt.sym_planes == 0 ? sym_walk_planes(Lv.g) : hd->opt.sym_planes;
-    info->sym_planes = pl > 0 ? pl : 0;
-  }
+  if (Lv.form == SM_SYMHALF && hd->dim == 3) info->sym_planes = Lv.sym_planes > 0 ? Lv.sym_planes : 0;
   for (int ls = 6; ls >= 0; --ls)
     if (Lv.mfma_txp[ls]) {
       info->mfma_sources = 1 << ls;
@@ -2152,6 +2159,9 @@ size_t vh_footprint_bytes(int dim, const int* n, int levels, int patch, int nsrc
     const Grid g = make_grid(dim, (int)nn[0], (int)nn[1], (int)nn[2]);
     const size_t Npad = (size_t)g.Np;
     common += ((size_t)E * Npad + (sym ? (size_t)(sym_guard(g) + sym_tail(g)) : 0)) * esz;
+    if (sym && dim == 3)  // the z walk's carry between chunks of planes
+      common += (size_t)sym_carry_elems(g, o.sym_planes == 0 ? sym_walk_planes(g) : o.sym_planes) *
+                esz;
     if (assembled) {  // a temporary slab buffer when the basis is too small to hold one
       const SlabPlan p = slab_plan(dim, g, Np, esz, (size_t)(o.restart + 1) * N0 * 16);
       if (p.own && (size_t)p.cnt_max * p.per_plane > slab_tmp) slab_tmp = (size_t)p.cnt_max * p.per_plane;

@@ -88,7 +88,7 @@ def test_setup_rejects_bad_options():
     for field, value in (("restart", 0), ("restart", 65), ("precision", 7), ("nu1", -1),
                          ("bc", 5), ("smoother", 3), ("sweep_tile", 11), ("sweep_tile", -1),
                          ("split_residual", 3), ("split_residual", -1), ("sym_planes", -2),
-                         ("sym_planes", 65), ("setup_pivot", 2), ("setup_pivot", -1)):
+                         ("sym_planes", 1), ("sym_planes", 65), ("setup_pivot", 2), ("setup_pivot", -1)):
         o = B.make_options(**{field: value})
         with pytest.raises(B.VhError) as e:
             B.vh_setup(2, (33, 33), 1 / 32, 10.0, None, None, 0.1, 3, B.VH_PATCH_FULL, o)

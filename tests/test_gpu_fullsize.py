@@ -44,7 +44,7 @@ def sampled_nodes(n, seed):
     # corners, faces, and planes on both sides of the slab edges of the assembled setup
     pts = [(0, 0, 0), (1, 128, 256), (256, 17, 3), (10, 20, 14), (11, 21, 15), (5, 9, 16),
            (200, 40, 17), (12, 22, 29), (13, 23, 30), (250, 250, 255), (3, 4, 240)]
-    # both sides of the chunk edges of the symmetric sweep's z walk (24 planes), and the
+    # both sides of the chunk edges of the symmetric sweep's z walk (8 or 24 planes), and the
     # x-tile edges of its 32 x 8 columns
     pts += [(31, 7, 23), (32, 8, 24), (255, 200, 47), (256, 201, 48), (96, 15, 239)]
     pts += [tuple(int(rng.integers(1, k - 1)) for k in n) for _ in range(8)]

@@ -37,9 +37,11 @@ def to_gpu(a):
 
 
 # 3D sweep forms (vh_options.sym_planes): the default choice (one plane per workgroup on
-# these small grids), and the z walk of 5 planes (several chunks, a short last one) or 16
-WALKS = [("2d_cubic", 0), ("2d_levdep", 0), ("3d", 0), ("3d", 16), ("3d_dirichlet", 0),
-         ("3d_dirichlet", 5), ("3d_chunks", 0), ("3d_chunks", 5), ("3d_chunks", 16)]
+# these small grids), and the z walk of 2, 3, 5 or 16 planes (several chunks handing their
+# mirrored sums on, a short last one)
+WALKS = [("2d_cubic", 0), ("2d_levdep", 0), ("3d", 0), ("3d", 3), ("3d", 16),
+         ("3d_dirichlet", 0), ("3d_dirichlet", 5), ("3d_chunks", 0), ("3d_chunks", 2),
+         ("3d_chunks", 5), ("3d_chunks", 16)]
 
 
 @pytest.mark.parametrize("key,planes", WALKS)

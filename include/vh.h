@@ -160,7 +160,7 @@ typedef struct vh_options {
     int sym_planes;         /* 3D symmetric-half sweep (VH_SMOOTHER_SYMMETRIC): how many
                                z-planes one workgroup walks, reading the entries of each
                                plane once for its own terms and, from the caches, for the
-                               mirrored terms of the planes above.  0 (default): 8 where
+                               mirrored terms of the planes above.  0 (default): 6 where
                                the level still gets >= 1024 workgroups, else one plane per
                                workgroup; -1: one plane per workgroup; 2..64 forced (a
                                walked level keeps a small carry buffer: two planes per

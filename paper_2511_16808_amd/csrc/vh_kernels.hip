@@ -1129,7 +1129,7 @@ long long sym_guard(const Grid& g) {
 long long sym_tail(const Grid& g) { return g.dim == 3 ? 2 + 2LL * g.nxp : 0; }
 
 // 3D form of the symmetric-half sweep, walked along z.  A block takes a 32 x 8 column of
-// nodes through a chunk of zc >= 2 planes (8 by default).  At plane z each lane reads the
+// nodes through a chunk of zc >= 2 planes (6 by default).  At plane z each lane reads the
 // 63 stored entries of its node once for its own terms, S(i, i + d) r(i + d), and, in the
 // same step, the entries stored at the nodes i - d of plane z for the mirrored terms
 // S(i - d, i) r(i - d) of the targets i in planes z, z + 1, z + 2: those loads touch the
@@ -1140,9 +1140,10 @@ long long sym_tail(const Grid& g) { return g.dim == 3 ? 2 + 2LL * g.nxp : 0; }
 // fastest), and sym_carry_add() adds them once every chunk is done.  The residual planes
 // z .. z + 2 (with a halo of 2, zero outside the grid) sit in a four-slot LDS ring; the
 // slot of plane z + 3 is filled while plane z is summed.  One stencil row (5 own and 5
-// mirrored loads) per iteration keeps 62 VGPRs and 8 waves per SIMD; tiles of 64 x 8,
-// 64 x 16, 32 x 16 and 16 x 16 measured within 15 % of this one at 257^3, and chunks of
-// 12 to 43 planes 1 to 10 % slower than 8.
+// mirrored loads) per iteration keeps 62 VGPRs and 8 waves per SIMD.  At 257^3, tiles of
+// 64 x 8, 64 x 4, 32 x 16 and 16 x 16 measured up to 4 % slower than this one; chunks of 6
+// planes 2.5 % faster than 8, of 3 to 5 planes and 12 to 43 planes slower (4 varied by
+// 8 % from one allocation of the level to the next).
 constexpr int SZ_TX = 32, SZ_TY = 8;
 
 template <bool ZERO, class T>

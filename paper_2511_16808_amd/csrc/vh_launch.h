@@ -105,7 +105,7 @@ long long sym_tail(const Grid& g);
 // walk of SYM_WALK_PLANES planes when it still gives SYM_WALK_MIN_BLOCKS blocks.  The walk
 // needs `carry`, device scratch of sym_carry_elems(g, planes) complex entries at the
 // preconditioner precision (the mirrored sums handed from one chunk of planes to the next)
-constexpr int SYM_WALK_PLANES = 8, SYM_WALK_MIN_BLOCKS = 1024;
+constexpr int SYM_WALK_PLANES = 6, SYM_WALK_MIN_BLOCKS = 1024;
 int sym_walk_planes(const Grid& g);
 long long sym_carry_elems(const Grid& g, int planes);
 hipError_t vanka_sweep_sym(int dim, Grid g, int prec, const void* S, double w, const void* r,

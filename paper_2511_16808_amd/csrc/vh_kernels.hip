@@ -771,7 +771,10 @@ __global__ __launch_bounds__(256, 1) void k_vanka_setup(Grid g, const cpx<double
   cpx<double> ndinv = cmk(0.0, 0.0);  // -1 / d of this lane's row once used (NOPIV)
   cpx<double>* pr = prow[wib][slot < (unsigned)PPW ? slot : 0];
   constexpr int CH = 6;  // pivot-row entries read per batch
-#pragma unroll 3
+  // unrolled three steps at a time, the rotating row costs register moves at the loop edge
+  // (a rotation by three); the no-pivot 3D form is unrolled whole instead
+  constexpr int UNROLL = (NOPIV && GW == 32) ? Np : 3;
+#pragma unroll UNROLL
   for (int s = 0; s < Np; ++s) {
     const cpx<double> as = a[0];
     int best = s;

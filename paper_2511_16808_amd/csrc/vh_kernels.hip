@@ -1940,6 +1940,53 @@ hipError_t resid_restrict(int dim, int rf, int shape, Grid gf, Grid gc, int prec
   return hipErrorInvalidValue;
 }
 
+// Linear prolongation with two fine nodes per thread, x = 2J and 2J + 1: both take the
+// coarse nodes J and J + 1 of their y-z neighbourhood (the even one with weights 1 and 0),
+// so each coarse value is loaded once for the pair and the pair's two inputs and outputs
+// are adjacent.  The products and their order are those of k_prolong_add, so the results
+// are the same bits.
+template <int DIM, class T>
+__global__ __launch_bounds__(256) void k_prolong_add_lin2(Grid gf, Grid gc,
+                                                          const cpx<T>* __restrict__ e,
+                                                          cpx<T>* u, const cpx<T>* u_in) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nt = (long long)gc.nx * gf.ny * gf.nz;
+  if (t >= nt) return;
+  const int J = (int)(t % gc.nx);
+  const long long yz = t / gc.nx;
+  const int y = (int)(yz % gf.ny), z = (int)(yz / gf.ny);
+  const bool odd_y = (y & 1) != 0, odd_z = DIM == 3 && (z & 1) != 0;
+  const int ya = y >> 1, yb = odd_y ? ya + 1 : ya, za = z >> 1, zb = odd_z ? za + 1 : za;
+  const T wya = odd_y ? (T)0.5 : (T)1, wyb = odd_y ? (T)0.5 : (T)0;
+  const T wza = odd_z ? (T)0.5 : (T)1, wzb = odd_z ? (T)0.5 : (T)0;
+  const bool pair = 2 * J + 1 < gf.nx;  // the last even node has no odd partner
+  cpx<T> a0 = cmk<T>(0, 0), a1 = cmk<T>(0, 0);
+#pragma unroll
+  for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      const T wy = sy ? wyb : wya, wz = DIM == 3 ? (sz ? wzb : wza) : (T)1;
+      const int cy = sy ? yb : ya, cz = DIM == 3 ? (sz ? zb : za) : 0;
+      const cpx<T> e0 = e[lin(gc, J, cy, cz)];
+      const cpx<T> e1 = pair ? e[lin(gc, J + 1, cy, cz)] : e0;
+      // even node: weights 1 and 0 in x, both on coarse node J
+      const T w0 = ((T)1 * wy) * wz, w0b = ((T)0 * wy) * wz;
+      a0.re = fma(w0, e0.re, a0.re);
+      a0.im = fma(w0, e0.im, a0.im);
+      a0.re = fma(w0b, e0.re, a0.re);
+      a0.im = fma(w0b, e0.im, a0.im);
+      // odd node: weight 1/2 on J and on J + 1
+      const T w1 = ((T)0.5 * wy) * wz;
+      a1.re = fma(w1, e0.re, a1.re);
+      a1.im = fma(w1, e0.im, a1.im);
+      a1.re = fma(w1, e1.re, a1.re);
+      a1.im = fma(w1, e1.im, a1.im);
+    }
+  const long long i = lin(gf, 2 * J, y, z);
+  u[i] = u_in[i] + a0;
+  if (pair) u[i + 1] = u_in[i + 1] + a1;
+}
+
 hipError_t prolong_add(int dim, int pf, Grid gf, Grid gc, int prec, const void* e, void* u,
                        hipStream_t s, const void* u_in) {
   const unsigned nb = nblocks(gf.N, 256);
@@ -1951,14 +1998,23 @@ hipError_t prolong_add(int dim, int pf, Grid gf, Grid gc, int prec, const void* 
     VH_LAUNCH_CHECK();                                                                         \
     return hipSuccess;                                                                         \
   }
+#define VH_PL(D, T)                                                                            \
+  if (dim == D && pf == FAM_LINEAR) {                                                          \
+    const long long nt = (long long)gc.nx * gf.ny * gf.nz;                                     \
+    k_prolong_add_lin2<D, T><<<nblocks(nt, 256), 256, 0, s>>>(gf, gc, (const cpx<T>*)e,        \
+                                                              (cpx<T>*)u, (const cpx<T>*)u_in); \
+    VH_LAUNCH_CHECK();                                                                         \
+    return hipSuccess;                                                                         \
+  }
   if (prec == PREC_F64) {
-    VH_PA(2, FAM_LINEAR, double) VH_PA(2, FAM_CUBIC, double)
-    VH_PA(3, FAM_LINEAR, double) VH_PA(3, FAM_CUBIC, double)
+    VH_PL(2, double) VH_PA(2, FAM_CUBIC, double)
+    VH_PL(3, double) VH_PA(3, FAM_CUBIC, double)
   } else {
-    VH_PA(2, FAM_LINEAR, float) VH_PA(2, FAM_CUBIC, float)
-    VH_PA(3, FAM_LINEAR, float) VH_PA(3, FAM_CUBIC, float)
+    VH_PL(2, float) VH_PA(2, FAM_CUBIC, float)
+    VH_PL(3, float) VH_PA(3, FAM_CUBIC, float)
   }
 #undef VH_PA
+#undef VH_PL
   return hipErrorInvalidValue;
 }
 
